@@ -1,0 +1,607 @@
+"""Pins of the CPU oracle against closed forms, brute force, library
+routines and dense linear algebra (nothing here re-types the oracle's own
+formulas; each check is fixed by the mathematics or an independent routine).
+"""
+import json
+import os
+from collections import deque
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def poisson1d(n, neumann=False):
+    main = np.full(n, 2.0)
+    if neumann:
+        main[0] = main[-1] = 1.0
+    A = sp.diags([-np.ones(n - 1), main, -np.ones(n - 1)], [-1, 0, 1], format="csr")
+    A.sort_indices()
+    return A
+
+
+def poisson2d(nx, ny):
+    I1, I2 = sp.identity(nx), sp.identity(ny)
+    A = sp.kron(I2, poisson1d(nx)) + sp.kron(poisson1d(ny), I1)
+    A = A.tocsr()
+    A.sort_indices()
+    return A
+
+
+def csr_args(A):
+    return A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64)
+
+
+def block_of(s, f):
+    A = sp.csr_matrix((s.val, s.col, s.rowptr), shape=(s.n, s.n))
+    m = s.field_of_row == f
+    B = A[m][:, m].tocsr()
+    B.sort_indices()
+    return B
+
+
+# ------------------------------------------------------------ strength (SoC)
+def test_strength_brute_force():
+    s = synth.make_system(5, 4, 6, 1, seed=9)
+    B = block_of(s, 0)
+    d = B.diagonal()
+    for theta in (0.0, 0.04, 0.2):
+        st = oracle.strength(*csr_args(B), theta)
+        Bd = B.toarray()
+        k = 0
+        for i in range(B.shape[0]):
+            for q in range(B.indptr[i], B.indptr[i + 1]):
+                j = B.indices[q]
+                if j == i:
+                    exp = False
+                else:
+                    exp = (Bd[i, j] ** 2 >= theta ** 2 * abs(d[i]) * abs(d[j])) or \
+                          (Bd[j, i] ** 2 >= theta ** 2 * abs(d[j]) * abs(d[i]))
+                assert st[q] == exp, (i, j, theta)
+                k += 1
+
+
+def test_strength_theta_zero_and_monotone():
+    s = synth.make_system(6, 5, 6, 1, seed=1)
+    B = block_of(s, 0)
+    rp, ci, v = csr_args(B)
+    row = np.repeat(np.arange(B.shape[0]), np.diff(rp))
+    s0 = oracle.strength(rp, ci, v, 0.0)
+    assert np.array_equal(s0, row != ci)
+    prev = s0
+    for th in (0.01, 0.04, 0.1, 0.3, 0.64):
+        cur = oracle.strength(rp, ci, v, th)
+        assert not np.any(cur & ~prev)  # monotone: strong set shrinks
+        prev = cur
+
+
+def test_strength_interface_faces_phi_s():
+    """theta = 0.04 drops collector-electrode faces of phi_s in 3D, keeps them in 2D.
+
+    Face transmissibility 2*1e4*1e2/(1e4+1e2) = 198.02.  3D interior cells:
+    a_ii = 5*1e4 + 198 = 50198, a_jj ~ 5*1e2 + 198 + k ~ 700, so
+    0.04*sqrt(a_ii a_jj) ~ 237 > 198 (weak).  2D interior cells: a_ii = 30198,
+    a_jj ~ 500, so 0.04*sqrt(a_ii a_jj) ~ 155 < 198 (strong)."""
+    for dims, expect_weak in (((6, 6, 20), True), ((6, 20, 0), False)):
+        s = synth.make_system(*dims, 1, seed=2)
+        B = block_of(s, 0)
+        rp, ci, v = csr_args(B)
+        st = oracle.strength(rp, ci, v, 0.04)
+        lay = s.layer
+        ncell = len(lay)
+        T = 2 * 1e4 * 1e2 / (1e4 + 1e2)
+        found = 0
+        for i in range(B.shape[0]):
+            for q in range(rp[i], rp[i + 1]):
+                j = ci[q]
+                cx, cy = i % dims[0], (i // dims[0]) % dims[1]
+                interior = 0 < cx < dims[0] - 1 and (dims[2] == 0 or 0 < cy < dims[1] - 1)
+                if interior and lay[i] in (0, 4) and lay[j] == (1 if lay[i] == 0 else 3) \
+                        and abs(v[q] + T) < 1e-9:
+                    found += 1
+                    assert st[q] == (not expect_weak)
+        assert found > 0 and ncell == B.shape[0]
+
+
+# ------------------------------------------------------------- aggregation
+def _graph(rp, ci, strong):
+    n = len(rp) - 1
+    adj = [[] for _ in range(n)]
+    for i in range(n):
+        for q in range(rp[i], rp[i + 1]):
+            if strong[q]:
+                adj[i].append(ci[q])
+    return adj
+
+
+def _dist(adj, src, cap=2):
+    d = {src: 0}
+    dq = deque([src])
+    while dq:
+        u = dq.popleft()
+        if d[u] == cap:
+            continue
+        for w in adj[u]:
+            if w not in d:
+                d[w] = d[u] + 1
+                dq.append(w)
+    return d
+
+
+def _mis2_rounds(adj, keys, excluded):
+    """Synchronous-round distance-2 MIS (the parallel form)."""
+    n = len(adj)
+    state = np.where(excluded, 3, 0)  # 0 undecided, 1 root, 2 out, 3 excluded
+    while np.any(state == 0):
+        und = np.where(state == 0, keys, 0)
+        m1 = und.copy()
+        for i in range(n):
+            for j in adj[i]:
+                m1[i] = max(m1[i], und[j])
+        m2 = m1.copy()
+        for i in range(n):
+            for j in adj[i]:
+                m2[i] = max(m2[i], m1[j])
+        new = (state == 0) & (m2 == keys)
+        state[new] = 1
+        r1 = new.copy()
+        for i in range(n):
+            for j in adj[i]:
+                r1[i] |= new[j]
+        r2 = r1.copy()
+        for i in range(n):
+            for j in adj[i]:
+                r2[i] |= r1[j]
+        state[(state == 0) & r2] = 2
+    return state == 1
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_mis2_independent_maximal_and_equals_rounds(seed):
+    rng = np.random.default_rng(seed)
+    n = 120
+    M = sp.random(n, n, density=0.03, random_state=seed, format="csr")
+    M = ((M + M.T) != 0).astype(float) + sp.identity(n) * 4
+    M = M.tocsr()
+    M.sort_indices()
+    rp, ci, v = csr_args(M)
+    v = v * (1 + rng.random(len(v)))
+    strong = oracle.strength(rp, ci, v, 0.0)
+    salt = 1234 + seed
+    agg, root, nagg = oracle.aggregate(rp, ci, v, strong, salt)
+    adj = _graph(rp, ci, strong)
+    excluded = np.array([len(adj[i]) == 0 and all(ci[q] == i for q in range(rp[i], rp[i + 1])) for i in range(n)])
+    roots = np.flatnonzero(root)
+    for r in roots:  # independence at distance 2
+        d = _dist(adj, r)
+        assert not any(root[u] for u in d if u != r)
+    for i in range(n):  # maximality
+        if excluded[i]:
+            assert agg[i] == -1
+            continue
+        d = _dist(adj, i)
+        assert any(root[u] for u in d)
+    keys = np.array([oracle.agg_key(i, salt) for i in range(n)], dtype=np.uint64)
+    assert np.array_equal(_mis2_rounds(adj, keys, excluded), root)
+    # every non-excluded row in exactly one aggregate; ids 0..nagg-1 all used
+    assert set(agg[~excluded]) == set(range(nagg))
+    # roots numbered by ascending row index
+    assert np.array_equal(agg[roots], np.arange(len(roots)))
+    # aggregates are connected and contain exactly one root (or are singletons)
+    for a in range(nagg):
+        mem = np.flatnonzero(agg == a)
+        assert root[mem].sum() == 1 or len(mem) == 1
+
+
+def test_mis2_path_graph():
+    n = 400
+    A = poisson1d(n)
+    rp, ci, v = csr_args(A)
+    strong = oracle.strength(rp, ci, v, 0.0)
+    agg, root, nagg = oracle.aggregate(rp, ci, v, strong, 77)
+    r = np.flatnonzero(root)
+    gaps = np.diff(r)
+    assert gaps.min() >= 3 and gaps.max() <= 5
+    sizes = np.bincount(agg)
+    assert sizes.min() >= 1 and sizes.max() <= 5
+    interior = sizes[1:-1]
+    assert interior.min() >= 3
+    # aggregates are contiguous runs
+    for a in range(nagg):
+        mem = np.flatnonzero(agg == a)
+        assert mem.max() - mem.min() + 1 == len(mem)
+
+
+# -------------------------------------------------- prolongator and filter
+def test_tentative_prolongator_reproduces_constants():
+    """With omega -> 0 the smoothed prolongator is the tentative one; here the
+    tentative operator is rebuilt from the aggregates and P_tent 1_c = 1."""
+    s = synth.make_system(8, 8, 10, 1, seed=4)
+    for f in range(4):
+        B = block_of(s, f)
+        h = oracle.Amg(*csr_args(B), theta=0.04 if f == 0 else 0.0, salt=5,
+                       opts=oracle.options(coarse_max=50))
+        agg = h.agg(0)
+        nagg = h.get(1, "A")[0].shape[0] - 1
+        Pt = sp.csr_matrix((np.ones((agg >= 0).sum()), (np.flatnonzero(agg >= 0), agg[agg >= 0])),
+                           shape=(len(agg), nagg))
+        one = Pt @ np.ones(nagg)
+        assert np.array_equal(one[agg >= 0], np.ones((agg >= 0).sum()))
+        assert np.all(one[agg < 0] == 0)
+
+
+def test_filter_lumping_preserves_row_sums():
+    s = synth.make_system(6, 6, 12, 1, seed=3)
+    B = block_of(s, 0)
+    rp, ci, v = csr_args(B)
+    st = oracle.strength(rp, ci, v, 0.04)
+    frp, fci, fv, dabs = oracle.filtered(rp, ci, v, st)
+    F = sp.csr_matrix((fv, fci, frp), shape=B.shape)
+    assert np.allclose(F @ np.ones(B.shape[0]), B @ np.ones(B.shape[0]), rtol=1e-13, atol=1e-9)
+    assert np.allclose(dabs, abs(F).sum(axis=1).A1, rtol=1e-15)
+    assert F.nnz < B.nnz  # something was dropped at theta = 0.04
+
+
+def test_smoothed_prolongator_closed_form_1d():
+    """1D Poisson, theta = 0, omega = 4/3, interior D_abs = 4: every interior
+    size-3 aggregate's column is the linear hat (1/3, 2/3, 1, 2/3, 1/3)."""
+    with open(os.path.join(GOLDEN, "sa_hat_1d.json")) as fh:
+        gold = json.load(fh)
+    A = poisson1d(300)
+    h = oracle.Amg(*csr_args(A), theta=0.0, salt=31,
+                   opts=oracle.options(coarse_max=10, max_levels=2, omega_override=4.0 / 3.0))
+    prp, pci, pv, nc = h.get(0, "P")
+    P = sp.csr_matrix((pv, pci, prp), shape=(300, nc)).toarray()
+    agg = h.agg(0)
+    checked = 0
+    for a in range(nc):
+        mem = np.flatnonzero(agg == a)
+        if len(mem) != 3 or mem.min() < 3 or mem.max() > 296:
+            continue
+        col = P[mem.min() - 1: mem.max() + 2, a]
+        assert np.allclose(col, gold["column"], rtol=2.3e-16, atol=0)
+        assert np.count_nonzero(P[:, a]) == 5
+        checked += 1
+    assert checked > 10
+
+
+def test_rap_matches_scipy():
+    s = synth.make_system(8, 8, 12, 1, seed=6)
+    for f, th in ((0, 0.04), (2, 0.0), (3, 0.0)):
+        B = block_of(s, f)
+        h = oracle.Amg(*csr_args(B), theta=th, salt=9, opts=oracle.options(coarse_max=20))
+        for l in range(h.levels - 1):
+            arp, aci, av, _ = h.get(l, "A")
+            prp, pci, pv, nc = h.get(l, "P")
+            rrp, rci, rv, _ = h.get(l, "R")
+            crp, cci, cv, _ = h.get(l + 1, "A")
+            A = sp.csr_matrix((av, aci, arp))
+            P = sp.csr_matrix((pv, pci, prp), shape=(A.shape[0], nc))
+            R = sp.csr_matrix((rv, rci, rrp), shape=(nc, A.shape[0]))
+            assert (abs(R - P.T) > 0).nnz == 0
+            ref = (P.T @ A @ P).toarray()
+            Ac = sp.csr_matrix((cv, cci, crp), shape=(nc, nc)).toarray()
+            assert np.allclose(Ac, ref, rtol=1e-13, atol=1e-13 * abs(ref).max())
+            # structural pattern: product of the patterns
+            pat = ((abs(P).T @ abs(A) @ abs(P)) != 0).toarray()
+            got = np.zeros_like(pat)
+            for i in range(nc):
+                got[i, cci[crp[i]:crp[i + 1]]] = True
+            Pb = sp.csr_matrix((np.ones(len(pv)), pci, prp), shape=P.shape)
+            Ab = sp.csr_matrix((np.ones(len(av)), aci, arp), shape=A.shape)
+            assert np.array_equal(got, ((Pb.T @ Ab @ Pb) != 0).toarray())
+            # row-sum identity A_c 1 = P^T (A (P 1))
+            assert np.allclose(Ac @ np.ones(nc), P.T @ (A @ (P @ np.ones(nc))), rtol=1e-12,
+                               atol=1e-12 * abs(ref).max())
+            if f in (0, 2):  # symmetric blocks give symmetric coarse operators
+                assert np.allclose(Ac, Ac.T, rtol=0, atol=1e-12 * abs(Ac).max())
+
+
+def test_spgemm_against_scipy_random():
+    rng = np.random.default_rng(0)
+    A = sp.random(40, 30, density=0.1, random_state=1, format="csr")
+    B = sp.random(30, 25, density=0.1, random_state=2, format="csr")
+    A.sort_indices()
+    B.sort_indices()
+    crp, cci, cv = oracle.spgemm((A.indptr, A.indices, A.data, 30), (B.indptr, B.indices, B.data, 25))
+    C = sp.csr_matrix((cv, cci, crp), shape=(40, 25)).toarray()
+    assert np.allclose(C, (A @ B).toarray(), rtol=1e-14, atol=1e-15)
+    _ = rng
+
+
+def test_lu_against_numpy():
+    s = synth.make_system(5, 5, 0, 1, seed=8)
+    for f in range(4):
+        B = block_of(s, f)
+        b = np.random.default_rng(f).standard_normal(B.shape[0])
+        x = oracle.lu_solve(*csr_args(B), b)
+        xt = oracle.lu_solve(*csr_args(B), b, transpose=True)
+        Bd = B.toarray()
+        k = np.linalg.cond(Bd)
+        assert np.linalg.norm(x - np.linalg.solve(Bd, b)) <= 1e-15 * k * np.linalg.norm(x) * 10
+        assert np.linalg.norm(xt - np.linalg.solve(Bd.T, b)) <= 1e-15 * k * np.linalg.norm(xt) * 10
+
+
+# ----------------------------------------------------------------- Chebyshev
+def test_chebyshev_eigencomponents_closed_form():
+    """1D Poisson: D^-1 A = A/2 has eigenpairs (1 - cos(k pi/(n+1)), sin modes).
+    A degree-2 Chebyshev smoother from a zero guess multiplies each error
+    component by T_2((theta - lam)/delta) / T_2(theta/delta)."""
+    n = 60
+    A = poisson1d(n)
+    opts = oracle.options(coarse_max=5, max_levels=2)
+    h = oracle.Amg(*csr_args(A), theta=0.0, salt=3, opts=opts)
+    est = h.scalars(0)["lam_cheb"]
+    lmax = 1.1 * est
+    lmin = lmax / 30.0
+    th, de = (lmax + lmin) / 2, (lmax - lmin) / 2
+
+    def T2(x):
+        return 2 * x * x - 1
+
+    for k in (1, 5, 20, 45, 60):
+        v = np.sin(k * np.pi * np.arange(1, n + 1) / (n + 1))
+        lam = 1 - np.cos(k * np.pi / (n + 1))
+        x = h.chebyshev(0, A @ v)
+        factor = T2((th - lam) / de) / T2(th / de)
+        assert np.allclose(v - x, factor * v, atol=1e-12)
+    # the estimate lies below the largest eigenvalue of D^-1 A and the boosted
+    # interval end covers it
+    lam_top = 1 - np.cos(n * np.pi / (n + 1))
+    assert est <= lam_top * (1 + 1e-12) and lmax >= lam_top
+
+
+def test_power_estimate_converges_to_spectral_radius():
+    rng = np.random.default_rng(5)
+    Q, _ = np.linalg.qr(rng.standard_normal((40, 40)))
+    lam = np.concatenate([np.linspace(0.1, 1.0, 39), [1.6]])
+    A = sp.csr_matrix(Q @ np.diag(lam) @ Q.T)
+    A.sort_indices()
+    rp, ci, v = csr_args(A)
+    d = A.diagonal()
+    ev = np.linalg.eigvals(np.diag(1 / d) @ A.toarray()).real.max()
+    est = oracle.power_estimate(rp, ci, v, d, 200, 17)
+    assert abs(est - ev) < 1e-3 * ev
+    est10 = oracle.power_estimate(rp, ci, v, d, 10, 17)
+    assert 0.8 * ev < est10 <= ev * (1 + 1e-12)
+
+
+# ------------------------------------------------------------------ V-cycle
+def _vcycle_matrix(h, n, transpose=False):
+    return np.column_stack([h.vcycle(np.eye(n)[:, i], transpose=transpose) for i in range(n)])
+
+
+def test_vcycle_symmetric_on_spd_block():
+    s = synth.make_system(6, 6, 8, 1, seed=12)
+    for f in (0, 2):
+        B = block_of(s, f)
+        h = oracle.Amg(*csr_args(B), theta=0.04 if f == 0 else 0.0, salt=4, opts=oracle.options(coarse_max=30))
+        assert h.levels >= 2
+        M = _vcycle_matrix(h, B.shape[0])
+        assert np.allclose(M, M.T, rtol=0, atol=1e-13 * abs(M).max())
+
+
+def test_vcycle_adjoint_is_transpose():
+    s = synth.make_system(6, 6, 8, 1, seed=12)
+    B = block_of(s, 3)  # nonsymmetric (upwind convection)
+    h = oracle.Amg(*csr_args(B), theta=0.0, salt=4, opts=oracle.options(coarse_max=30))
+    assert h.levels >= 2
+    M = _vcycle_matrix(h, B.shape[0])
+    MT = _vcycle_matrix(h, B.shape[0], transpose=True)
+    assert not np.allclose(M, M.T, atol=1e-10 * abs(M).max())
+    assert np.allclose(MT, M.T, rtol=0, atol=1e-13 * abs(M).max())
+
+
+def _cheb_error_map_deg(A, est, deg, ratio=30.0):
+    n = A.shape[0]
+    D1A = np.diag(1 / A.diagonal()) @ A
+    lmax = 1.1 * est
+    lmin = lmax / ratio
+    th, de = (lmax + lmin) / 2, (lmax - lmin) / 2
+    X = (th * np.eye(n) - D1A) / de
+    s = th / de
+    T0, T1, t0, t1 = np.eye(n), X.copy(), 1.0, s
+    for _ in range(1, deg):
+        T0, T1 = T1, 2 * X @ T1 - T0
+        t0, t1 = t1, 2 * s * t1 - t0
+    return T1 / t1
+
+
+def _measured_factor(h, A, n, iters=150):
+    rng = np.random.default_rng(0)
+    e = rng.standard_normal(n)
+    r = 0.0
+    for _ in range(iters):
+        en = e - h.vcycle(A @ e)
+        r = np.sqrt(en @ (A @ en)) / np.sqrt(e @ (A @ e))
+        e = en / np.sqrt(en @ (A @ en))
+    return r
+
+
+_RHO = {}
+
+
+@pytest.mark.parametrize("n", [999, 9999])
+def test_two_grid_factor_1d_poisson(n):
+    """Two-grid error operator E = S (I - P A_c^-1 P^T A) S with S the
+    Chebyshev error polynomial in D^-1 A, built densely here.  The oracle's
+    measured asymptotic factor (A-norm power iteration on the cycle error)
+    equals rho(E); it lies in [0.3, 0.8] (degree 2 on [lmax/30, lmax] damps
+    the smoothing range only by 1/T_2(sigma) ~ 0.78 per application) and is
+    h-independent.  A higher polynomial degree gives a smaller factor."""
+    A = poisson1d(n)
+    h = oracle.Amg(*csr_args(A), theta=0.0, salt=21, opts=oracle.options(coarse_max=10, max_levels=2))
+    assert h.levels == 2
+    rho_meas = _measured_factor(h, A, n)
+    assert 0.3 <= rho_meas <= 0.8
+    _RHO[n] = rho_meas
+    if n <= 1000:
+        prp, pci, pv, nc = h.get(0, "P")
+        P = sp.csr_matrix((pv, pci, prp), shape=(n, nc)).toarray()
+        Ad = A.toarray()
+        Ac = P.T @ Ad @ P
+        for deg in (2, 4):
+            if deg != 2:
+                h = oracle.Amg(*csr_args(A), theta=0.0, salt=21,
+                               opts=oracle.options(coarse_max=10, max_levels=2, cheb_degree=deg))
+                rho_meas = _measured_factor(h, A, n)
+                assert rho_meas < _RHO[n] - 0.1
+            S = _cheb_error_map_deg(Ad, h.scalars(0)["lam_cheb"], deg)
+            E = S @ (np.eye(n) - P @ np.linalg.solve(Ac, P.T @ Ad)) @ S
+            rho = np.abs(np.linalg.eigvals(E)).max()
+            assert abs(rho - rho_meas) < 1e-3
+    elif 999 in _RHO:
+        assert abs(rho_meas - _RHO[999]) <= 0.05
+
+
+# ------------------------------------------------------ block Gauss-Seidel
+def _dense(s):
+    return sp.csr_matrix((s.val, s.col, s.rowptr), shape=(s.n, s.n)).toarray()
+
+
+def test_bgs_exact_leaves_equals_block_triangular_solve():
+    s = synth.make_system(4, 4, 6, 1, seed=13)
+    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, exact_leaves=1)
+    A = _dense(s)
+    f = s.field_of_row
+    # block lower triangular part of A in field order
+    L = A * (f[:, None] >= f[None, :])
+    r = np.random.default_rng(0).standard_normal(s.n)
+    z = o.apply(r)
+    zt = o.apply(r, transpose=True)  # M^-T with M = L
+    assert np.linalg.norm(z - np.linalg.solve(L, r)) <= 1e-12 * np.linalg.norm(z)
+    assert np.linalg.norm(zt - np.linalg.solve(L.T, r)) <= 1e-12 * np.linalg.norm(zt)
+
+
+def test_tree_equals_flat_sweep():
+    s = synth.make_system(5, 4, 6, 3, seed=14)
+    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, coarse_max=40)
+    r = np.random.default_rng(1).standard_normal(s.n)
+    for tr in (False, True):
+        a, b = o.apply(r, transpose=tr), o.apply(r, transpose=tr, flat=True)
+        assert np.linalg.norm(a - b) <= 1e-15 * np.linalg.norm(a)
+
+
+def test_preconditioner_duality():
+    s = synth.make_system(5, 4, 6, 3, seed=15)
+    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, coarse_max=40)
+    rng = np.random.default_rng(2)
+    for _ in range(3):
+        u, v = rng.standard_normal(s.n), rng.standard_normal(s.n)
+        lhs = u @ o.apply(v)
+        rhs = o.apply(u, transpose=True) @ v
+        assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(u) * np.linalg.norm(o.apply(v)) * 10
+
+
+# -------------------------------------------------------------------- GMRES
+def test_gmres_block_triangular_exact_in_one_step():
+    """A block lower-triangular system with exact leaves: M^-1 = A^-1, so
+    GMRES stops after one Arnoldi step."""
+    s = synth.make_system(4, 4, 6, 1, seed=16)
+    f = s.field_of_row
+    A = sp.csr_matrix((s.val, s.col, s.rowptr), shape=(s.n, s.n)).tocoo()
+    keep = f[A.row] >= f[A.col]
+    L = sp.csr_matrix((A.data[keep], (A.row[keep], A.col[keep])), shape=A.shape)
+    L.sort_indices()
+    o = oracle.Oracle(L.indptr, L.indices, L.data, s.nf, f, s.tree, exact_leaves=1, rtol=1e-12)
+    b = L @ s.x_star
+    r = o.solve(b)
+    assert r["status"] == 0 and r["iters"] == 1
+    assert np.linalg.norm(r["x"] - s.x_star) <= 1e-9 * np.linalg.norm(s.x_star)
+
+
+@pytest.mark.parametrize("coarse_max", [2000, 40])
+def test_gmres_against_dense_solve(coarse_max):
+    s = synth.make_system(6, 5, 8, 1, seed=17)
+    A = _dense(s)
+    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, coarse_max=coarse_max, rtol=1e-12)
+    for tr in (False, True):
+        b = s.b if not tr else s.x_t
+        r = o.solve(b, transpose=tr)
+        M = A.T if tr else A
+        x_ref = np.linalg.solve(M, b)
+        assert r["status"] == 0
+        res = np.linalg.norm(b - M @ r["x"]) / np.linalg.norm(b)
+        assert res <= 1e-12
+        k = np.linalg.cond(M)
+        assert np.linalg.norm(r["x"] - x_ref) <= 10 * k * 1e-12 * np.linalg.norm(x_ref)
+        h = r["hist"]
+        assert h[0] == pytest.approx(1.0)
+        assert np.all(np.diff(h[:-1]) <= 1e-15)  # estimates non-increasing in a cycle
+        assert h[-1] <= 1e-12
+
+
+def test_gmres_restart_and_cap():
+    s = synth.make_system(6, 5, 8, 1, seed=18)
+    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, coarse_max=40, restart=3,
+                      rtol=1e-10)
+    r = o.solve(s.b)
+    assert r["status"] == 0
+    A = _dense(s)
+    assert np.linalg.norm(s.b - A @ r["x"]) / np.linalg.norm(s.b) <= 1e-10
+    o2 = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, coarse_max=40, max_iters=3)
+    r2 = o2.solve(s.b)
+    assert r2["status"] == 1 and r2["iters"] == 3
+    z = o.solve(np.zeros(s.n))
+    assert z["iters"] == 0 and not np.any(z["x"])
+
+
+def test_mixed_precision_vcycle_close_to_double():
+    s = synth.make_system(8, 8, 10, 1, seed=19)
+    B = block_of(s, 2)
+    h = oracle.Amg(*csr_args(B), theta=0.0, salt=4, opts=oracle.options(coarse_max=30))
+    b = np.random.default_rng(3).standard_normal(B.shape[0])
+    x64 = h.vcycle(b)
+    x32 = h.vcycle(b, precision=1)
+    assert np.linalg.norm(x32 - x64) <= 1e-5 * np.linalg.norm(x64)
+    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, coarse_max=30, precision=1)
+    r = o.solve(s.b)
+    A = _dense(s)
+    assert r["status"] == 0
+    assert np.linalg.norm(s.b - A @ r["x"]) / np.linalg.norm(s.b) <= 1e-8
+
+
+# ------------------------------------------------------- adjoint, gradient
+def test_adjoint_and_gradient_dense():
+    s = synth.make_system(4, 3, 6, 3, seed=20)
+    A = _dense(s)
+    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, coarse_max=30, rtol=1e-13)
+    x = o.solve(s.b)["x"]
+    g = x - s.x_t
+    lam = o.solve(g, transpose=True)["x"]
+    lam_ref = np.linalg.solve(A.T, g)
+    k = np.linalg.cond(A)
+    assert np.linalg.norm(lam - lam_ref) <= 10 * k * 1e-13 * np.linalg.norm(lam_ref)
+    assert abs(lam @ s.b - g @ x) <= 1e-9 * abs(g @ x) + 1e-12
+    gv = o.grad_values(lam, x)
+    row = np.repeat(np.arange(s.n), np.diff(s.rowptr))
+    assert np.array_equal(gv, -lam[row] * x[s.col])
+    # j0 gradient: closed form per electrode cell
+    m = s.dcell >= 0
+    gj = np.bincount(s.dcell[m], weights=gv[m] * s.dcoef[m], minlength=len(s.j0))
+    nf = s.nf
+    for c in np.flatnonzero((s.layer == 1) | (s.layer == 3))[:10]:
+        xs, xe = x[nf * c], x[nf * c + 1]
+        cf = (xs - xe) * (-(lam[nf * c] - lam[nf * c + 1]) + 0.5 * sum(lam[nf * c + 3 + q] for q in range(3)))
+        assert gj[c] == pytest.approx(cf, rel=1e-12, abs=1e-15)
+    # finite differences of L(j0) = 0.5 ||x(j0) - x_t||^2 with b frozen (dense solves)
+    def loss(j0):
+        s2 = synth.make_system(4, 3, 6, 3, seed=20, j0=j0)
+        xx = np.linalg.solve(_dense(s2), s.b)
+        return 0.5 * np.sum((xx - s.x_t) ** 2)
+    xd = np.linalg.solve(A, s.b)
+    gjd = np.bincount(s.dcell[m], weights=(-np.linalg.solve(A.T, xd - s.x_t)[row] * xd[s.col])[m]
+                      * s.dcoef[m], minlength=len(s.j0))
+    for c in synth.fd_cells(s.seed, s.layer, 4):
+        hstep = 1e-4 * s.j0[c]
+        jp, jm = s.j0.copy(), s.j0.copy()
+        jp[c] += hstep
+        jm[c] -= hstep
+        fd = (loss(jp) - loss(jm)) / (2 * hstep)
+        assert fd == pytest.approx(gjd[c], rel=1e-5, abs=1e-10)
+        assert gj[c] == pytest.approx(gjd[c], rel=1e-6, abs=1e-12)
