@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Benchmark: solve to 1e-8 true relative residual, FP64 vs mixed precision,
+on the 4,194,304-DOF layered-battery system (128x128x64 cells, 4 fields).
+
+One step = the whole hot path on one synthetic system already resident in
+HBM: device setup of the preconditioner from the CSR values (block split,
+strength, MIS-2 aggregation, prolongator smoothing, Galerkin products,
+coarsest factor), the mixed-precision forward solve, the FP64 forward solve,
+the mixed-precision adjoint solve and the value gradient.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "solve s to 1e-8 rel resid (fp64 vs mixed), V-cycle HBM GB/s, at 4.2M DOF"
+HBM_PEAK_GBS = 8000.0
+VCYCLE_KINDS = ("cheb_pre", "cheb_post_a", "cheb_post_b", "cheb_other", "resid", "restrict", "prolong", "coarse",
+                "couple")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2, help="layered-battery configuration (default: 4.2M DOF)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the solver is single-device; see the sharding notes in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2602_13079_amd as H
+    import synth
+
+    dev = torch.device("cuda:0")
+    t = time.time()
+    s = synth.make_system(cfg=args.config)
+    log(f"system: n={s.n} nnz={s.nnz} fields={s.nf} ({time.time() - t:.1f}s to generate)")
+    rp, ci, val, fl = (torch.from_numpy(a).to(dev) for a in (s.rowptr, s.col, s.val, s.field_of_row))
+    b = torch.from_numpy(s.b).to(dev)
+    xt = torch.from_numpy(s.x_t).to(dev)
+    solver = H.Solver(rp, ci, val, fl, s.nf, s.tree, precision=1)
+    st0 = solver.stats()
+    log("levels", st0["levels"], "rows", st0["rows"])
+
+    def step():
+        r = {}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solver.set_values(val)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        solver.set_precision(1)
+        x, stm, itm, hm = solver.solve(b)
+        t2 = time.perf_counter()
+        solver.set_precision(0)
+        x64, st64, it64, h64 = solver.solve(b)
+        t3 = time.perf_counter()
+        solver.set_precision(1)
+        lam, sta, ita, _ = solver.solve(x - xt, transpose=True)
+        t4 = time.perf_counter()
+        g = solver.grad_values(lam, x)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        assert stm == 0 and st64 == 0 and sta == 0, (stm, st64, sta)
+        r.update(setup_s=t1 - t0, mixed_s=t2 - t1, fp64_s=t3 - t2, adjoint_s=t4 - t3, grad_s=t5 - t4,
+                 it_mixed=itm, it_fp64=it64, it_adjoint=ita, res_mixed=hm[-1], res_fp64=h64[-1],
+                 err_mixed_vs_fp64=float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)),
+                 grad_finite=bool(torch.isfinite(g).all()))
+        return r
+
+    # warmup; the first warmup step is profiled for every kernel class
+    solver.profile(True)
+    prof_steps = []
+    for w in range(max(1, args.warmup)):
+        r = step()
+        if w == 0:
+            kt = solver.kernel_times()
+            solver.profile(False)
+        log(f"warmup {w}: " + ", ".join(f"{k}={v:.4g}" if isinstance(v, float) else f"{k}={v}" for k, v in r.items()))
+        prof_steps.append(r)
+    tot_ms = {k: v["ms"] for k, v in kt.items()}
+    dominant = max(tot_ms, key=tot_ms.get)
+    vc_ms = sum(kt[k]["ms"] for k in VCYCLE_KINDS)
+    vc_bytes = sum(kt[k]["bytes"] for k in VCYCLE_KINDS)
+    log("kernel classes (profiled warmup step):")
+    for k, v in sorted(kt.items(), key=lambda kv: -kv[1]["ms"]):
+        if v["launches"]:
+            log(f"  {k:12s} {v['ms']:9.3f} ms {v['launches']:7d} launches "
+                f"{v['bytes'] / max(v['ms'], 1e-9) / 1e6:8.1f} GB/s")
+
+    # timed region: only the dominant kernel class is bracketed by events
+    solver.profile(True, kinds=[dominant])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dk = solver.kernel_times()[dominant]
+    solver.profile(False)
+    for i, r in enumerate(rs):
+        log(f"step {i}: " + ", ".join(f"{k}={v:.4g}" if isinstance(v, float) else f"{k}={v}" for k, v in r.items()))
+
+    def mean(k):
+        return float(np.mean([r[k] for r in rs]))
+
+    # V-cycle bandwidth: preconditioner applies in mixed precision
+    solver.set_precision(1)
+    v0 = torch.randn(s.n, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        solver.apply(v0)
+    torch.cuda.synchronize()
+    napply = 20
+    ta = time.perf_counter()
+    for _ in range(napply):
+        solver.apply(v0)
+    torch.cuda.synchronize()
+    apply_s = (time.perf_counter() - ta) / napply
+    st = solver.stats()
+    vbytes = st["vcycle_bytes"][1]
+
+    achieved = dk["bytes"] / (dk["ms"] * 1e-3) / 1e9 if dk["ms"] > 0 else 0.0
+    out = {
+        "metric": METRIC,
+        "value": round(mean("mixed_s"), 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 GMRES + f32 V-cycle (mixed); f64 reference solve",
+        "data": "synthetic",
+        "config": {
+            "workload": f"layered-battery FV system {s.dims[0]}x{s.dims[1]}x{s.dims[2]} cells, {s.nf} fields, "
+                        f"{s.n} DOF, {s.nnz} nnz; GMRES({solver.opts.restart}) to 1e-8 true relative residual, "
+                        f"block lower Gauss-Seidel with one SA-AMG V-cycle per field",
+            "n_dof": s.n, "nnz": s.nnz, "fields": s.nf, "seed": s.seed,
+        },
+        "mixed_solve_s": round(mean("mixed_s"), 6),
+        "fp64_solve_s": round(mean("fp64_s"), 6),
+        "mixed_speedup_vs_fp64": round(mean("fp64_s") / mean("mixed_s"), 3),
+        "iters_mixed": int(rs[-1]["it_mixed"]),
+        "iters_fp64": int(rs[-1]["it_fp64"]),
+        "ms_per_iter_mixed": round(mean("mixed_s") / rs[-1]["it_mixed"] * 1e3, 4),
+        "ms_per_iter_fp64": round(mean("fp64_s") / rs[-1]["it_fp64"] * 1e3, 4),
+        "true_res_mixed": float(rs[-1]["res_mixed"]),
+        "true_res_fp64": float(rs[-1]["res_fp64"]),
+        "err_mixed_vs_fp64": float(rs[-1]["err_mixed_vs_fp64"]),
+        "setup_s": round(mean("setup_s"), 4),
+        "adjoint_mixed_s": round(mean("adjoint_s"), 6),
+        "iters_adjoint": int(rs[-1]["it_adjoint"]),
+        "grad_s": round(mean("grad_s"), 6),
+        "vcycle_gbs_kernels": round(vc_bytes / (vc_ms * 1e-3) / 1e9, 1) if vc_ms > 0 else None,
+        "vcycle_gbs_apply": round(vbytes / apply_s / 1e9, 1),
+        "vcycle_frac_apply": round(vbytes / apply_s / 1e9 / HBM_PEAK_GBS, 4),
+        "apply_ms_mixed": round(apply_s * 1e3, 4),
+        "levels": st["levels"],
+        "roofline": {
+            "kernel": dominant,
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "launches": dk["launches"],
+            "avg_launch_us": round(dk["ms"] / max(dk["launches"], 1) * 1e3, 3),
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(s)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(s):
+    """The CPU oracle (single-threaded, plain loops) on the same system: one
+    mixed-precision solve to 1e-8; its setup is timed separately."""
+    import oracle
+    t = time.perf_counter()
+    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, precision=1)
+    setup_s = time.perf_counter() - t
+    t = time.perf_counter()
+    r = o.solve(s.b)
+    solve_s = time.perf_counter() - t
+    log(f"cpu oracle: setup {setup_s:.2f}s, mixed solve {solve_s:.2f}s, {r['iters']} iterations")
+    return {"value": round(solve_s, 3), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"the full {s.n}-DOF system: one mixed-precision solve to 1e-8 "
+                      f"({r['iters']} iterations); oracle setup {setup_s:.2f}s not included",
+            "setup_s": round(setup_s, 3), "iters": r["iters"], "os_cpu_count": os.cpu_count()}
+
+
+if __name__ == "__main__":
+    main()

@@ -276,16 +276,28 @@ void filter(const CsrD& a, const std::vector<char>& strong, CsrD& af, std::vecto
   }
 }
 
-// sum over a long vector: 256-element chunks in order, then the chunk sums in order
+// Sum of a long vector of products with a fixed association: each run of
+// 256 consecutive terms is summed in order; while more than one partial sum
+// remains, runs of 256 consecutive partial sums are summed in order again.
 double chunked_dot(const std::vector<double>& x, const std::vector<double>& y) {
-  double total = 0.0;
   const size_t n = x.size();
+  std::vector<double> part;
   for (size_t c = 0; c < n; c += 256) {
     double s = 0.0;
     for (size_t i = c; i < std::min(n, c + 256); ++i) s += x[i] * y[i];
-    total += s;
+    part.push_back(s);
   }
-  return total;
+  if (part.empty()) return 0.0;
+  while (part.size() > 1) {
+    std::vector<double> next;
+    for (size_t c = 0; c < part.size(); c += 256) {
+      double s = 0.0;
+      for (size_t i = c; i < std::min(part.size(), c + 256); ++i) s += part[i];
+      next.push_back(s);
+    }
+    part.swap(next);
+  }
+  return part[0];
 }
 
 // Eigenvalue estimate of D^-1 B (reading: the usual power method with a

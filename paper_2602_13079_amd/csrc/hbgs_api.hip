@@ -1,0 +1,1048 @@
+// Host orchestration and C ABI of libhbgs: device setup pipeline, the
+// block Gauss-Seidel sweep with per-field SA-AMG V-cycles, and flexible
+// GMRES(m) with classical Gram-Schmidt applied twice.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hbgs_internal.h"
+
+namespace hbgs {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+Pool::~Pool() {
+  for (auto& b : blocks_) (void)hipFree(b.first);
+}
+void* Pool::get(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    set_error(std::string("device allocation of ") + std::to_string(bytes) + " bytes failed: " +
+              hipGetErrorString(e));
+    throw Error{HBGS_ENOMEM};
+  }
+  blocks_.push_back({p, bytes});
+  total_ += bytes;
+  return p;
+}
+void Pool::release(void* p) {
+  for (size_t i = 0; i < blocks_.size(); ++i)
+    if (blocks_[i].first == p) {
+      (void)hipFree(p);
+      total_ -= blocks_[i].second;
+      blocks_.erase(blocks_.begin() + i);
+      return;
+    }
+}
+
+static uint64_t splitmix64_host(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// ------------------------------------------------------------- profiler
+struct Profiler {
+  bool on = false;
+  uint32_t mask = 0;  // kernel classes bracketed while on
+  struct Rec {
+    hipEvent_t a, b;
+    int kind;
+    double bytes;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> free_events;
+  double total_ms[solve::K_COUNT] = {};
+  int64_t launches[solve::K_COUNT] = {};
+  double bytes[solve::K_COUNT] = {};
+  hipEvent_t ev() {
+    if (!free_events.empty()) {
+      hipEvent_t e = free_events.back();
+      free_events.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HBGS_HIP(hipEventCreate(&e));
+    return e;
+  }
+  void flush() {
+    for (auto& r : pending) {
+      HBGS_HIP(hipEventSynchronize(r.b));
+      float ms = 0.f;
+      HBGS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      total_ms[r.kind] += ms;
+      launches[r.kind] += 1;
+      bytes[r.kind] += r.bytes;
+      free_events.push_back(r.a);
+      free_events.push_back(r.b);
+    }
+    pending.clear();
+  }
+  ~Profiler() {
+    for (auto& r : pending) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : free_events) (void)hipEventDestroy(e);
+  }
+};
+
+// brackets one kernel launch when profiling is on
+struct Prof {
+  Profiler* p;
+  hipStream_t s;
+  int kind;
+  double bytes;
+  hipEvent_t a = nullptr;
+  Prof(Profiler& pr, hipStream_t st, int k, double b) : p(&pr), s(st), kind(k), bytes(b) {
+    if (p->on && (p->mask >> k & 1u)) {
+      a = p->ev();
+      HBGS_HIP(hipEventRecord(a, s));
+    }
+  }
+  ~Prof() {
+    if (p->on && a) {
+      hipEvent_t b = p->ev();
+      (void)hipEventRecord(b, s);
+      p->pending.push_back({a, b, kind, bytes});
+      if (p->pending.size() > 4096) p->flush();
+    }
+  }
+};
+
+// ------------------------------------------------------------- structures
+struct Level {
+  DCsr A, AT, P, R;
+  int* agg = nullptr;
+  double* dinv = nullptr;
+  float* dinvf = nullptr;
+  double lam_cheb = 0, lam_p = 0, omega = 0;
+  solve::ChebCoef cc{};
+  // work vectors: rhs b, solution x, residual r, directions d / dn
+  double *bd = nullptr, *xd = nullptr, *rd = nullptr, *dd = nullptr, *dnd = nullptr;
+  float *bf = nullptr, *xf = nullptr, *rf = nullptr, *df = nullptr, *dnf = nullptr;
+};
+
+struct Field {
+  int id = 0, lo = 0, hi = 0;
+  std::vector<Level> lv;  // lv.back() is the coarsest level
+  double* inv = nullptr;  // dense inverse of the coarsest operator
+  DCsr lower;             // rows of this field, columns of earlier leaves (global)
+  DCsr upperT;            // rows of A^T in this field, columns of later leaves (global)
+  double* td = nullptr;   // fine-level right-hand side
+  float* tf = nullptr;
+  int n() const { return hi - lo; }
+};
+
+}  // namespace hbgs
+
+struct hbgs_ctx {
+  hbgs_options o{};
+  int precision = 0;
+  int n = 0, nf = 0;
+  int64_t nnz = 0;
+  hbgs::Pool pool;
+  hbgs::Pool hier;  // value-dependent hierarchy (rebuilt by set_values)
+  int *rp0 = nullptr, *ci0 = nullptr;  // caller's pattern
+  int *perm = nullptr, *iperm = nullptr, *src = nullptr;
+  hbgs::DCsr Ap, ApT;
+  std::vector<int> leaf_order, f_lo, f_hi;
+  std::vector<hbgs::Field> F;
+  // GMRES workspace (permuted ordering)
+  int m = 0;
+  size_t ld = 0;
+  double *V = nullptr, *Zd = nullptr;
+  float* Zf = nullptr;
+  double *bp = nullptr, *xp = nullptr, *r = nullptr, *part = nullptr, *h1 = nullptr, *h2 = nullptr,
+         *hn2 = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *scal = nullptr,
+         *tmp = nullptr;
+  double* host_scal = nullptr;  // pinned
+  hbgs::Profiler prof;
+  hbgs_stats_t stats{};
+  ~hbgs_ctx() {
+    if (host_scal) (void)hipHostFree(host_scal);
+  }
+};
+
+namespace hbgs {
+
+using solve::VcOps;
+
+static void validate_options(const hbgs_options& o) {
+  if (o.precision != 0 && o.precision != 1) HBGS_FAIL(HBGS_EINVAL, "precision must be 0 or 1");
+  if (o.restart < 1 || o.restart > 64) HBGS_FAIL(HBGS_EINVAL, "restart must be in [1, 64]");
+  if (o.max_iters < 0) HBGS_FAIL(HBGS_EINVAL, "max_iters must be >= 0");
+  if (!(o.rtol >= 0.0)) HBGS_FAIL(HBGS_EINVAL, "rtol must be >= 0");
+  if (o.cheb_degree < 1 || o.cheb_degree > 8) HBGS_FAIL(HBGS_EINVAL, "cheb_degree must be in [1, 8]");
+  if (!(o.cheb_ratio > 1.0) || !(o.cheb_boost > 0.0)) HBGS_FAIL(HBGS_EINVAL, "bad Chebyshev interval options");
+  if (o.eig_iters < 0 || !(o.sa_damping > 0.0)) HBGS_FAIL(HBGS_EINVAL, "bad eigenvalue / damping options");
+  if (o.coarse_max < 1 || o.coarse_max > 8000) HBGS_FAIL(HBGS_EINVAL, "coarse_max must be in [1, 8000]");
+  if (o.max_levels < 1 || o.max_levels > HBGS_MAX_LEVELS) HBGS_FAIL(HBGS_EINVAL, "max_levels out of range");
+}
+
+static void parse_tree(hbgs_ctx* c, const int32_t* tree, int len) {
+  std::vector<char> seen(c->nf, 0);
+  int depth = 0, closed_root = 0;
+  c->leaf_order.clear();
+  for (int t = 0; t < len; ++t) {
+    int code = tree[t];
+    if (closed_root) HBGS_FAIL(HBGS_EINVAL, "group tree: entries after the outermost group");
+    if (code == -1) {
+      ++depth;
+    } else if (code == -2) {
+      if (depth == 0) HBGS_FAIL(HBGS_EINVAL, "group tree: unbalanced close");
+      if (--depth == 0) closed_root = 1;
+    } else if (code >= 0 && code < c->nf) {
+      if (depth == 0 || seen[code]) HBGS_FAIL(HBGS_EINVAL, "group tree: field outside a group or repeated");
+      seen[code] = 1;
+      c->leaf_order.push_back(code);
+    } else {
+      HBGS_FAIL(HBGS_EINVAL, "group tree: invalid code");
+    }
+  }
+  if (depth != 0 || !closed_root) HBGS_FAIL(HBGS_EINVAL, "group tree: unbalanced");
+  for (int f = 0; f < c->nf; ++f)
+    if (!seen[f]) HBGS_FAIL(HBGS_EINVAL, "group tree: a field is missing");
+}
+
+// extract rows [r0,r1) x columns [c0,c1) (shifted by -coff) of a into a new CSR
+static DCsr extract(Pool& pool, const DCsr& a, int r0, int r1, int c0, int c1, int coff, int ncols,
+                    hipStream_t s) {
+  DCsr b;
+  b.n = r1 - r0;
+  b.m = ncols;
+  Tmp<int> cnt(b.n);
+  b.rp = pool.make<int>(b.n + 1);
+  setup::block_count(a, r0, r1, c0, c1, cnt.p, s);
+  b.nnz = setup::counts_to_rowptr(cnt.p, b.rp, b.n, s);
+  b.ci = pool.make<int>(b.nnz);
+  b.v = pool.make<double>(b.nnz);
+  setup::block_fill(a, r0, r1, c0, c1, coff, b.rp, b.ci, b.v, s);
+  return b;
+}
+
+static DCsr transpose_new(Pool& pool, const DCsr& a, hipStream_t s) {
+  DCsr t;
+  t.rp = pool.make<int>(a.m + 1);
+  t.ci = pool.make<int>(a.nnz);
+  t.v = pool.make<double>(a.nnz);
+  setup::transpose(a, t, s);
+  return t;
+}
+
+static void add_f32(Pool& pool, DCsr& a, hipStream_t s) {
+  a.vf = pool.make<float>(a.nnz);
+  setup::cast_f32(a.nnz, a.v, a.vf, s);
+}
+
+static solve::ChebCoef cheb_coef(const hbgs_options& o, double lam) {
+  solve::ChebCoef c{};
+  c.degree = o.cheb_degree;
+  double lmax = o.cheb_boost * lam, lmin = lmax / o.cheb_ratio;
+  double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  double sigma = theta / delta, rho = 1.0 / sigma;
+  c.c0 = 1.0 / theta;
+  for (int k = 1; k < o.cheb_degree; ++k) {
+    double rn = 1.0 / (2.0 * sigma - rho);
+    c.c1[k] = rn * rho;
+    c.c2[k] = 2.0 * rn / delta;
+    rho = rn;
+  }
+  return c;
+}
+
+static bool structurally_symmetric(const DCsr& a, const DCsr& at, hipStream_t s) {
+  if (a.nnz != at.nnz) return false;
+  std::vector<int> r1(a.n + 1), r2(a.n + 1), c1(a.nnz), c2(a.nnz);
+  HBGS_HIP(hipMemcpyAsync(r1.data(), a.rp, sizeof(int) * (a.n + 1), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipMemcpyAsync(r2.data(), at.rp, sizeof(int) * (a.n + 1), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipMemcpyAsync(c1.data(), a.ci, sizeof(int) * a.nnz, hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipMemcpyAsync(c2.data(), at.ci, sizeof(int) * a.nnz, hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  return r1 == r2 && c1 == c2;
+}
+
+// SA-AMG hierarchy of one field's diagonal block (level 0 already set)
+static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
+  const hbgs_options& o = c->o;
+  Pool& pool = c->hier;
+  const uint64_t salt_base = splitmix64_host(o.seed + 0x1000ull * (uint64_t)(F.id + 1));
+  Tmp<int> flag1(1);
+  for (int l = 0;; ++l) {
+    const int n = F.lv[l].A.n;
+    Tmp<double> d(n);
+    HBGS_HIP(hipMemsetAsync(flag1.p, 0, sizeof(int), s));
+    setup::diagonal(F.lv[l].A, d.p, flag1.p, s);
+    int missing = 0;
+    HBGS_HIP(hipMemcpyAsync(&missing, flag1.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HBGS_HIP(hipStreamSynchronize(s));
+    if (missing) HBGS_FAIL(HBGS_EINVAL, "zero or missing diagonal entry in a field block");
+    bool last = n <= o.coarse_max || l + 1 >= o.max_levels;
+    if (!last) {
+      DCsr& A = F.lv[l].A;
+      Tmp<char> strong(A.nnz), excluded(n), state(n), r1(n);
+      Tmp<uint64_t> m1(n);
+      setup::strength(A, d.p, o.theta[F.id], strong.p, excluded.p, s);
+      const uint64_t salt = salt_base + (uint64_t)l;
+      setup::mis2_init(n, excluded.p, state.p, s);
+      for (int round = 0;; ++round) {
+        setup::mis2_round(A, strong.p, salt, state.p, m1.p, r1.p, flag1.p, s);
+        int und = 0;
+        HBGS_HIP(hipMemcpyAsync(&und, flag1.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HBGS_HIP(hipStreamSynchronize(s));
+        if (und == 0) break;
+        if (round > n + 2) HBGS_FAIL(HBGS_ESETUP, "aggregation did not terminate");
+      }
+      Tmp<int> rflag(n), sflag(n);
+      Tmp<int64_t> rrank(n + 1), srank(n + 1);
+      setup::agg_roots(n, state.p, rflag.p, s);
+      int64_t nroot = setup::scan_i32_to_i64(rflag.p, rrank.p, n, s);
+      int* agg = pool.make<int>(n);
+      setup::agg_phase12(A, strong.p, salt, state.p, rrank.p, agg, sflag.p, s);
+      int64_t nsingle = setup::scan_i32_to_i64(sflag.p, srank.p, n, s);
+      setup::agg_phase3(n, sflag.p, srank.p, (int)nroot, agg, s);
+      int64_t nagg = nroot + nsingle;
+      if (nagg == 0 || (double)nagg > 0.95 * n) {
+        pool.release(agg);
+        last = true;
+      } else {
+        F.lv[l].agg = agg;
+        // filtered matrix and absolute-row-sum weight
+        DCsr af;
+        af.n = af.m = n;
+        Tmp<int> cnt(n), afrp(n + 1);
+        setup::filter_count(A, strong.p, cnt.p, s);
+        af.nnz = setup::counts_to_rowptr(cnt.p, afrp.p, n, s);
+        Tmp<int> afci(af.nnz);
+        Tmp<double> afv(af.nnz), dabs(n);
+        af.rp = afrp.p;
+        af.ci = afci.p;
+        af.v = afv.p;
+        setup::filter_fill(A, strong.p, af.rp, af.ci, af.v, dabs.p, s);
+        double lam_p = setup::power_estimate(af, dabs.p, o.eig_iters, splitmix64_host(salt_base + 0x5000 + l), s);
+        if (!(lam_p > 0.0)) HBGS_FAIL(HBGS_ESETUP, "non-positive eigenvalue estimate for prolongator smoothing");
+        double omega = o.sa_damping / lam_p;
+        F.lv[l].lam_p = lam_p;
+        F.lv[l].omega = omega;
+        DCsr P;
+        P.n = n;
+        P.m = (int)nagg;
+        P.rp = pool.make<int>(n + 1);
+        setup::psmooth_count(af, agg, cnt.p, s);
+        P.nnz = setup::counts_to_rowptr(cnt.p, P.rp, n, s);
+        P.ci = pool.make<int>(P.nnz);
+        P.v = pool.make<double>(P.nnz);
+        setup::psmooth_fill(af, agg, dabs.p, omega, P.rp, P.ci, P.v, s);
+        DCsr R = transpose_new(pool, P, s);
+        DCsr AP, Ac;
+        Pool tmp_pool;
+        setup::spgemm(A, P, AP, tmp_pool, s);
+        setup::spgemm(R, AP, Ac, pool, s);
+        F.lv[l].P = P;
+        F.lv[l].R = R;
+        F.lv.emplace_back();
+        F.lv[l + 1].A = Ac;
+      }
+    }
+    Level& L = F.lv[l];
+    if (last) {
+      if (n > 8000) HBGS_FAIL(HBGS_ESETUP, "coarsest level too large for the dense factorisation");
+      F.inv = pool.make<double>((size_t)n * n);
+      if (setup::dense_inverse(L.A, F.inv, s) != 0) HBGS_FAIL(HBGS_ESINGULAR, "singular coarsest-level matrix");
+      break;
+    }
+    L.dinv = pool.make<double>(n);
+    L.dinvf = pool.make<float>(n);
+    setup::reciprocal(n, d.p, L.dinv, L.dinvf, s);
+    L.lam_cheb = setup::power_estimate(L.A, d.p, o.eig_iters, splitmix64_host(salt_base + 0x9000 + l), s);
+    L.cc = cheb_coef(o, L.lam_cheb);
+  }
+  // solve-phase data: transposes, FP32 copies, work vectors
+  for (size_t l = 0; l < F.lv.size(); ++l) {
+    Level& L = F.lv[l];
+    L.AT = transpose_new(pool, L.A, s);
+    add_f32(pool, L.A, s);
+    add_f32(pool, L.AT, s);
+    if (l + 1 < F.lv.size()) {
+      add_f32(pool, L.P, s);
+      add_f32(pool, L.R, s);
+    }
+    const int n = L.A.n;
+    L.bd = pool.make<double>(n);
+    L.xd = pool.make<double>(n);
+    L.rd = pool.make<double>(n);
+    L.dd = pool.make<double>(n);
+    L.dnd = pool.make<double>(n);
+    L.bf = pool.make<float>(n);
+    L.xf = pool.make<float>(n);
+    L.rf = pool.make<float>(n);
+    L.df = pool.make<float>(n);
+    L.dnf = pool.make<float>(n);
+  }
+  if (!structurally_symmetric(F.lv[0].A, F.lv[0].AT, s))
+    HBGS_FAIL(HBGS_EINVAL, "a diagonal field block is not structurally symmetric");
+}
+
+static double spmv_bytes(const DCsr& a, int tv, int tx, int ty, int extra_vec) {
+  return (double)a.nnz * (tv + 4) + 4.0 * (a.n + 1) + (double)a.m * tx + (double)a.n * ty +
+         (double)extra_vec * a.n * tv;
+}
+
+static void compute_stats(hbgs_ctx* c) {
+  hbgs_stats_t& st = c->stats;
+  st.n = c->n;
+  st.n_fields = c->nf;
+  st.nnz = c->nnz;
+  for (int p = 0; p < 2; ++p) {
+    int T = p == 0 ? 8 : 4;
+    double b = 0;
+    for (int f : c->leaf_order) {
+      const Field& F = c->F[f];
+      if (F.lower.nnz) b += spmv_bytes(F.lower, T, T, T, 0) + 8.0 * F.n();
+      for (size_t l = 0; l + 1 < F.lv.size(); ++l) {
+        const Level& L = F.lv[l];
+        const DCsr& A = L.A;
+        b += spmv_bytes(A, T, T, T, 1);          // pre (b, dinv gathered; x written)
+        b += spmv_bytes(A, T, T, T, 1);          // residual
+        b += spmv_bytes(L.R, T, T, T, 0);        // restriction
+        b += spmv_bytes(L.P, T, T, T, 1);        // prolongation (x read+write)
+        b += spmv_bytes(A, T, T, 2 * T, 2);      // post start
+        b += spmv_bytes(A, T, T, T, 3);          // post step
+      }
+      int nc = F.lv.back().A.n;
+      b += 8.0 * nc * nc + 2.0 * nc * T;
+    }
+    st.vcycle_bytes[p] = b;
+    st.spmv_bytes[p] = spmv_bytes(c->Ap, 8, T, 8, 0);
+  }
+  for (int f = 0; f < c->nf && f < HBGS_MAX_FIELDS; ++f) {
+    const Field& F = c->F[f];
+    st.levels[f] = (int)F.lv.size();
+    for (size_t l = 0; l < F.lv.size() && l < HBGS_MAX_LEVELS; ++l) {
+      st.rows[f][l] = F.lv[l].A.n;
+      st.nnz_a[f][l] = F.lv[l].A.nnz;
+      st.nnz_p[f][l] = l + 1 < F.lv.size() ? F.lv[l].P.nnz : 0;
+    }
+  }
+}
+
+// value-dependent part of setup: blocks, couplings, hierarchies
+static void build_values(hbgs_ctx* c, hipStream_t s) {
+  c->hier.~Pool();
+  new (&c->hier) Pool();
+  c->F.assign(c->nf, Field{});
+  for (int f = 0; f < c->nf; ++f) {
+    Field& F = c->F[f];
+    F.id = f;
+    F.lo = c->f_lo[f];
+    F.hi = c->f_hi[f];
+    F.lv.clear();
+    F.lv.emplace_back();
+    F.lv[0].A = extract(c->hier, c->Ap, F.lo, F.hi, F.lo, F.hi, F.lo, F.n(), s);
+    F.lower = extract(c->hier, c->Ap, F.lo, F.hi, 0, F.lo, 0, c->n, s);
+    F.upperT = extract(c->hier, c->ApT, F.lo, F.hi, F.hi, c->n, 0, c->n, s);
+    add_f32(c->hier, F.lower, s);
+    add_f32(c->hier, F.upperT, s);
+    F.td = c->hier.make<double>(F.n());
+    F.tf = c->hier.make<float>(F.n());
+    build_hierarchy(c, F, s);
+  }
+  HBGS_HIP(hipStreamSynchronize(s));
+  compute_stats(c);
+}
+
+// --------------------------------------------------------------- V-cycle
+template <class T>
+struct Buf;
+template <>
+struct Buf<double> {
+  static double* b(Level& L) { return L.bd; }
+  static double* x(Level& L) { return L.xd; }
+  static double* r(Level& L) { return L.rd; }
+  static double* d(Level& L) { return L.dd; }
+  static double* dn(Level& L) { return L.dnd; }
+  static const double* dinv(const Level& L) { return L.dinv; }
+  static double* t(Field& F) { return F.td; }
+};
+template <>
+struct Buf<float> {
+  static float* b(Level& L) { return L.bf; }
+  static float* x(Level& L) { return L.xf; }
+  static float* r(Level& L) { return L.rf; }
+  static float* d(Level& L) { return L.df; }
+  static float* dn(Level& L) { return L.dnf; }
+  static const float* dinv(const Level& L) { return L.dinvf; }
+  static float* t(Field& F) { return F.tf; }
+};
+
+template <class T>
+static void vcycle(hbgs_ctx* c, Field& F, int l, int tr, const T* b, T* x, hipStream_t s) {
+  using B = Buf<T>;
+  const int TS = (int)sizeof(T);
+  Level& L = F.lv[l];
+  const int n = L.A.n;
+  if (l + 1 == (int)F.lv.size()) {
+    Prof p(c->prof, s, solve::K_COARSE, 8.0 * n * n + 2.0 * n * TS);
+    VcOps<T>::coarse(n, F.inv, tr, b, x, s);
+    return;
+  }
+  const DCsr& A = tr ? L.AT : L.A;
+  const T* dinv = B::dinv(L);
+  const solve::ChebCoef& cc = L.cc;
+  T *r = B::r(L), *d = B::d(L), *dn = B::dn(L);
+  // pre-smoothing from a zero guess
+  if (cc.degree == 2) {
+    Prof p(c->prof, s, solve::K_CHEB_PRE, spmv_bytes(A, TS, TS, TS, 1));
+    VcOps<T>::pre2(A, dinv, cc, b, x, s);
+  } else {
+    {
+      Prof p(c->prof, s, solve::K_CHEB_OTHER, 4.0 * n * TS);
+      VcOps<T>::init0(n, dinv, cc, b, r, d, x, s);
+    }
+    for (int k = 1; k < cc.degree; ++k) {
+      Prof p(c->prof, s, solve::K_CHEB_OTHER, spmv_bytes(A, TS, TS, 3 * TS, 2));
+      VcOps<T>::step(A, dinv, cc, k, false, k + 1 < cc.degree, r, d, dn, x, s);
+      std::swap(d, dn);
+    }
+  }
+  {
+    Prof p(c->prof, s, solve::K_RESID, spmv_bytes(A, TS, TS, TS, 1));
+    VcOps<T>::resid(A, b, x, r, s);
+  }
+  Level& C = F.lv[l + 1];
+  {
+    Prof p(c->prof, s, solve::K_RESTRICT, spmv_bytes(L.R, TS, TS, TS, 0));
+    VcOps<T>::restrict_(L.R, r, B::b(C), s);
+  }
+  vcycle<T>(c, F, l + 1, tr, B::b(C), B::x(C), s);
+  {
+    Prof p(c->prof, s, solve::K_PROLONG, spmv_bytes(L.P, TS, TS, TS, 1));
+    VcOps<T>::prolong(L.P, B::x(C), x, s);
+  }
+  // post-smoothing from x
+  d = B::d(L);
+  dn = B::dn(L);
+  {
+    Prof p(c->prof, s, solve::K_CHEB_POST_A, spmv_bytes(A, TS, TS, 2 * TS, 2));
+    VcOps<T>::post_start(A, dinv, cc, b, x, r, d, s);
+  }
+  if (cc.degree == 1) {
+    Prof p(c->prof, s, solve::K_CHEB_OTHER, 3.0 * n * TS);
+    VcOps<T>::add(n, d, x, s);
+  }
+  for (int k = 1; k < cc.degree; ++k) {
+    bool keep = k + 1 < cc.degree;
+    Prof p(c->prof, s, keep ? solve::K_CHEB_OTHER : solve::K_CHEB_POST_B, spmv_bytes(A, TS, TS, TS, 3));
+    VcOps<T>::step(A, dinv, cc, k, k == 1, keep, r, d, dn, x, s);
+    std::swap(d, dn);
+  }
+}
+
+// z = M^-1 v (tr = 0) or M^-T v (tr = 1), permuted ordering; z has type T
+template <class T>
+static void sweep(hbgs_ctx* c, int tr, const double* v, T* z, hipStream_t s) {
+  const int nl = (int)c->leaf_order.size();
+  const int TS = (int)sizeof(T);
+  for (int q = 0; q < nl; ++q) {
+    Field& F = c->F[c->leaf_order[tr ? nl - 1 - q : q]];
+    const DCsr& cpl = tr ? F.upperT : F.lower;
+    const T* t;
+    if (cpl.nnz > 0) {
+      Prof p(c->prof, s, solve::K_COUPLE, spmv_bytes(cpl, TS, 0, TS, 0) + 8.0 * F.n() + (double)std::min<int64_t>(cpl.nnz, c->n) * TS);
+      VcOps<T>::couple(cpl, v + F.lo, z, Buf<T>::t(F), s);
+      t = Buf<T>::t(F);
+    } else if (sizeof(T) == sizeof(double)) {
+      t = reinterpret_cast<const T*>(v + F.lo);
+    } else {
+      Prof p(c->prof, s, solve::K_COUPLE, 12.0 * F.n());
+      VcOps<T>::cast_in(F.n(), v + F.lo, Buf<T>::t(F), s);
+      t = Buf<T>::t(F);
+    }
+    vcycle<T>(c, F, 0, tr, t, z + F.lo, s);
+  }
+}
+
+// ------------------------------------------------------------------ GMRES
+static void ensure_workspace(hbgs_ctx* c) {
+  if (c->V) {
+    if (c->precision == 1 && !c->Zf) c->Zf = c->pool.make<float>((size_t)c->m * c->ld);
+    if (c->precision == 0 && !c->Zd) c->Zd = c->pool.make<double>((size_t)c->m * c->ld);
+    return;
+  }
+  const int n = c->n, m = c->m;
+  c->ld = ((size_t)n + 63) / 64 * 64;
+  c->V = c->pool.make<double>((size_t)(m + 1) * c->ld);
+  if (c->precision == 1)
+    c->Zf = c->pool.make<float>((size_t)m * c->ld);
+  else
+    c->Zd = c->pool.make<double>((size_t)m * c->ld);
+  c->bp = c->pool.make<double>(n);
+  c->xp = c->pool.make<double>(n);
+  c->r = c->pool.make<double>(n);
+  c->tmp = c->pool.make<double>(n);
+  int nb = solve::dot_blocks(n);
+  c->part = c->pool.make<double>((size_t)(m + 2) * nb);
+  c->h1 = c->pool.make<double>(m + 2);
+  c->h2 = c->pool.make<double>(m + 2);
+  c->hn2 = c->pool.make<double>(2);
+  c->H = c->pool.make<double>((size_t)(m + 1) * m);
+  c->cs = c->pool.make<double>(m);
+  c->sn = c->pool.make<double>(m);
+  c->g = c->pool.make<double>(m + 1);
+  c->y = c->pool.make<double>(m);
+  c->scal = c->pool.make<double>(4);
+  if (!c->host_scal) HBGS_HIP(hipHostMalloc((void**)&c->host_scal, 8 * sizeof(double), hipHostMallocDefault));
+}
+
+static double norm2(hbgs_ctx* c, const double* x, hipStream_t s) {
+  int nb = solve::dot_blocks(c->n);
+  {
+    Prof p(c->prof, s, solve::K_REDUCE, 8.0 * c->n);
+    solve::norm2_partial(c->n, x, c->part, s);
+    solve::mdot_reduce(1, nb, c->part, c->hn2, s);
+  }
+  HBGS_HIP(hipMemcpyAsync(c->host_scal, c->hn2, sizeof(double), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  return c->host_scal[0];
+}
+
+static void apply_perm(hbgs_ctx* c, int tr, const double* v, int j, hipStream_t s) {
+  if (c->precision == 1)
+    sweep<float>(c, tr, v, c->Zf + (size_t)j * c->ld, s);
+  else
+    sweep<double>(c, tr, v, c->Zd + (size_t)j * c->ld, s);
+}
+
+static hbgs_status gmres(hbgs_ctx* c, int tr, int use_x0, int32_t* iters, double* hist, int cap, int32_t* hlen,
+                         hipStream_t s) {
+  const int n = c->n, m = c->m;
+  const DCsr& A = tr ? c->ApT : c->Ap;
+  const size_t ld = c->ld;
+  const int nb = solve::dot_blocks(n);
+  *iters = 0;
+  *hlen = 0;
+  auto push = [&](double v) {
+    if (hist && *hlen < cap) hist[*hlen] = v;
+    (*hlen)++;
+  };
+  double bnorm = std::sqrt(norm2(c, c->bp, s));
+  if (bnorm == 0.0) {
+    HBGS_HIP(hipMemsetAsync(c->xp, 0, sizeof(double) * n, s));
+    push(0.0);
+    return HBGS_OK;
+  }
+  if (!use_x0) HBGS_HIP(hipMemsetAsync(c->xp, 0, sizeof(double) * n, s));
+  auto true_resid = [&]() {
+    {
+      Prof p(c->prof, s, solve::K_SPMV_RESID, spmv_bytes(A, 8, 8, 8, 1));
+      solve::spmv_resid_f64(A, c->xp, c->bp, c->r, s);
+    }
+    return std::sqrt(norm2(c, c->r, s));
+  };
+  double beta = true_resid();
+  push(beta / bnorm);
+  for (;;) {
+    if (beta / bnorm <= c->o.rtol) return HBGS_OK;
+    if (*iters >= c->o.max_iters) return HBGS_NOT_CONVERGED;
+    {
+      Prof p(c->prof, s, solve::K_SCALE, 16.0 * n);
+      solve::scale_copy(n, c->r, c->hn2, c->V, s);  // hn2 holds ||r||^2 from true_resid
+    }
+    std::vector<double> g0(m + 1, 0.0);
+    g0[0] = beta;
+    HBGS_HIP(hipMemcpyAsync(c->g, g0.data(), sizeof(double) * (m + 1), hipMemcpyHostToDevice, s));
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = c->V + (size_t)j * ld;
+      double* w = c->V + (size_t)(j + 1) * ld;
+      apply_perm(c, tr, vj, j, s);
+      {
+        Prof p(c->prof, s, solve::K_SPMV_OUTER, spmv_bytes(A, 8, c->precision ? 4 : 8, 8, 0));
+        if (c->precision == 1)
+          solve::spmv_outer_mixed(A, c->Zf + (size_t)j * ld, w, s);
+        else
+          solve::spmv_outer_f64(A, c->Zd + (size_t)j * ld, w, s);
+      }
+      {
+        Prof p(c->prof, s, solve::K_DOT1, 8.0 * n * (j + 2));
+        solve::mdot(n, j, c->V, ld, w, c->part, s);
+      }
+      {
+        Prof p(c->prof, s, solve::K_REDUCE, 8.0 * nb * (j + 2));
+        solve::mdot_reduce(j + 2, nb, c->part, c->h1, s);
+      }
+      {
+        Prof p(c->prof, s, solve::K_UPD_DOT2, 8.0 * n * (j + 3));
+        solve::upd_mdot(n, j, c->V, ld, w, c->h1, c->part, s);
+      }
+      {
+        Prof p(c->prof, s, solve::K_REDUCE, 8.0 * nb * (j + 2));
+        solve::mdot_reduce(j + 2, nb, c->part, c->h2, s);
+      }
+      {
+        Prof p(c->prof, s, solve::K_UPD_NORM, 8.0 * n * (j + 3));
+        solve::upd_norm(n, j, c->V, ld, w, c->h2, c->part, s);
+      }
+      {
+        Prof p(c->prof, s, solve::K_REDUCE, 8.0 * nb);
+        solve::mdot_reduce(1, nb, c->part + (size_t)(j + 1) * nb, c->hn2, s);
+      }
+      {
+        Prof p(c->prof, s, solve::K_GIVENS, 0.0);
+        solve::givens(j, m, c->h1, c->h2, c->hn2, c->h1 + (j + 1), c->H, c->cs, c->sn, c->g, c->scal, s);
+      }
+      {
+        Prof p(c->prof, s, solve::K_SCALE, 16.0 * n);
+        solve::scale(n, w, c->scal, w, s);
+      }
+      HBGS_HIP(hipMemcpyAsync(c->host_scal, c->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HBGS_HIP(hipStreamSynchronize(s));
+      (*iters)++;
+      double est = c->host_scal[0] / bnorm, hn = c->host_scal[1], w0 = c->host_scal[2];
+      push(est);
+      jend = j + 1;
+      if (!(est == est)) HBGS_FAIL(HBGS_EHIP, "non-finite residual estimate");
+      if (est <= c->o.rtol || hn <= 1e-14 * w0 || *iters >= c->o.max_iters) break;
+    }
+    solve::backsolve(jend, m, c->H, c->g, c->y, s);
+    {
+      Prof p(c->prof, s, solve::K_XUPDATE, (double)n * (16 + jend * (c->precision ? 4 : 8)));
+      if (c->precision == 1)
+        solve::xupdate<float>(n, jend, c->Zf, ld, c->y, c->xp, s);
+      else
+        solve::xupdate<double>(n, jend, c->Zd, ld, c->y, c->xp, s);
+    }
+    beta = true_resid();
+    if (hist && *hlen - 1 < cap) hist[*hlen - 1] = beta / bnorm;
+  }
+}
+
+}  // namespace hbgs
+
+// ===================================================================== C ABI
+using namespace hbgs;
+
+#define HBGS_API_BEGIN try {
+#define HBGS_API_END                                 \
+  }                                                  \
+  catch (const hbgs::Error& e) {                     \
+    return e.code;                                   \
+  }                                                  \
+  catch (const std::exception& e) {                  \
+    hbgs::set_error(std::string("exception: ") + e.what()); \
+    return HBGS_EHIP;                                \
+  }
+
+extern "C" {
+
+void hbgs_default_options(hbgs_options* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->precision = 0;
+  o->restart = 50;
+  o->max_iters = 2000;
+  o->rtol = 1e-8;
+  o->cheb_degree = 2;
+  o->cheb_ratio = 30.0;
+  o->cheb_boost = 1.1;
+  o->eig_iters = 10;
+  o->sa_damping = 4.0 / 3.0;
+  o->coarse_max = 2000;
+  o->max_levels = 10;
+  o->seed = 0x2602ull;
+  o->theta[0] = 0.04;
+}
+
+const char* hbgs_last_error(void) { return g_last_error.c_str(); }
+
+hbgs_status hbgs_setup(hbgs_ctx** out, int32_t n, int64_t nnz, const int32_t* rowptr, const int32_t* col,
+                       const double* val, int32_t n_fields, const int32_t* field_of_row, int32_t tree_len,
+                       const int32_t* group_tree, const hbgs_options* opt, void* stream) {
+  if (!out) {
+    set_error("out is NULL");
+    return HBGS_EINVAL;
+  }
+  *out = nullptr;
+  hbgs_ctx* c = nullptr;
+  HBGS_API_BEGIN
+  hipStream_t s = (hipStream_t)stream;
+  auto t0 = std::chrono::steady_clock::now();
+  if (n <= 0 || nnz <= 0 || nnz > INT32_MAX) HBGS_FAIL(HBGS_EINVAL, "n and nnz must be positive (nnz < 2^31)");
+  if (n_fields < 1 || n_fields > HBGS_MAX_FIELDS) HBGS_FAIL(HBGS_EINVAL, "n_fields out of range");
+  if (!rowptr || !col || !val || !field_of_row || !group_tree) HBGS_FAIL(HBGS_EINVAL, "NULL argument");
+  c = new hbgs_ctx();
+  if (opt)
+    c->o = *opt;
+  else
+    hbgs_default_options(&c->o);
+  validate_options(c->o);
+  c->precision = c->o.precision;
+  c->m = c->o.restart;
+  c->n = n;
+  c->nf = n_fields;
+  c->nnz = nnz;
+  parse_tree(c, group_tree, tree_len);
+  // keep the caller's pattern and validate it
+  c->rp0 = c->pool.make<int>(n + 1);
+  c->ci0 = c->pool.make<int>(nnz);
+  HBGS_HIP(hipMemcpyAsync(c->rp0, rowptr, sizeof(int) * (n + 1), hipMemcpyDeviceToDevice, s));
+  HBGS_HIP(hipMemcpyAsync(c->ci0, col, sizeof(int) * nnz, hipMemcpyDeviceToDevice, s));
+  int64_t last = 0;
+  HBGS_HIP(hipMemcpyAsync(&last, rowptr + n, sizeof(int), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  if ((int)last != nnz) HBGS_FAIL(HBGS_EINVAL, "rowptr[n] != nnz");
+  {
+    Tmp<int> flags(1);
+    HBGS_HIP(hipMemsetAsync(flags.p, 0, sizeof(int), s));
+    setup::validate(n, nnz, c->rp0, c->ci0, val, n_fields, field_of_row, flags.p, s);
+    int f = 0;
+    HBGS_HIP(hipMemcpyAsync(&f, flags.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HBGS_HIP(hipStreamSynchronize(s));
+    if (f & 1) HBGS_FAIL(HBGS_EINVAL, "invalid row pointers");
+    if (f & 2) HBGS_FAIL(HBGS_EINVAL, "column index out of range");
+    if (f & 4) HBGS_FAIL(HBGS_EINVAL, "columns not strictly increasing within a row");
+    if (f & 8) HBGS_FAIL(HBGS_EINVAL, "missing or zero diagonal entry");
+    if (f & 16) HBGS_FAIL(HBGS_EINVAL, "field id out of range");
+    if (f & 32) HBGS_FAIL(HBGS_EINVAL, "non-finite matrix value");
+  }
+  // field-major permutation in depth-first leaf order
+  std::vector<int> counts(n_fields);
+  {
+    Tmp<int> dc(n_fields);
+    setup::field_histogram(n, field_of_row, n_fields, dc.p, s);
+    HBGS_HIP(hipMemcpyAsync(counts.data(), dc.p, sizeof(int) * n_fields, hipMemcpyDeviceToHost, s));
+    HBGS_HIP(hipStreamSynchronize(s));
+  }
+  c->f_lo.assign(n_fields, 0);
+  c->f_hi.assign(n_fields, 0);
+  int off = 0;
+  for (int f : c->leaf_order) {
+    if (counts[f] == 0) HBGS_FAIL(HBGS_EINVAL, "a field has no rows");
+    c->f_lo[f] = off;
+    off += counts[f];
+    c->f_hi[f] = off;
+  }
+  c->perm = c->pool.make<int>(n);
+  c->iperm = c->pool.make<int>(n);
+  setup::field_ranks_all(n, field_of_row, n_fields, c->f_lo.data(), c->perm, s);
+  setup::invert_perm(n, c->perm, c->iperm, s);
+  {
+    Tmp<int> len(n);
+    setup::permuted_lengths(n, c->rp0, c->perm, len.p, s);
+    c->Ap.n = c->Ap.m = n;
+    c->Ap.rp = c->pool.make<int>(n + 1);
+    c->Ap.nnz = setup::counts_to_rowptr(len.p, c->Ap.rp, n, s);
+    c->Ap.ci = c->pool.make<int>(nnz);
+    c->Ap.v = c->pool.make<double>(nnz);
+    c->src = c->pool.make<int>(nnz);
+    setup::permute_fill(n, c->rp0, c->ci0, val, c->perm, c->iperm, c->Ap.rp, c->Ap.ci, c->Ap.v, c->src, s);
+  }
+  c->ApT = transpose_new(c->pool, c->Ap, s);
+  build_values(c, s);
+  c->stats.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *out = c;
+  return HBGS_OK;
+  }
+  catch (const hbgs::Error& e) {
+    delete c;
+    return e.code;
+  }
+  catch (const std::exception& e) {
+    delete c;
+    hbgs::set_error(std::string("exception: ") + e.what());
+    return HBGS_EHIP;
+  }
+}
+
+__global__ void k_gather_vals(int64_t nnz, const double* v, const int* src, double* vp) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) vp[k] = v[src[k]];
+}
+
+hbgs_status hbgs_set_values(hbgs_ctx* c, const double* val, void* stream) {
+  if (!c || !val) {
+    set_error("NULL argument");
+    return HBGS_EINVAL;
+  }
+  HBGS_API_BEGIN
+  hipStream_t s = (hipStream_t)stream;
+  auto t0 = std::chrono::steady_clock::now();
+  k_gather_vals<<<grid_for(c->nnz, 256), 256, 0, s>>>(c->nnz, val, c->src, c->Ap.v);
+  HBGS_HIP(hipGetLastError());
+  // A^T values: transpose again (same pattern)
+  setup::transpose(c->Ap, c->ApT, s);
+  build_values(c, s);
+  c->stats.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return HBGS_OK;
+  HBGS_API_END
+}
+
+hbgs_status hbgs_set_precision(hbgs_ctx* c, int32_t precision) {
+  if (!c || (precision != 0 && precision != 1)) {
+    set_error("invalid precision");
+    return HBGS_EINVAL;
+  }
+  c->precision = precision;
+  return HBGS_OK;
+}
+
+hbgs_status hbgs_apply(hbgs_ctx* c, const double* r, double* z, int32_t transpose, void* stream) {
+  if (!c || !r || !z) {
+    set_error("NULL argument");
+    return HBGS_EINVAL;
+  }
+  HBGS_API_BEGIN
+  hipStream_t s = (hipStream_t)stream;
+  ensure_workspace(c);
+  solve::permute_in(c->n, c->perm, r, c->bp, s);
+  apply_perm(c, transpose ? 1 : 0, c->bp, 0, s);
+  const double* zp = c->Zd;
+  if (c->precision == 1) {  // widen the FP32 result: tmp = 0 + 1 * Z_0
+    c->host_scal[4] = 1.0;
+    HBGS_HIP(hipMemcpyAsync(c->y, c->host_scal + 4, sizeof(double), hipMemcpyHostToDevice, s));
+    HBGS_HIP(hipMemsetAsync(c->tmp, 0, sizeof(double) * c->n, s));
+    solve::xupdate<float>(c->n, 1, c->Zf, c->ld, c->y, c->tmp, s);
+    zp = c->tmp;
+  }
+  solve::permute_out(c->n, c->perm, zp, z, s);
+  HBGS_HIP(hipStreamSynchronize(s));
+  return HBGS_OK;
+  HBGS_API_END
+}
+
+hbgs_status hbgs_solve(hbgs_ctx* c, const double* b, double* x, int32_t use_x0, int32_t transpose, int32_t* iters,
+                       double* hist, int32_t hist_cap, int32_t* hist_len, void* stream) {
+  if (!c || !b || !x) {
+    set_error("NULL argument");
+    return HBGS_EINVAL;
+  }
+  HBGS_API_BEGIN
+  hipStream_t s = (hipStream_t)stream;
+  ensure_workspace(c);
+  int32_t it = 0, hl = 0;
+  solve::permute_in(c->n, c->perm, b, c->bp, s);
+  if (use_x0) solve::permute_in(c->n, c->perm, x, c->xp, s);
+  hbgs_status st = gmres(c, transpose ? 1 : 0, use_x0, &it, hist, hist_cap, &hl, s);
+  solve::permute_out(c->n, c->perm, c->xp, x, s);
+  HBGS_HIP(hipStreamSynchronize(s));
+  if (c->prof.on) c->prof.flush();
+  if (iters) *iters = it;
+  if (hist_len) *hist_len = hl;
+  return st;
+  HBGS_API_END
+}
+
+hbgs_status hbgs_grad_values(hbgs_ctx* c, const double* lambda, const double* x, double* grad_val, void* stream) {
+  if (!c || !lambda || !x || !grad_val) {
+    set_error("NULL argument");
+    return HBGS_EINVAL;
+  }
+  HBGS_API_BEGIN
+  solve::grad_values(c->n, c->rp0, c->ci0, lambda, x, grad_val, (hipStream_t)stream);
+  return HBGS_OK;
+  HBGS_API_END
+}
+
+hbgs_status hbgs_stats(hbgs_ctx* c, hbgs_stats_t* out) {
+  if (!c || !out) {
+    set_error("NULL argument");
+    return HBGS_EINVAL;
+  }
+  *out = c->stats;
+  return HBGS_OK;
+}
+
+hbgs_status hbgs_get_level(hbgs_ctx* c, int32_t field, int32_t level, int32_t which, int32_t* n_rows,
+                           int32_t* n_cols, int64_t* nnz, int32_t* rowptr, int32_t* col, double* val) {
+  if (!c || field < 0 || field >= c->nf || level < 0 || level >= (int)c->F[field].lv.size() || which < 0 ||
+      which > 3) {
+    set_error("invalid field/level/which");
+    return HBGS_EINVAL;
+  }
+  HBGS_API_BEGIN
+  const Level& L = c->F[field].lv[level];
+  bool coarsest = level + 1 == (int)c->F[field].lv.size();
+  if ((which == 1 || which == 2) && coarsest) HBGS_FAIL(HBGS_EINVAL, "the coarsest level has no transfer operators");
+  const DCsr& a = which == 0 ? L.A : which == 1 ? L.P : which == 2 ? L.R : L.AT;
+  if (n_rows) *n_rows = a.n;
+  if (n_cols) *n_cols = a.m;
+  if (nnz) *nnz = a.nnz;
+  if (rowptr) HBGS_HIP(hipMemcpy(rowptr, a.rp, sizeof(int) * (a.n + 1), hipMemcpyDeviceToHost));
+  if (col) HBGS_HIP(hipMemcpy(col, a.ci, sizeof(int) * a.nnz, hipMemcpyDeviceToHost));
+  if (val) HBGS_HIP(hipMemcpy(val, a.v, sizeof(double) * a.nnz, hipMemcpyDeviceToHost));
+  return HBGS_OK;
+  HBGS_API_END
+}
+
+hbgs_status hbgs_get_aggregates(hbgs_ctx* c, int32_t field, int32_t level, int32_t* agg, double* out3) {
+  if (!c || field < 0 || field >= c->nf || level < 0 || level >= (int)c->F[field].lv.size()) {
+    set_error("invalid field/level");
+    return HBGS_EINVAL;
+  }
+  HBGS_API_BEGIN
+  const Level& L = c->F[field].lv[level];
+  if (agg) {
+    if (!L.agg) HBGS_FAIL(HBGS_EINVAL, "the coarsest level has no aggregates");
+    HBGS_HIP(hipMemcpy(agg, L.agg, sizeof(int) * L.A.n, hipMemcpyDeviceToHost));
+  }
+  if (out3) {
+    out3[0] = L.lam_cheb;
+    out3[1] = L.lam_p;
+    out3[2] = L.omega;
+  }
+  return HBGS_OK;
+  HBGS_API_END
+}
+
+hbgs_status hbgs_profile(hbgs_ctx* c, int32_t enable) {
+  if (!c) {
+    set_error("NULL context");
+    return HBGS_EINVAL;
+  }
+  HBGS_API_BEGIN
+  c->prof.flush();
+  c->prof.on = enable != 0;
+  c->prof.mask = enable == -1 ? 0xFFFFFFFFu : (uint32_t)enable;
+  if (enable) {
+    std::fill(std::begin(c->prof.total_ms), std::end(c->prof.total_ms), 0.0);
+    std::fill(std::begin(c->prof.launches), std::end(c->prof.launches), 0);
+    std::fill(std::begin(c->prof.bytes), std::end(c->prof.bytes), 0.0);
+  }
+  return HBGS_OK;
+  HBGS_API_END
+}
+
+int32_t hbgs_kernel_times(hbgs_ctx* c, char (*names)[48], double* total_ms, int64_t* launches, double* bytes,
+                          int32_t cap) {
+  if (!c) return 0;
+  try {
+    c->prof.flush();
+  } catch (const hbgs::Error&) {
+    return -1;
+  }
+  int k = 0;
+  for (int q = 0; q < solve::K_COUNT && k < cap; ++q) {
+    if (names) {
+      std::strncpy(names[k], solve::kind_names[q], 47);
+      names[k][47] = 0;
+    }
+    if (total_ms) total_ms[k] = c->prof.total_ms[q];
+    if (launches) launches[k] = c->prof.launches[q];
+    if (bytes) bytes[k] = c->prof.bytes[q];
+    ++k;
+  }
+  return k;
+}
+
+void hbgs_destroy(hbgs_ctx* c) { delete c; }
+
+}  // extern "C"

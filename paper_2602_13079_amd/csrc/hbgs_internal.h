@@ -1,0 +1,244 @@
+// Internal declarations shared by the HIP translation units of libhbgs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hbgs.h"
+
+namespace hbgs {
+
+// ----------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+
+struct Error {
+  hbgs_status code;
+};
+
+#define HBGS_HIP(expr)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      ::hbgs::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));         \
+      throw ::hbgs::Error{e_ == hipErrorOutOfMemory ? HBGS_ENOMEM : HBGS_EHIP};     \
+    }                                                                               \
+  } while (0)
+
+#define HBGS_FAIL(code, msg)      \
+  do {                            \
+    ::hbgs::set_error(msg);       \
+    throw ::hbgs::Error{code};    \
+  } while (0)
+
+// ----------------------------------------------------- device memory owner
+// All device memory of a context goes through a Pool: persistent buffers
+// live until the pool is destroyed, temporaries are released explicitly.
+class Pool {
+ public:
+  ~Pool();
+  void* get(size_t bytes);  // persistent
+  void release(void* p);    // free one persistent allocation early
+  template <class T>
+  T* make(size_t count) {
+    return static_cast<T*>(get(count * sizeof(T) + (count == 0 ? sizeof(T) : 0)));
+  }
+  size_t bytes() const { return total_; }
+
+ private:
+  std::vector<std::pair<void*, size_t>> blocks_;
+  size_t total_ = 0;
+};
+
+// Temporary device buffer (setup only).
+template <class T>
+struct Tmp {
+  T* p = nullptr;
+  size_t count = 0;
+  Tmp() = default;
+  explicit Tmp(size_t n) { alloc(n); }
+  void alloc(size_t n) {
+    release();
+    count = n;
+    HBGS_HIP(hipMalloc(&p, (n ? n : 1) * sizeof(T)));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+  }
+  ~Tmp() { release(); }
+  Tmp(const Tmp&) = delete;
+  Tmp& operator=(const Tmp&) = delete;
+};
+
+// ------------------------------------------------------------- device CSR
+struct DCsr {
+  int n = 0, m = 0;  // rows, columns
+  int64_t nnz = 0;
+  int* rp = nullptr;
+  int* ci = nullptr;
+  double* v = nullptr;
+  float* vf = nullptr;  // FP32 copy of v (solve phase, mixed precision)
+  float avg_row() const { return n ? (float)nnz / (float)n : 0.f; }
+};
+
+// ------------------------------------------------------ launch helpers
+inline unsigned grid_for(int64_t work, int block, int64_t cap = 1 << 20) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// ======================================================== setup kernels
+// (setup_kernels.hip, compiled without floating-point contraction so that
+// every value matches a sequential, rounded-product-then-add evaluation)
+namespace setup {
+// exclusive prefix sums; out has n+1 entries (out[n] = total); returns total
+int64_t scan_i32_to_i64(const int* in, int64_t* out, int64_t n, hipStream_t s);
+int64_t scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s);
+int64_t counts_to_rowptr(const int* counts, int* rp, int n, hipStream_t s);  // int32 rowptr
+
+void validate(int n, int64_t nnz, const int* rp, const int* ci, const double* v, int nf, const int* field,
+              int* flags, hipStream_t s);
+void field_histogram(int n, const int* field, int nf, int* counts, hipStream_t s);
+void field_ranks(int n, const int* field, int f, const int* f_lo_dev, int* perm, hipStream_t s);
+void field_ranks_all(int n, const int* field, int nf, const int* f_lo_host, int* perm, hipStream_t s);
+void invert_perm(int n, const int* perm, int* iperm, hipStream_t s);
+void permuted_lengths(int n, const int* rp, const int* perm, int* len, hipStream_t s);
+void permute_fill(int n, const int* rp, const int* ci, const double* v, const int* perm, const int* iperm,
+                  const int* rp_p, int* ci_p, double* v_p, int* pos_p, hipStream_t s);
+void scatter_values(int64_t nnz, const double* v, const int* pos, double* v_p, hipStream_t s);
+
+// transpose: t must have rp (m+1), ci, v allocated with a.nnz entries
+void transpose(const DCsr& a, DCsr& t, hipStream_t s);
+// sub-block: rows [r0,r1), columns [c0,c1) shifted by -coff; two passes
+void block_count(const DCsr& a, int r0, int r1, int c0, int c1, int* cnt, hipStream_t s);
+void block_fill(const DCsr& a, int r0, int r1, int c0, int c1, int coff, const int* rp_out, int* ci_out,
+                double* v_out, hipStream_t s);
+
+void diagonal(const DCsr& a, double* d, int* missing, hipStream_t s);
+void strength(const DCsr& a, const double* d, double theta, char* strong, char* excluded, hipStream_t s);
+// MIS-2 rounds: state 0 undecided, 1 root, 2 out, 3 excluded
+void mis2_init(int n, const char* excluded, char* state, hipStream_t s);
+void mis2_round(const DCsr& a, const char* strong, uint64_t salt, char* state, uint64_t* m1, char* r1,
+                int* undecided, hipStream_t s);
+void agg_roots(int n, const char* state, int* flag, hipStream_t s);
+void agg_phase12(const DCsr& a, const char* strong, uint64_t salt, const char* state, const int64_t* root_rank,
+                 int* agg, int* single_flag, hipStream_t s);
+void agg_phase3(int n, const int* single_flag, const int64_t* single_rank, int nroot, int* agg, hipStream_t s);
+
+void filter_count(const DCsr& a, const char* strong, int* cnt, hipStream_t s);
+void filter_fill(const DCsr& a, const char* strong, const int* rp_f, int* ci_f, double* v_f, double* dabs,
+                 hipStream_t s);
+
+// power estimate of D^-1 B: returns lambda (host), syncs the stream
+double power_estimate(const DCsr& b, const double* d, int iters, uint64_t salt, hipStream_t s);
+
+void psmooth_count(const DCsr& af, const int* agg, int* cnt, hipStream_t s);
+void psmooth_fill(const DCsr& af, const int* agg, const double* dabs, double omega, const int* rp_p, int* ci_p,
+                  double* v_p, hipStream_t s);
+
+// C = A B with in-order accumulation; allocates C's arrays from pool
+void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s);
+
+// dense coarsest factor: returns 0 ok, -4 singular; inv (row-major n*n) = A^-1
+int dense_inverse(const DCsr& a, double* inv, hipStream_t s);
+
+void cast_f32(int64_t n, const double* in, float* out, hipStream_t s);
+void reciprocal(int n, const double* d, double* dinv, float* dinvf, hipStream_t s);
+void sort_rows(const DCsr& a, hipStream_t s);
+}  // namespace setup
+
+// ======================================================== solve kernels
+namespace solve {
+// kernel classes tracked by the optional profiler
+enum Kind {
+  K_SPMV_OUTER = 0,
+  K_SPMV_RESID,
+  K_CHEB_PRE,
+  K_CHEB_POST_A,
+  K_CHEB_POST_B,
+  K_CHEB_OTHER,
+  K_RESID,
+  K_RESTRICT,
+  K_PROLONG,
+  K_COARSE,
+  K_COUPLE,
+  K_DOT1,
+  K_UPD_DOT2,
+  K_UPD_NORM,
+  K_REDUCE,
+  K_GIVENS,
+  K_SCALE,
+  K_XUPDATE,
+  K_PERMUTE,
+  K_COUNT
+};
+extern const char* kind_names[K_COUNT];
+
+struct ChebCoef {
+  int degree;
+  double c0;              // 1 / theta
+  double c1[8], c2[8];    // step k >= 1: d = c1 d + c2 D^-1 r
+};
+
+// outer SpMV, y = A x with x double or float; resid: y = b - A x
+void spmv_outer_f64(const DCsr& a, const double* x, double* y, hipStream_t s);
+void spmv_outer_mixed(const DCsr& a, const float* x, double* y, hipStream_t s);
+void spmv_resid_f64(const DCsr& a, const double* x, const double* b, double* r, hipStream_t s);
+
+template <class T>
+struct VcOps {
+  // degree-2 pre-smoothing from a zero guess, one fused kernel:
+  // x = d0 + c1 d0 + c2 D^-1 (b - A d0), d0 = D^-1 b / theta
+  static void pre2(const DCsr& a, const T* dinv, const ChebCoef& c, const T* b, T* x, hipStream_t s);
+  // general degree, zero guess: r = b, d = D^-1 b / theta, x = d
+  static void init0(int n, const T* dinv, const ChebCoef& c, const T* b, T* r, T* d, T* x, hipStream_t s);
+  // post-smoothing start from x: r = b - A x, d = D^-1 r / theta (x not yet updated)
+  static void post_start(const DCsr& a, const T* dinv, const ChebCoef& c, const T* b, const T* x, T* r, T* d,
+                         hipStream_t s);
+  // Chebyshev step k >= 1: r -= A d; dn = c1 d + c2 D^-1 r; x (+ d when add_d) += dn;
+  // r and dn are stored only when keep
+  static void step(const DCsr& a, const T* dinv, const ChebCoef& c, int k, bool add_d, bool keep, T* r,
+                   const T* d, T* dn, T* x, hipStream_t s);
+  static void add(int n, const T* d, T* x, hipStream_t s);
+  static void resid(const DCsr& a, const T* b, const T* x, T* r, hipStream_t s);
+  static void restrict_(const DCsr& rmat, const T* r, T* bc, hipStream_t s);
+  static void prolong(const DCsr& p, const T* xc, T* x, hipStream_t s);
+  static void coarse(int n, const double* inv, int transpose, const T* b, T* x, hipStream_t s);
+  // t = (T)v - sum over coupling columns of a * z, rows of one field
+  static void couple(const DCsr& c, const double* v, const T* z, T* t, hipStream_t s);
+  static void cast_in(int n, const double* v, T* t, hipStream_t s);
+};
+
+// GMRES pieces (FP64)
+void permute_in(int n, const int* perm, const double* x, double* xp, hipStream_t s);   // xp[perm[i]] = x[i]
+void permute_out(int n, const int* perm, const double* xp, double* x, hipStream_t s);  // x[i] = xp[perm[i]]
+int dot_blocks(int n);
+// h[k] = V_k . w for k <= j, plus w.w (h[j+1]); partial sums per block
+void mdot(int n, int j, const double* V, size_t ldv, const double* w, double* part, hipStream_t s);
+void mdot_reduce(int nvec, int nblocks, const double* part, double* out, hipStream_t s);
+// w -= V h (k <= j), then partial dots of the updated w with V_k (k <= j) and w.w
+void upd_mdot(int n, int j, const double* V, size_t ldv, double* w, const double* h, double* part,
+              hipStream_t s);
+// w -= V h, partial w.w
+void upd_norm(int n, int j, const double* V, size_t ldv, double* w, const double* h, double* part,
+              hipStream_t s);
+// Givens update of column j; writes scal[0] = est (|g_{j+1}|), scal[1] = 1/h_{j+1,j},
+// scal[2] = h_{j+1,j}, scal[3] = ||w|| before orthogonalisation
+void givens(int j, int m, const double* h1, const double* h2, const double* hn2, const double* w0sq, double* H,
+            double* cs, double* sn, double* g, double* scal, hipStream_t s);
+void scale(int n, const double* w, const double* scal, double* v, hipStream_t s);
+void backsolve(int jend, int m, const double* H, const double* g, double* y, hipStream_t s);
+template <class TZ>
+void xupdate(int n, int jend, const TZ* Z, size_t ldz, const double* y, double* x, hipStream_t s);
+void norm2_partial(int n, const double* x, double* part, hipStream_t s);
+void scale_copy(int n, const double* r, const double* part_sum, double* v, hipStream_t s);  // v = r / sqrt(sum)
+void grad_values(int n, const int* rp, const int* ci, const double* lam, const double* x, double* g,
+                 hipStream_t s);
+}  // namespace solve
+
+}  // namespace hbgs

@@ -1,0 +1,1023 @@
+// Device setup of the block Gauss-Seidel / SA-AMG preconditioner (gfx950).
+//
+// Built with -ffp-contract=off: every floating-point value below is produced
+// by the sequential, rounded-product-then-add evaluation that the method's
+// definitions state (ascending column order within a row), so aggregates,
+// sparsity patterns and hierarchy values are reproducible bit for bit.
+// Parallelism comes from rows (one thread per row); only integer decisions
+// and order-independent max reductions use atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "hbgs_internal.h"
+
+namespace hbgs {
+namespace setup {
+
+constexpr int BLK = 256;
+constexpr int SCAN_PER_THREAD = 4;
+constexpr int SCAN_TILE = BLK * SCAN_PER_THREAD;
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+// aggregation priority: hash32(i ^ salt) << 32 | i (distinct per row)
+__device__ __forceinline__ uint64_t agg_key(int i, uint64_t salt) {
+  uint64_t h = splitmix64((uint64_t)(uint32_t)i ^ salt) >> 32;
+  return (h << 32) | (uint64_t)(uint32_t)i;
+}
+
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+// ------------------------------------------------------------------ scans
+// Exclusive scan in tiles of 1024: tile sums, scan of the tile sums
+// (recursive), then a block-local scan with the tile offset.  Integers only.
+template <class TI>
+__global__ void k_tile_sums(const TI* in, int64_t n, int64_t* tsum) {
+  __shared__ int64_t sh[BLK];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER_THREAD;
+  int64_t acc = 0;
+  for (int q = 0; q < SCAN_PER_THREAD; ++q)
+    if (base + q < n) acc += (int64_t)in[base + q];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = BLK / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tsum[blockIdx.x] = sh[0];
+}
+
+template <class TI, class TO>
+__global__ void k_tile_scan(const TI* in, int64_t n, const int64_t* toff, TO* out) {
+  __shared__ int64_t sh[BLK];
+  int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_PER_THREAD;
+  int64_t v[SCAN_PER_THREAD];
+  int64_t acc = 0;
+  for (int q = 0; q < SCAN_PER_THREAD; ++q) {
+    v[q] = base + q < n ? (int64_t)in[base + q] : 0;
+    acc += v[q];
+  }
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  // inclusive Hillis-Steele scan of the per-thread sums
+  for (int s = 1; s < BLK; s <<= 1) {
+    int64_t t = (int)threadIdx.x >= s ? sh[threadIdx.x - s] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int64_t run = toff[blockIdx.x] + sh[threadIdx.x] - acc;
+  for (int q = 0; q < SCAN_PER_THREAD; ++q) {
+    if (base + q < n) out[base + q] = (TO)run;
+    run += v[q];
+  }
+}
+
+template <class TO>
+__global__ void k_scan_total(const int64_t* toff, int64_t ntiles, int64_t n, TO* out) {
+  out[n] = (TO)toff[ntiles];
+}
+
+// out[0..n] exclusive prefix of in[0..n-1] (out[n] = total); toff scratch
+template <class TI, class TO>
+static int64_t scan_impl(const TI* in, TO* out, int64_t n, hipStream_t s) {
+  if (n == 0) {
+    TO z = 0;
+    HBGS_HIP(hipMemcpyAsync(out, &z, sizeof(TO), hipMemcpyHostToDevice, s));
+    HBGS_HIP(hipStreamSynchronize(s));
+    return 0;
+  }
+  int64_t nt = (n + SCAN_TILE - 1) / SCAN_TILE;
+  Tmp<int64_t> tsum(nt), toff(nt + 1);
+  k_tile_sums<TI><<<(unsigned)nt, BLK, 0, s>>>(in, n, tsum.p);
+  HBGS_HIP(hipGetLastError());
+  if (nt == 1) {
+    int64_t h[2] = {0, 0};
+    HBGS_HIP(hipMemcpyAsync(&h[1], tsum.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HBGS_HIP(hipStreamSynchronize(s));
+    HBGS_HIP(hipMemcpyAsync(toff.p, h, 2 * sizeof(int64_t), hipMemcpyHostToDevice, s));
+  } else {
+    scan_impl<int64_t, int64_t>(tsum.p, toff.p, nt, s);
+  }
+  k_tile_scan<TI, TO><<<(unsigned)nt, BLK, 0, s>>>(in, n, toff.p, out);
+  HBGS_HIP(hipGetLastError());
+  k_scan_total<TO><<<1, 1, 0, s>>>(toff.p, nt, n, out);
+  HBGS_HIP(hipGetLastError());
+  int64_t total = 0;
+  HBGS_HIP(hipMemcpyAsync(&total, toff.p + nt, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  return total;
+}
+
+int64_t scan_i32_to_i64(const int* in, int64_t* out, int64_t n, hipStream_t s) {
+  return scan_impl<int, int64_t>(in, out, n, s);
+}
+int64_t scan_i64(const int64_t* in, int64_t* out, int64_t n, hipStream_t s) {
+  return scan_impl<int64_t, int64_t>(in, out, n, s);
+}
+int64_t counts_to_rowptr(const int* counts, int* rp, int n, hipStream_t s) {
+  return scan_impl<int, int>(counts, rp, n, s);
+}
+
+// --------------------------------------------------------------- validate
+// flags bit 0: bad row pointers, 1: column out of range, 2: unsorted or
+// duplicate columns, 3: missing or zero diagonal, 4: field id out of range,
+// 5: non-finite value
+__global__ void k_validate(int n, int64_t nnz, const int* rp, const int* ci, const double* v, int nf,
+                           const int* field, int* flags) {
+  GRID_STRIDE(i, n) {
+    int f = 0;
+    int s = rp[i], e = rp[i + 1];
+    if (s < 0 || e < s || (int64_t)e > nnz) {
+      atomicOr(flags, 1);
+      continue;
+    }
+    bool diag = false;
+    for (int k = s; k < e; ++k) {
+      int c = ci[k];
+      if (c < 0 || c >= n) f |= 2;
+      if (k > s && c <= ci[k - 1]) f |= 4;
+      if (c == i && v[k] != 0.0) diag = true;
+      if (!isfinite(v[k])) f |= 32;
+    }
+    if (!diag) f |= 8;
+    if (field[i] < 0 || field[i] >= nf) f |= 16;
+    if (f) atomicOr(flags, f);
+  }
+}
+
+void validate(int n, int64_t nnz, const int* rp, const int* ci, const double* v, int nf, const int* field,
+              int* flags, hipStream_t s) {
+  k_validate<<<grid_for(n, BLK, 65536), BLK, 0, s>>>(n, nnz, rp, ci, v, nf, field, flags);
+  HBGS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ permutation
+__global__ void k_field_hist(int n, const int* field, int nf, int* counts) {
+  __shared__ int sh[HBGS_MAX_FIELDS];
+  if (threadIdx.x < HBGS_MAX_FIELDS) sh[threadIdx.x] = 0;
+  __syncthreads();
+  GRID_STRIDE(i, n) atomicAdd(&sh[field[i]], 1);
+  __syncthreads();
+  if ((int)threadIdx.x < nf) atomicAdd(&counts[threadIdx.x], sh[threadIdx.x]);
+}
+
+void field_histogram(int n, const int* field, int nf, int* counts, hipStream_t s) {
+  HBGS_HIP(hipMemsetAsync(counts, 0, nf * sizeof(int), s));
+  k_field_hist<<<grid_for(n, BLK, 4096), BLK, 0, s>>>(n, field, nf, counts);
+  HBGS_HIP(hipGetLastError());
+}
+
+__global__ void k_flag_field(int n, const int* field, int f, int* flag) {
+  GRID_STRIDE(i, n) flag[i] = field[i] == f ? 1 : 0;
+}
+
+__global__ void k_perm_from_rank(int n, const int* field, int f, int lo, const int64_t* rank, int* perm) {
+  GRID_STRIDE(i, n) if (field[i] == f) perm[i] = lo + (int)rank[i];
+}
+
+void field_ranks_all(int n, const int* field, int nf, const int* f_lo_host, int* perm, hipStream_t s) {
+  Tmp<int> flag(n);
+  Tmp<int64_t> rank(n + 1);
+  for (int f = 0; f < nf; ++f) {
+    k_flag_field<<<grid_for(n, BLK), BLK, 0, s>>>(n, field, f, flag.p);
+    HBGS_HIP(hipGetLastError());
+    scan_i32_to_i64(flag.p, rank.p, n, s);
+    k_perm_from_rank<<<grid_for(n, BLK), BLK, 0, s>>>(n, field, f, f_lo_host[f], rank.p, perm);
+    HBGS_HIP(hipGetLastError());
+  }
+}
+
+__global__ void k_invert_perm(int n, const int* perm, int* iperm) {
+  GRID_STRIDE(i, n) iperm[perm[i]] = (int)i;
+}
+void invert_perm(int n, const int* perm, int* iperm, hipStream_t s) {
+  k_invert_perm<<<grid_for(n, BLK), BLK, 0, s>>>(n, perm, iperm);
+  HBGS_HIP(hipGetLastError());
+}
+
+__global__ void k_perm_len(int n, const int* rp, const int* perm, int* len) {
+  GRID_STRIDE(i, n) len[perm[i]] = rp[i + 1] - rp[i];
+}
+void permuted_lengths(int n, const int* rp, const int* perm, int* len, hipStream_t s) {
+  k_perm_len<<<grid_for(n, BLK), BLK, 0, s>>>(n, rp, perm, len);
+  HBGS_HIP(hipGetLastError());
+}
+
+// row p of P A P^T: old row iperm[p] with columns mapped and re-sorted
+// (insertion sort carrying value and source position)
+__global__ void k_permute_fill(int n, const int* rp, const int* ci, const double* v, const int* perm,
+                               const int* iperm, const int* rp_p, int* ci_p, double* v_p, int* pos_p) {
+  GRID_STRIDE(p, n) {
+    int i = iperm[p];
+    int s = rp[i], e = rp[i + 1], o = rp_p[p];
+    for (int k = s; k < e; ++k) {
+      int c = perm[ci[k]];
+      double x = v[k];
+      int src = k;
+      int q = o + (k - s) - 1;
+      while (q >= o && ci_p[q] > c) {
+        ci_p[q + 1] = ci_p[q];
+        v_p[q + 1] = v_p[q];
+        pos_p[q + 1] = pos_p[q];
+        --q;
+      }
+      ci_p[q + 1] = c;
+      v_p[q + 1] = x;
+      pos_p[q + 1] = src;
+    }
+  }
+}
+
+// pos_p[q] holds the source entry of permuted entry q; invert it
+__global__ void k_invert_pos(int64_t nnz, int* pos_p, int* tmp) {
+  GRID_STRIDE(q, nnz) tmp[pos_p[q]] = (int)q;
+}
+
+void permute_fill(int n, const int* rp, const int* ci, const double* v, const int* perm, const int* iperm,
+                  const int* rp_p, int* ci_p, double* v_p, int* pos_p, hipStream_t s) {
+  k_permute_fill<<<grid_for(n, BLK), BLK, 0, s>>>(n, rp, ci, v, perm, iperm, rp_p, ci_p, v_p, pos_p);
+  HBGS_HIP(hipGetLastError());
+}
+
+__global__ void k_scatter_values(int64_t nnz, const double* v, const int* pos, double* v_p) {
+  GRID_STRIDE(k, nnz) v_p[pos[k]] = v[k];
+}
+void scatter_values(int64_t nnz, const double* v, const int* pos, double* v_p, hipStream_t s) {
+  k_scatter_values<<<grid_for(nnz, BLK), BLK, 0, s>>>(nnz, v, pos, v_p);
+  HBGS_HIP(hipGetLastError());
+}
+
+// --------------------------------------------------------------- transpose
+__global__ void k_col_count(int64_t nnz, const int* ci, int* cnt) {
+  GRID_STRIDE(k, nnz) atomicAdd(&cnt[ci[k]], 1);
+}
+__global__ void k_transpose_scatter(int n, const int* rp, const int* ci, const double* v, int* cursor,
+                                    int* tci, double* tv) {
+  GRID_STRIDE(i, n) {
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      int q = atomicAdd(&cursor[ci[k]], 1);
+      tci[q] = (int)i;
+      if (v) tv[q] = v[k];
+    }
+  }
+}
+// sort each row by column (entries are distinct, so the result is unique)
+__global__ void k_sort_rows(int n, const int* rp, int* ci, double* v) {
+  GRID_STRIDE(i, n) {
+    int s = rp[i], e = rp[i + 1];
+    for (int k = s + 1; k < e; ++k) {
+      int c = ci[k];
+      double x = v ? v[k] : 0.0;
+      int q = k - 1;
+      while (q >= s && ci[q] > c) {
+        ci[q + 1] = ci[q];
+        if (v) v[q + 1] = v[q];
+        --q;
+      }
+      ci[q + 1] = c;
+      if (v) v[q + 1] = x;
+    }
+  }
+}
+
+void sort_rows(const DCsr& a, hipStream_t s) {
+  k_sort_rows<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v);
+  HBGS_HIP(hipGetLastError());
+}
+
+void transpose(const DCsr& a, DCsr& t, hipStream_t s) {
+  t.n = a.m;
+  t.m = a.n;
+  t.nnz = a.nnz;
+  Tmp<int> cnt(a.m);
+  HBGS_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int) * a.m, s));
+  k_col_count<<<grid_for(a.nnz, BLK), BLK, 0, s>>>(a.nnz, a.ci, cnt.p);
+  HBGS_HIP(hipGetLastError());
+  counts_to_rowptr(cnt.p, t.rp, a.m, s);
+  HBGS_HIP(hipMemcpyAsync(cnt.p, t.rp, sizeof(int) * a.m, hipMemcpyDeviceToDevice, s));
+  k_transpose_scatter<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v, cnt.p, t.ci, t.v);
+  HBGS_HIP(hipGetLastError());
+  sort_rows(t, s);
+  HBGS_HIP(hipStreamSynchronize(s));
+}
+
+// ----------------------------------------------------------- block extract
+__global__ void k_block_count(int r0, int r1, const int* rp, const int* ci, int c0, int c1, int* cnt) {
+  GRID_STRIDE(t, r1 - r0) {
+    int i = r0 + (int)t, c = 0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) c += (ci[k] >= c0 && ci[k] < c1) ? 1 : 0;
+    cnt[t] = c;
+  }
+}
+__global__ void k_block_fill(int r0, int r1, const int* rp, const int* ci, const double* v, int c0, int c1,
+                             int coff, const int* rpo, int* cio, double* vo) {
+  GRID_STRIDE(t, r1 - r0) {
+    int i = r0 + (int)t, q = rpo[t];
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] >= c0 && ci[k] < c1) {
+        cio[q] = ci[k] - coff;
+        vo[q] = v[k];
+        ++q;
+      }
+  }
+}
+void block_count(const DCsr& a, int r0, int r1, int c0, int c1, int* cnt, hipStream_t s) {
+  k_block_count<<<grid_for(r1 - r0, BLK), BLK, 0, s>>>(r0, r1, a.rp, a.ci, c0, c1, cnt);
+  HBGS_HIP(hipGetLastError());
+}
+void block_fill(const DCsr& a, int r0, int r1, int c0, int c1, int coff, const int* rp_out, int* ci_out,
+                double* v_out, hipStream_t s) {
+  k_block_fill<<<grid_for(r1 - r0, BLK), BLK, 0, s>>>(r0, r1, a.rp, a.ci, a.v, c0, c1, coff, rp_out, ci_out,
+                                                         v_out);
+  HBGS_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- strength
+__global__ void k_diagonal(int n, const int* rp, const int* ci, const double* v, double* d, int* missing) {
+  GRID_STRIDE(i, n) {
+    double x = 0.0;
+    bool found = false;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] == i) {
+        x = v[k];
+        found = true;
+      }
+    d[i] = x;
+    if (!found || x == 0.0) atomicOr(missing, 1);
+  }
+}
+void diagonal(const DCsr& a, double* d, int* missing, hipStream_t s) {
+  k_diagonal<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v, d, missing);
+  HBGS_HIP(hipGetLastError());
+}
+
+// (i,j) strong: a_ij*a_ij >= (theta^2 |a_ii|) |a_jj|, or the same test on the
+// transposed entry (j,i); rows with no off-diagonal entry are excluded
+__global__ void k_strength(int n, const int* rp, const int* ci, const double* v, const double* d, double th2,
+                           char* strong, char* excluded) {
+  GRID_STRIDE(i, n) {
+    bool offd = false;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      int j = ci[k];
+      if (j == i) {
+        strong[k] = 0;
+        continue;
+      }
+      offd = true;
+      bool st = v[k] * v[k] >= (th2 * fabs(d[i])) * fabs(d[j]);
+      if (!st) {
+        int lo = rp[j], hi = rp[j + 1] - 1;
+        while (lo <= hi) {
+          int mid = (lo + hi) >> 1;
+          int cm = ci[mid];
+          if (cm == i) {
+            st = v[mid] * v[mid] >= (th2 * fabs(d[j])) * fabs(d[i]);
+            break;
+          }
+          if (cm < i)
+            lo = mid + 1;
+          else
+            hi = mid - 1;
+        }
+      }
+      strong[k] = st ? 1 : 0;
+    }
+    excluded[i] = offd ? 0 : 1;
+  }
+}
+void strength(const DCsr& a, const double* d, double theta, char* strong, char* excluded, hipStream_t s) {
+  k_strength<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v, d, theta * theta, strong, excluded);
+  HBGS_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- MIS-2
+// Synchronous rounds: an undecided row becomes a root when its key is the
+// largest among the undecided rows within strength distance 2 (the maxima
+// propagate through all rows, decided or not); rows within distance 2 of a
+// root leave.  This yields the greedy maximal distance-2 independent set
+// taken in decreasing key order.
+__global__ void k_mis2_init(int n, const char* excluded, char* state) {
+  GRID_STRIDE(i, n) state[i] = excluded[i] ? 3 : 0;
+}
+__global__ void k_mis2_max1(int n, const int* rp, const int* ci, const char* strong, uint64_t salt,
+                            const char* state, uint64_t* m1) {
+  GRID_STRIDE(i, n) {
+    uint64_t m = state[i] == 0 ? agg_key((int)i, salt) : 0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      if (!strong[k]) continue;
+      int j = ci[k];
+      if (state[j] == 0) {
+        uint64_t kj = agg_key(j, salt);
+        m = kj > m ? kj : m;
+      }
+    }
+    m1[i] = m;
+  }
+}
+__global__ void k_mis2_max2(int n, const int* rp, const int* ci, const char* strong, uint64_t salt,
+                            const uint64_t* m1, char* state) {
+  GRID_STRIDE(i, n) {
+    if (state[i] != 0) continue;
+    uint64_t m = m1[i];
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (strong[k]) m = m1[ci[k]] > m ? m1[ci[k]] : m;
+    if (m == agg_key((int)i, salt)) state[i] = 1;
+  }
+}
+__global__ void k_mis2_near1(int n, const int* rp, const int* ci, const char* strong, const char* state,
+                             char* r1) {
+  GRID_STRIDE(i, n) {
+    char r = state[i] == 1;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (strong[k] && state[ci[k]] == 1) r = 1;
+    r1[i] = r;
+  }
+}
+__global__ void k_mis2_near2(int n, const int* rp, const int* ci, const char* strong, const char* r1,
+                             char* state, int* undecided) {
+  int local = 0;
+  GRID_STRIDE(i, n) {
+    if (state[i] != 0) continue;
+    bool out = r1[i];
+    for (int k = rp[i]; k < rp[i + 1] && !out; ++k)
+      if (strong[k] && r1[ci[k]]) out = true;
+    if (out)
+      state[i] = 2;
+    else
+      ++local;
+  }
+  if (local) atomicAdd(undecided, local);
+}
+
+void mis2_init(int n, const char* excluded, char* state, hipStream_t s) {
+  k_mis2_init<<<grid_for(n, BLK), BLK, 0, s>>>(n, excluded, state);
+  HBGS_HIP(hipGetLastError());
+}
+
+void mis2_round(const DCsr& a, const char* strong, uint64_t salt, char* state, uint64_t* m1, char* r1,
+                int* undecided, hipStream_t s) {
+  unsigned g = grid_for(a.n, BLK);
+  k_mis2_max1<<<g, BLK, 0, s>>>(a.n, a.rp, a.ci, strong, salt, state, m1);
+  k_mis2_max2<<<g, BLK, 0, s>>>(a.n, a.rp, a.ci, strong, salt, m1, state);
+  k_mis2_near1<<<g, BLK, 0, s>>>(a.n, a.rp, a.ci, strong, state, r1);
+  HBGS_HIP(hipMemsetAsync(undecided, 0, sizeof(int), s));
+  k_mis2_near2<<<g, BLK, 0, s>>>(a.n, a.rp, a.ci, strong, r1, state, undecided);
+  HBGS_HIP(hipGetLastError());
+}
+
+__global__ void k_agg_roots(int n, const char* state, int* flag) {
+  GRID_STRIDE(i, n) flag[i] = state[i] == 1 ? 1 : 0;
+}
+void agg_roots(int n, const char* state, int* flag, hipStream_t s) {
+  k_agg_roots<<<grid_for(n, BLK), BLK, 0, s>>>(n, state, flag);
+  HBGS_HIP(hipGetLastError());
+}
+
+// phase 1: a row next to a root joins it (the root is unique: roots are at
+// least 3 apart); phase 2: other rows join the phase-1 neighbour of largest
+// key; rows left over are flagged for phase 3
+__global__ void k_agg_phase1(int n, const int* rp, const int* ci, const char* strong, const char* state,
+                             const int64_t* root_rank, int* p1) {
+  GRID_STRIDE(i, n) {
+    int a = -1;
+    if (state[i] == 1) {
+      a = (int)root_rank[i];
+    } else if (state[i] != 3) {
+      for (int k = rp[i]; k < rp[i + 1]; ++k)
+        if (strong[k] && state[ci[k]] == 1) a = (int)root_rank[ci[k]];
+    }
+    p1[i] = a;
+  }
+}
+__global__ void k_agg_phase2(int n, const int* rp, const int* ci, const char* strong, uint64_t salt,
+                             const char* state, const int* p1, int* agg, int* single_flag) {
+  GRID_STRIDE(i, n) {
+    int a = p1[i];
+    int single = 0;
+    if (state[i] != 3 && a < 0) {
+      uint64_t best = 0;
+      int besta = -1;
+      for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        if (!strong[k]) continue;
+        int u = ci[k];
+        if (p1[u] >= 0 && state[u] != 1) {
+          uint64_t ku = agg_key(u, salt);
+          if (besta < 0 || ku > best) {
+            best = ku;
+            besta = p1[u];
+          }
+        }
+      }
+      a = besta;
+      single = besta < 0 ? 1 : 0;
+    }
+    agg[i] = a;
+    single_flag[i] = single;
+  }
+}
+__global__ void k_agg_phase3(int n, const int* single_flag, const int64_t* single_rank, int nroot, int* agg) {
+  GRID_STRIDE(i, n) if (single_flag[i]) agg[i] = nroot + (int)single_rank[i];
+}
+
+void agg_phase12(const DCsr& a, const char* strong, uint64_t salt, const char* state, const int64_t* root_rank,
+                 int* agg, int* single_flag, hipStream_t s) {
+  Tmp<int> p1(a.n);
+  unsigned g = grid_for(a.n, BLK);
+  k_agg_phase1<<<g, BLK, 0, s>>>(a.n, a.rp, a.ci, strong, state, root_rank, p1.p);
+  k_agg_phase2<<<g, BLK, 0, s>>>(a.n, a.rp, a.ci, strong, salt, state, p1.p, agg, single_flag);
+  HBGS_HIP(hipGetLastError());
+  HBGS_HIP(hipStreamSynchronize(s));
+}
+void agg_phase3(int n, const int* single_flag, const int64_t* single_rank, int nroot, int* agg, hipStream_t s) {
+  k_agg_phase3<<<grid_for(n, BLK), BLK, 0, s>>>(n, single_flag, single_rank, nroot, agg);
+  HBGS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ filter
+// A_F: strong off-diagonal entries kept, dropped entries added to the
+// diagonal in ascending column order; D_abs = sum |A_F| along the row
+__global__ void k_filter_count(int n, const int* rp, const int* ci, const char* strong, int* cnt) {
+  GRID_STRIDE(i, n) {
+    int c = 0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) c += (ci[k] == i || strong[k]) ? 1 : 0;
+    cnt[i] = c;
+  }
+}
+__global__ void k_filter_fill(int n, const int* rp, const int* ci, const double* v, const char* strong,
+                              const int* rpf, int* cif, double* vf, double* dabs) {
+  GRID_STRIDE(i, n) {
+    double d = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] == i) d = v[k];
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] != i && !strong[k]) d += v[k];
+    int q = rpf[i];
+    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      if (ci[k] == i) {
+        cif[q] = (int)i;
+        vf[q] = d;
+        ++q;
+      } else if (strong[k]) {
+        cif[q] = ci[k];
+        vf[q] = v[k];
+        ++q;
+      }
+    }
+    double sa = 0.0;
+    for (int k = rpf[i]; k < q; ++k) sa += fabs(vf[k]);
+    dabs[i] = sa;
+  }
+}
+void filter_count(const DCsr& a, const char* strong, int* cnt, hipStream_t s) {
+  k_filter_count<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, strong, cnt);
+  HBGS_HIP(hipGetLastError());
+}
+void filter_fill(const DCsr& a, const char* strong, const int* rp_f, int* ci_f, double* v_f, double* dabs,
+                 hipStream_t s) {
+  k_filter_fill<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v, strong, rp_f, ci_f, v_f, dabs);
+  HBGS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------ power method
+__global__ void k_pw_init(int n, uint64_t salt, double* w) {
+  GRID_STRIDE(i, n) {
+    uint64_t h = splitmix64((uint64_t)(uint32_t)i ^ salt);
+    w[i] = 2.0 * ((double)(h >> 11) * 0x1.0p-53) - 1.0;
+  }
+}
+// y = D^-1 B w, row sums in ascending column order; track max |y|
+__global__ void k_pw_apply(int n, const int* rp, const int* ci, const double* v, const double* d, const double* w,
+                           double* y, unsigned long long* amax) {
+  __shared__ unsigned long long sh[BLK];
+  unsigned long long m = 0;
+  GRID_STRIDE(i, n) {
+    double s = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) s += v[k] * w[ci[k]];
+    double yi = s / d[i];
+    y[i] = yi;
+    unsigned long long b = (unsigned long long)__double_as_longlong(fabs(yi));
+    m = b > m ? b : m;
+  }
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int st = BLK / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] = sh[threadIdx.x] > sh[threadIdx.x + st] ? sh[threadIdx.x]
+                                                                                          : sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && amax) atomicMax(amax, sh[0]);
+}
+// w = y * 2^-e with max|y| = f * 2^e, f in [0.5, 1)
+__global__ void k_pw_scale(int n, const double* y, const unsigned long long* amax, double* w) {
+  double mx = __longlong_as_double((long long)*amax);
+  int e = 0;
+  if (mx > 0.0) frexp(mx, &e);
+  GRID_STRIDE(i, n) w[i] = mx > 0.0 ? ldexp(y[i], -e) : 0.0;
+}
+// fixed-association sum: consecutive runs of 256 terms summed in order
+__global__ void k_chunk_dot(int64_t n, const double* x, const double* y, double* part) {
+  GRID_STRIDE(c, (n + 255) / 256) {
+    double s = 0.0;
+    int64_t e = (c + 1) * 256 < n ? (c + 1) * 256 : n;
+    for (int64_t i = c * 256; i < e; ++i) s += x[i] * y[i];
+    part[c] = s;
+  }
+}
+__global__ void k_chunk_sum(int64_t n, const double* x, double* part) {
+  GRID_STRIDE(c, (n + 255) / 256) {
+    double s = 0.0;
+    int64_t e = (c + 1) * 256 < n ? (c + 1) * 256 : n;
+    for (int64_t i = c * 256; i < e; ++i) s += x[i];
+    part[c] = s;
+  }
+}
+
+static double tree_dot(int64_t n, const double* x, const double* y, double* buf_a, double* buf_b,
+                       hipStream_t s) {
+  if (n == 0) return 0.0;
+  int64_t m = (n + 255) / 256;
+  k_chunk_dot<<<grid_for(m, 64), 64, 0, s>>>(n, x, y, buf_a);
+  HBGS_HIP(hipGetLastError());
+  double* cur = buf_a;
+  double* nxt = buf_b;
+  while (m > 1) {
+    int64_t m2 = (m + 255) / 256;
+    k_chunk_sum<<<grid_for(m2, 64), 64, 0, s>>>(m, cur, nxt);
+    HBGS_HIP(hipGetLastError());
+    std::swap(cur, nxt);
+    m = m2;
+  }
+  double r = 0.0;
+  HBGS_HIP(hipMemcpyAsync(&r, cur, sizeof(double), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  return r;
+}
+
+double power_estimate(const DCsr& b, const double* d, int iters, uint64_t salt, hipStream_t s) {
+  const int n = b.n;
+  Tmp<double> w(n), y(n), pa((n + 255) / 256 + 1), pb((n + 255) / 256 + 1);
+  Tmp<unsigned long long> amax(1);
+  unsigned g = grid_for(n, BLK);
+  k_pw_init<<<g, BLK, 0, s>>>(n, salt, w.p);
+  HBGS_HIP(hipGetLastError());
+  for (int it = 0; it < iters; ++it) {
+    HBGS_HIP(hipMemsetAsync(amax.p, 0, sizeof(unsigned long long), s));
+    k_pw_apply<<<g, BLK, 0, s>>>(n, b.rp, b.ci, b.v, d, w.p, y.p, amax.p);
+    k_pw_scale<<<g, BLK, 0, s>>>(n, y.p, amax.p, w.p);
+    HBGS_HIP(hipGetLastError());
+  }
+  unsigned long long mx = 0;
+  HBGS_HIP(hipMemcpyAsync(&mx, amax.p, sizeof(mx), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  if (iters > 0) {
+    double m = 0.0;
+    std::memcpy(&m, &mx, sizeof(m));
+    if (m == 0.0) return 0.0;
+  }
+  k_pw_apply<<<g, BLK, 0, s>>>(n, b.rp, b.ci, b.v, d, w.p, y.p, nullptr);
+  HBGS_HIP(hipGetLastError());
+  double wy = tree_dot(n, w.p, y.p, pa.p, pb.p, s);
+  double ww = tree_dot(n, w.p, w.p, pa.p, pb.p, s);
+  return wy / ww;
+}
+
+// ------------------------------------------------------ smoothed prolongator
+// Row i of P = P_tent - omega D_abs^-1 A_F P_tent: its columns are the
+// aggregates met along row i of A_F (ascending); entry c is
+// [agg(i)==c] - (omega / D_abs_i) * sum_{k: agg(k)==c} a_F(i,k).
+__global__ void k_psmooth_count(int n, const int* rp, const int* ci, const int* agg, int* cnt) {
+  GRID_STRIDE(i, n) {
+    int c = 0;
+    if (agg[i] >= 0) {
+      int prev = -1;
+      for (;;) {
+        int next = INT32_MAX;
+        for (int k = rp[i]; k < rp[i + 1]; ++k) {
+          int a = agg[ci[k]];
+          if (a > prev && a < next) next = a;
+        }
+        if (next == INT32_MAX) break;
+        ++c;
+        prev = next;
+      }
+    }
+    cnt[i] = c;
+  }
+}
+__global__ void k_psmooth_fill(int n, const int* rp, const int* ci, const double* v, const int* agg,
+                               const double* dabs, double omega, const int* rpp, int* cip, double* vp) {
+  GRID_STRIDE(i, n) {
+    if (agg[i] < 0) continue;
+    double q = omega / dabs[i];
+    int o = rpp[i];
+    int prev = -1;
+    for (;;) {
+      int next = INT32_MAX;
+      for (int k = rp[i]; k < rp[i + 1]; ++k) {
+        int a = agg[ci[k]];
+        if (a > prev && a < next) next = a;
+      }
+      if (next == INT32_MAX) break;
+      double sum = 0.0;
+      for (int k = rp[i]; k < rp[i + 1]; ++k)
+        if (agg[ci[k]] == next) sum += v[k];
+      double t = agg[i] == next ? 1.0 : 0.0;
+      cip[o] = next;
+      vp[o] = t - q * sum;
+      ++o;
+      prev = next;
+    }
+  }
+}
+void psmooth_count(const DCsr& af, const int* agg, int* cnt, hipStream_t s) {
+  k_psmooth_count<<<grid_for(af.n, BLK), BLK, 0, s>>>(af.n, af.rp, af.ci, agg, cnt);
+  HBGS_HIP(hipGetLastError());
+}
+void psmooth_fill(const DCsr& af, const int* agg, const double* dabs, double omega, const int* rp_p, int* ci_p,
+                  double* v_p, hipStream_t s) {
+  k_psmooth_fill<<<grid_for(af.n, BLK), BLK, 0, s>>>(af.n, af.rp, af.ci, af.v, agg, dabs, omega, rp_p, ci_p,
+                                                       v_p);
+  HBGS_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ SpGEMM
+// C = A B, Gustavson row by row.  Each row of C owns an open-addressing
+// table (in a scratch buffer) whose slots accumulate the products a_ik b_kj
+// in the order they are generated, i.e. ascending k, starting from 0.0; the
+// occupied slots are then written out and sorted by column.  The pattern is
+// structural (entries that cancel to zero are kept).
+__global__ void k_spgemm_ub(int n, const int* arp, const int* aci, const int* brp, int64_t* ub) {
+  GRID_STRIDE(i, n) {
+    int64_t u = 0;
+    for (int k = arp[i]; k < arp[i + 1]; ++k) u += brp[aci[k] + 1] - brp[aci[k]];
+    ub[i] = u;
+  }
+}
+__device__ __forceinline__ int64_t table_size(int64_t ub) {
+  if (ub == 0) return 0;
+  int64_t t = 16;
+  while (t < 2 * ub) t <<= 1;
+  return t;
+}
+__global__ void k_spgemm_tsize(int n, const int64_t* ub, int64_t* ts) {
+  GRID_STRIDE(i, n) ts[i] = table_size(ub[i]);
+}
+__device__ __forceinline__ uint32_t hslot(int c, uint32_t mask) { return ((uint32_t)c * 2654435761u) & mask; }
+
+__global__ void k_spgemm_symbolic(int r0, int r1, const int* arp, const int* aci, const int* brp, const int* bci,
+                                  const int64_t* toff, int64_t tbase, int* keys, int* cnt) {
+  GRID_STRIDE(t, r1 - r0) {
+    int i = r0 + (int)t;
+    int64_t ts = toff[i + 1] - toff[i];
+    int* tk = keys + (toff[i] - tbase);
+    for (int64_t q = 0; q < ts; ++q) tk[q] = -1;
+    int u = 0;
+    uint32_t mask = (uint32_t)(ts - 1);
+    for (int k = arp[i]; k < arp[i + 1]; ++k) {
+      int kk = aci[k];
+      for (int q = brp[kk]; q < brp[kk + 1]; ++q) {
+        int c = bci[q];
+        uint32_t h = hslot(c, mask);
+        while (tk[h] != -1 && tk[h] != c) h = (h + 1) & mask;
+        if (tk[h] == -1) {
+          tk[h] = c;
+          ++u;
+        }
+      }
+    }
+    cnt[i] = u;
+  }
+}
+__global__ void k_spgemm_numeric(int r0, int r1, const int* arp, const int* aci, const double* av, const int* brp,
+                                 const int* bci, const double* bv, const int64_t* toff, int64_t tbase, int* keys,
+                                 double* vals, const int* crp, int* cci, double* cv) {
+  GRID_STRIDE(t, r1 - r0) {
+    int i = r0 + (int)t;
+    int64_t ts = toff[i + 1] - toff[i];
+    int* tk = keys + (toff[i] - tbase);
+    double* tv = vals + (toff[i] - tbase);
+    for (int64_t q = 0; q < ts; ++q) {
+      tk[q] = -1;
+      tv[q] = 0.0;
+    }
+    uint32_t mask = (uint32_t)(ts - 1);
+    for (int k = arp[i]; k < arp[i + 1]; ++k) {
+      int kk = aci[k];
+      double a = av[k];
+      for (int q = brp[kk]; q < brp[kk + 1]; ++q) {
+        int c = bci[q];
+        uint32_t h = hslot(c, mask);
+        while (tk[h] != -1 && tk[h] != c) h = (h + 1) & mask;
+        tk[h] = c;
+        tv[h] += a * bv[q];
+      }
+    }
+    int o = crp[i], e = crp[i + 1];
+    for (int64_t q = 0; q < ts; ++q)
+      if (tk[q] != -1) {
+        cci[o] = tk[q];
+        cv[o] = tv[q];
+        ++o;
+      }
+    int s = crp[i];
+    for (int k = s + 1; k < e; ++k) {
+      int c = cci[k];
+      double x = cv[k];
+      int q = k - 1;
+      while (q >= s && cci[q] > c) {
+        cci[q + 1] = cci[q];
+        cv[q + 1] = cv[q];
+        --q;
+      }
+      cci[q + 1] = c;
+      cv[q + 1] = x;
+    }
+  }
+}
+
+void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
+  const int n = a.n;
+  c.n = n;
+  c.m = b.m;
+  Tmp<int64_t> ub(n), ts(n), toff(n + 1);
+  k_spgemm_ub<<<grid_for(n, BLK), BLK, 0, s>>>(n, a.rp, a.ci, b.rp, ub.p);
+  k_spgemm_tsize<<<grid_for(n, BLK), BLK, 0, s>>>(n, ub.p, ts.p);
+  HBGS_HIP(hipGetLastError());
+  scan_i64(ts.p, toff.p, n, s);
+  std::vector<int64_t> h_off(n + 1);
+  HBGS_HIP(hipMemcpyAsync(h_off.data(), toff.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  // batches of rows whose tables fit the scratch budget
+  const int64_t budget = std::max<int64_t>(int64_t(64) << 20, (int64_t)1 << 26);  // table slots
+  std::vector<int> cuts{0};
+  int64_t maxbatch = 0;
+  while (cuts.back() < n) {
+    int r0 = cuts.back();
+    int r1 = (int)(std::upper_bound(h_off.begin() + r0 + 1, h_off.end(), h_off[r0] + budget) - h_off.begin()) - 1;
+    if (r1 <= r0) r1 = r0 + 1;
+    if (r1 > n) r1 = n;
+    maxbatch = std::max(maxbatch, h_off[r1] - h_off[r0]);
+    cuts.push_back(r1);
+  }
+  Tmp<int> keys(maxbatch);
+  Tmp<int> cnt(n);
+  for (size_t q = 0; q + 1 < cuts.size(); ++q) {
+    int r0 = cuts[q], r1 = cuts[q + 1];
+    k_spgemm_symbolic<<<grid_for(r1 - r0, 64), 64, 0, s>>>(r0, r1, a.rp, a.ci, b.rp, b.ci, toff.p, h_off[r0],
+                                                           keys.p, cnt.p);
+    HBGS_HIP(hipGetLastError());
+  }
+  c.rp = pool.make<int>(n + 1);
+  c.nnz = counts_to_rowptr(cnt.p, c.rp, n, s);
+  c.ci = pool.make<int>(c.nnz);
+  c.v = pool.make<double>(c.nnz);
+  Tmp<double> vals(maxbatch);
+  for (size_t q = 0; q + 1 < cuts.size(); ++q) {
+    int r0 = cuts[q], r1 = cuts[q + 1];
+    k_spgemm_numeric<<<grid_for(r1 - r0, 64), 64, 0, s>>>(r0, r1, a.rp, a.ci, a.v, b.rp, b.ci, b.v, toff.p,
+                                                          h_off[r0], keys.p, vals.p, c.rp, c.ci, c.v);
+    HBGS_HIP(hipGetLastError());
+  }
+  HBGS_HIP(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------- dense coarsest LU
+__global__ void k_dense_fill(int n, const int* rp, const int* ci, const double* v, double* m) {
+  GRID_STRIDE(i, n) {
+    for (int j = 0; j < n; ++j) m[i * (int64_t)n + j] = 0.0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) m[i * (int64_t)n + ci[k]] = v[k];
+  }
+}
+// step k: pivot = first row with maximal |a_ik| (i >= k); swap rows; multipliers
+__global__ void k_lu_pivot(int n, int k, double* m, int* piv, int* singular) {
+  __shared__ double sv[BLK];
+  __shared__ int si[BLK];
+  double best = -1.0;
+  int bi = n;
+  for (int i = k + threadIdx.x; i < n; i += BLK) {
+    double a = fabs(m[(int64_t)i * n + k]);
+    if (a > best) {
+      best = a;
+      bi = i;
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int st = BLK / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      double a = sv[threadIdx.x + st];
+      int ai = si[threadIdx.x + st];
+      if (a > sv[threadIdx.x] || (a == sv[threadIdx.x] && ai < si[threadIdx.x])) {
+        sv[threadIdx.x] = a;
+        si[threadIdx.x] = ai;
+      }
+    }
+    __syncthreads();
+  }
+  int p = si[0];
+  if (threadIdx.x == 0) {
+    piv[k] = p;
+    if (!(sv[0] > 0.0)) *singular = 1;
+  }
+  if (!(sv[0] > 0.0)) return;
+  if (p != k)
+    for (int j = threadIdx.x; j < n; j += BLK) {
+      double t = m[(int64_t)k * n + j];
+      m[(int64_t)k * n + j] = m[(int64_t)p * n + j];
+      m[(int64_t)p * n + j] = t;
+    }
+  __syncthreads();
+  double akk = m[(int64_t)k * n + k];
+  for (int i = k + 1 + threadIdx.x; i < n; i += BLK) m[(int64_t)i * n + k] = m[(int64_t)i * n + k] / akk;
+}
+__global__ void k_lu_update(int n, int k, double* m) {
+  int64_t w = (int64_t)(n - k - 1);
+  GRID_STRIDE(t, w * w) {
+    int i = k + 1 + (int)(t / w), j = k + 1 + (int)(t % w);
+    m[(int64_t)i * n + j] -= m[(int64_t)i * n + k] * m[(int64_t)k * n + j];
+  }
+}
+// column c of A^-1 = U^-1 L^-1 P e_c; pinv[c] = row of P e_c holding the 1
+__global__ void k_lu_inverse(int n, const double* lu, const int* pinv, double* inv) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  int r = pinv[c];
+  for (int i = 0; i < n; ++i) {
+    double y = i == r ? 1.0 : 0.0;
+    if (i > r)
+      for (int j = r; j < i; ++j) y -= lu[(int64_t)i * n + j] * inv[(int64_t)j * n + c];
+    inv[(int64_t)i * n + c] = i < r ? 0.0 : y;
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double y = inv[(int64_t)i * n + c];
+    for (int j = i + 1; j < n; ++j) y -= lu[(int64_t)i * n + j] * inv[(int64_t)j * n + c];
+    inv[(int64_t)i * n + c] = y / lu[(int64_t)i * n + i];
+  }
+}
+
+int dense_inverse(const DCsr& a, double* inv, hipStream_t s) {
+  const int n = a.n;
+  Tmp<double> m((size_t)n * n);
+  Tmp<int> piv(n), sing(1), pinv(n);
+  HBGS_HIP(hipMemsetAsync(sing.p, 0, sizeof(int), s));
+  k_dense_fill<<<grid_for(n, 64), 64, 0, s>>>(n, a.rp, a.ci, a.v, m.p);
+  HBGS_HIP(hipGetLastError());
+  for (int k = 0; k < n; ++k) {
+    k_lu_pivot<<<1, BLK, 0, s>>>(n, k, m.p, piv.p, sing.p);
+    if (k + 1 < n) k_lu_update<<<grid_for((int64_t)(n - k - 1) * (n - k - 1), BLK, 8192), BLK, 0, s>>>(n, k, m.p);
+  }
+  HBGS_HIP(hipGetLastError());
+  int singular = 0;
+  std::vector<int> hp(n);
+  HBGS_HIP(hipMemcpyAsync(&singular, sing.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipMemcpyAsync(hp.data(), piv.p, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  if (singular) return -4;
+  // P e_c: apply the interchanges k <-> piv[k] in order to the identity row ids
+  std::vector<int> rowof(n), where(n);
+  for (int i = 0; i < n; ++i) rowof[i] = i;  // rowof[r] = original index now at position r
+  for (int k = 0; k < n; ++k) std::swap(rowof[k], rowof[hp[k]]);
+  for (int r = 0; r < n; ++r) where[rowof[r]] = r;
+  HBGS_HIP(hipMemcpyAsync(pinv.p, where.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+  k_lu_inverse<<<grid_for(n, 64), 64, 0, s>>>(n, m.p, pinv.p, inv);
+  HBGS_HIP(hipGetLastError());
+  HBGS_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
+// ------------------------------------------------------------------ casts
+__global__ void k_cast_f32(int64_t n, const double* in, float* out) {
+  GRID_STRIDE(i, n) out[i] = (float)in[i];
+}
+void cast_f32(int64_t n, const double* in, float* out, hipStream_t s) {
+  if (n == 0) return;
+  k_cast_f32<<<grid_for(n, BLK), BLK, 0, s>>>(n, in, out);
+  HBGS_HIP(hipGetLastError());
+}
+__global__ void k_reciprocal(int n, const double* d, double* dinv, float* dinvf) {
+  GRID_STRIDE(i, n) {
+    double r = 1.0 / d[i];
+    dinv[i] = r;
+    dinvf[i] = (float)r;
+  }
+}
+void reciprocal(int n, const double* d, double* dinv, float* dinvf, hipStream_t s) {
+  k_reciprocal<<<grid_for(n, BLK), BLK, 0, s>>>(n, d, dinv, dinvf);
+  HBGS_HIP(hipGetLastError());
+}
+
+}  // namespace setup
+}  // namespace hbgs

@@ -1,0 +1,537 @@
+// Solve-phase kernels (gfx950, wave64): everything here is sparse or
+// vector work bound by HBM bandwidth, so no matrix cores are used.
+//
+// CSR kernels process one row per group of LPR lanes (LPR = 1..64 chosen
+// from the mean row length): the value and column streams of consecutive
+// rows are read by consecutive lanes, so a wavefront's loads are coalesced;
+// the partial products are combined with cross-lane shuffles and the row's
+// epilogue (residual, Chebyshev update, transfer accumulation) is fused into
+// the same kernel, so each vector is read and written once per step.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "hbgs_internal.h"
+
+namespace hbgs {
+namespace solve {
+
+constexpr int BLK = 256;
+
+const char* kind_names[K_COUNT] = {
+    "spmv_outer", "spmv_resid", "cheb_pre",  "cheb_post_a", "cheb_post_b", "cheb_other", "resid", "restrict",
+    "prolong",    "coarse",     "couple",    "dot1",        "upd_dot2",    "upd_norm",  "reduce",
+    "givens",     "scale",      "xupdate",   "permute"};
+
+// ---------------------------------------------------------- CSR row engine
+template <class T>
+__device__ __forceinline__ T lanes_sum(T v, int lpr) {
+  for (int off = lpr >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, lpr);
+  return v;
+}
+
+// acc = sum_k v[k] * X(ci[k]) over row `row`, then epi(row, acc)
+template <int LPR, class TV, class TACC, class LoadX, class Epi>
+__global__ __launch_bounds__(BLK) void k_csr(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                             const TV* __restrict__ v, LoadX lx, Epi epi) {
+  const int lane = threadIdx.x & (LPR - 1);
+  const int row = (int)((blockIdx.x * (unsigned)BLK + threadIdx.x) / LPR);
+  if (row >= n) return;
+  const int s = rp[row], e = rp[row + 1];
+  TACC acc = 0;
+  for (int k = s + lane; k < e; k += LPR) acc += (TACC)v[k] * (TACC)lx(ci[k]);
+  if (LPR > 1) acc = lanes_sum<TACC>(acc, LPR);
+  if (lane == 0) epi(row, acc);
+}
+
+template <class TV, class TACC, class LoadX, class Epi>
+static void launch_csr(const DCsr& a, const TV* v, LoadX lx, Epi epi, hipStream_t s) {
+  if (a.n == 0) return;
+  float avg = a.avg_row();
+  int lpr = avg <= 1.5f ? 1 : avg <= 3.f ? 2 : avg <= 6.f ? 4 : avg <= 12.f ? 8 : avg <= 24.f ? 16 : avg <= 48.f ? 32 : 64;
+  unsigned grid = (unsigned)(((int64_t)a.n * lpr + BLK - 1) / BLK);
+#define HBGS_CASE(L) \
+  case L:            \
+    k_csr<L, TV, TACC, LoadX, Epi><<<grid, BLK, 0, s>>>(a.n, a.rp, a.ci, v, lx, epi); break;
+  switch (lpr) {
+    HBGS_CASE(1)
+    HBGS_CASE(2)
+    HBGS_CASE(4)
+    HBGS_CASE(8)
+    HBGS_CASE(16)
+    HBGS_CASE(32)
+    HBGS_CASE(64)
+  }
+#undef HBGS_CASE
+  HBGS_HIP(hipGetLastError());
+}
+
+// operand loaders
+template <class T>
+struct LoadArr {
+  const T* __restrict__ x;
+  __device__ T operator()(int k) const { return x[k]; }
+};
+// zero-guess first Chebyshev direction d0 = (D^-1 b) / theta, formed on the fly
+template <class T>
+struct LoadD0 {
+  const T* __restrict__ dinv;
+  const T* __restrict__ b;
+  T c0;
+  __device__ T operator()(int k) const { return dinv[k] * b[k] * c0; }
+};
+
+// epilogues
+template <class T, class TACC>
+struct EpiStore {
+  T* __restrict__ y;
+  __device__ void operator()(int i, TACC acc) const { y[i] = (T)acc; }
+};
+template <class T, class TACC>
+struct EpiAdd {
+  T* __restrict__ y;
+  __device__ void operator()(int i, TACC acc) const { y[i] = y[i] + (T)acc; }
+};
+template <class T>
+struct EpiResid {
+  const T* __restrict__ b;
+  T* __restrict__ r;
+  __device__ void operator()(int i, T acc) const { r[i] = b[i] - acc; }
+};
+// degree-2 pre-smoothing from zero: x = d0 + c1 d0 + c2 D^-1 (b - A d0)
+template <class T>
+struct EpiChebPre2 {
+  const T* __restrict__ dinv;
+  const T* __restrict__ b;
+  T* __restrict__ x;
+  T c0, c1, c2;
+  __device__ void operator()(int i, T ad) const {
+    T d0 = dinv[i] * b[i] * c0;
+    T r1 = b[i] - ad;
+    T d1 = c1 * d0 + c2 * (dinv[i] * r1);
+    x[i] = d0 + d1;
+  }
+};
+// post-smoothing start from x: r = b - A x, d = D^-1 r / theta
+template <class T>
+struct EpiChebPostA {
+  const T* __restrict__ dinv;
+  const T* __restrict__ b;
+  T* __restrict__ r;
+  T* __restrict__ d;
+  T c0;
+  __device__ void operator()(int i, T ax) const {
+    T ri = b[i] - ax;
+    r[i] = ri;
+    d[i] = dinv[i] * ri * c0;
+  }
+};
+// Chebyshev step: r -= A d; dn = c1 d + c2 D^-1 r; x (+ d if pending) += dn
+template <class T, bool ADD_D, bool KEEP>
+struct EpiChebStep {
+  const T* __restrict__ dinv;
+  const T* __restrict__ d;
+  T* __restrict__ r;
+  T* __restrict__ dn;
+  T* __restrict__ x;
+  T c1, c2;
+  __device__ void operator()(int i, T ad) const {
+    T ri = r[i] - ad;
+    T di = c1 * d[i] + c2 * (dinv[i] * ri);
+    T xi = ADD_D ? x[i] + d[i] : x[i];
+    x[i] = xi + di;
+    if (KEEP) {
+      r[i] = ri;
+      dn[i] = di;
+    }
+  }
+};
+// coupling: t = (T)v - sum a z
+template <class T>
+struct EpiCouple {
+  const double* __restrict__ v;
+  T* __restrict__ t;
+  __device__ void operator()(int i, T acc) const { t[i] = (T)v[i] - acc; }
+};
+
+// ---------------------------------------------------------- outer SpMV
+void spmv_outer_f64(const DCsr& a, const double* x, double* y, hipStream_t s) {
+  launch_csr<double, double>(a, a.v, LoadArr<double>{x}, EpiStore<double, double>{y}, s);
+}
+void spmv_outer_mixed(const DCsr& a, const float* x, double* y, hipStream_t s) {
+  launch_csr<double, double>(a, a.v, LoadArr<float>{x}, EpiStore<double, double>{y}, s);
+}
+void spmv_resid_f64(const DCsr& a, const double* x, const double* b, double* r, hipStream_t s) {
+  launch_csr<double, double>(a, a.v, LoadArr<double>{x}, EpiResid<double>{b, r}, s);
+}
+
+// ------------------------------------------------------- V-cycle pieces
+template <class T>
+static const T* vals_of(const DCsr& a);
+template <>
+const double* vals_of<double>(const DCsr& a) {
+  return a.v;
+}
+template <>
+const float* vals_of<float>(const DCsr& a) {
+  return a.vf;
+}
+
+template <class T>
+__global__ void k_cheb_init0(int n, const T* __restrict__ dinv, const T* __restrict__ b, T c0, T* __restrict__ r,
+                             T* __restrict__ d, T* __restrict__ x) {
+  int i = blockIdx.x * BLK + threadIdx.x;
+  if (i >= n) return;
+  T di = dinv[i] * b[i] * c0;
+  r[i] = b[i];
+  d[i] = di;
+  x[i] = di;
+}
+
+template <class T>
+void VcOps<T>::pre2(const DCsr& a, const T* dinv, const ChebCoef& c, const T* b, T* x, hipStream_t s) {
+  launch_csr<T, T>(a, vals_of<T>(a), LoadD0<T>{dinv, b, (T)c.c0},
+                   EpiChebPre2<T>{dinv, b, x, (T)c.c0, (T)c.c1[1], (T)c.c2[1]}, s);
+}
+
+template <class T>
+void VcOps<T>::init0(int n, const T* dinv, const ChebCoef& c, const T* b, T* r, T* d, T* x, hipStream_t s) {
+  k_cheb_init0<T><<<grid_for(n, BLK), BLK, 0, s>>>(n, dinv, b, (T)c.c0, r, d, x);
+  HBGS_HIP(hipGetLastError());
+}
+
+template <class T>
+void VcOps<T>::post_start(const DCsr& a, const T* dinv, const ChebCoef& c, const T* b, const T* x, T* r, T* d,
+                          hipStream_t s) {
+  launch_csr<T, T>(a, vals_of<T>(a), LoadArr<T>{x}, EpiChebPostA<T>{dinv, b, r, d, (T)c.c0}, s);
+}
+
+template <class T>
+__global__ void k_add(int n, const T* __restrict__ d, T* __restrict__ x) {
+  int i = blockIdx.x * BLK + threadIdx.x;
+  if (i < n) x[i] = x[i] + d[i];
+}
+
+template <class T>
+void VcOps<T>::step(const DCsr& a, const T* dinv, const ChebCoef& c, int k, bool add_d, bool keep, T* r,
+                    const T* d, T* dn, T* x, hipStream_t s) {
+  const T* av = vals_of<T>(a);
+  const T c1 = (T)c.c1[k], c2 = (T)c.c2[k];
+  if (add_d && keep)
+    launch_csr<T, T>(a, av, LoadArr<T>{d}, EpiChebStep<T, true, true>{dinv, d, r, dn, x, c1, c2}, s);
+  else if (add_d)
+    launch_csr<T, T>(a, av, LoadArr<T>{d}, EpiChebStep<T, true, false>{dinv, d, r, dn, x, c1, c2}, s);
+  else if (keep)
+    launch_csr<T, T>(a, av, LoadArr<T>{d}, EpiChebStep<T, false, true>{dinv, d, r, dn, x, c1, c2}, s);
+  else
+    launch_csr<T, T>(a, av, LoadArr<T>{d}, EpiChebStep<T, false, false>{dinv, d, r, dn, x, c1, c2}, s);
+}
+
+template <class T>
+void VcOps<T>::add(int n, const T* d, T* x, hipStream_t s) {
+  k_add<T><<<grid_for(n, BLK), BLK, 0, s>>>(n, d, x);
+  HBGS_HIP(hipGetLastError());
+}
+
+template <class T>
+void VcOps<T>::resid(const DCsr& a, const T* b, const T* x, T* r, hipStream_t s) {
+  launch_csr<T, T>(a, vals_of<T>(a), LoadArr<T>{x}, EpiResid<T>{b, r}, s);
+}
+template <class T>
+void VcOps<T>::restrict_(const DCsr& rmat, const T* r, T* bc, hipStream_t s) {
+  launch_csr<T, T>(rmat, vals_of<T>(rmat), LoadArr<T>{r}, EpiStore<T, T>{bc}, s);
+}
+template <class T>
+void VcOps<T>::prolong(const DCsr& p, const T* xc, T* x, hipStream_t s) {
+  launch_csr<T, T>(p, vals_of<T>(p), LoadArr<T>{xc}, EpiAdd<T, T>{x}, s);
+}
+template <class T>
+void VcOps<T>::couple(const DCsr& c, const double* v, const T* z, T* t, hipStream_t s) {
+  launch_csr<T, T>(c, vals_of<T>(c), LoadArr<T>{z}, EpiCouple<T>{v, t}, s);
+}
+
+template <class T>
+__global__ void k_cast_in(int n, const double* __restrict__ v, T* __restrict__ t) {
+  int i = blockIdx.x * BLK + threadIdx.x;
+  if (i < n) t[i] = (T)v[i];
+}
+template <class T>
+void VcOps<T>::cast_in(int n, const double* v, T* t, hipStream_t s) {
+  k_cast_in<T><<<grid_for(n, BLK), BLK, 0, s>>>(n, v, t);
+  HBGS_HIP(hipGetLastError());
+}
+
+// coarsest level: x = A^-1 b with the dense FP64 inverse (row-major)
+template <class T>
+__global__ __launch_bounds__(BLK) void k_gemv_rows(int n, const double* __restrict__ inv, const T* __restrict__ b,
+                                                   T* __restrict__ x) {
+  const int wave = (blockIdx.x * BLK + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  if (wave >= n) return;
+  const double* row = inv + (int64_t)wave * n;
+  double acc = 0.0;
+  for (int j = lane; j < n; j += 64) acc += row[j] * (double)b[j];
+  acc = lanes_sum<double>(acc, 64);
+  if (lane == 0) x[wave] = (T)acc;
+}
+template <class T>
+__global__ __launch_bounds__(BLK) void k_gemv_cols(int n, const double* __restrict__ inv, const T* __restrict__ b,
+                                                   T* __restrict__ x) {
+  const int i = blockIdx.x * BLK + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < n; ++j) acc += inv[(int64_t)j * n + i] * (double)b[j];
+  x[i] = (T)acc;
+}
+template <class T>
+void VcOps<T>::coarse(int n, const double* inv, int transpose, const T* b, T* x, hipStream_t s) {
+  if (!transpose)
+    k_gemv_rows<T><<<grid_for((int64_t)n * 64, BLK), BLK, 0, s>>>(n, inv, b, x);
+  else
+    k_gemv_cols<T><<<grid_for(n, BLK), BLK, 0, s>>>(n, inv, b, x);
+  HBGS_HIP(hipGetLastError());
+}
+
+template struct VcOps<float>;
+template struct VcOps<double>;
+
+// --------------------------------------------------------------- GMRES
+__global__ void k_permute_in(int n, const int* __restrict__ perm, const double* __restrict__ x,
+                             double* __restrict__ xp) {
+  int i = blockIdx.x * BLK + threadIdx.x;
+  if (i < n) xp[perm[i]] = x[i];
+}
+__global__ void k_permute_out(int n, const int* __restrict__ perm, const double* __restrict__ xp,
+                              double* __restrict__ x) {
+  int i = blockIdx.x * BLK + threadIdx.x;
+  if (i < n) x[i] = xp[perm[i]];
+}
+void permute_in(int n, const int* perm, const double* x, double* xp, hipStream_t s) {
+  k_permute_in<<<grid_for(n, BLK), BLK, 0, s>>>(n, perm, x, xp);
+  HBGS_HIP(hipGetLastError());
+}
+void permute_out(int n, const int* perm, const double* xp, double* x, hipStream_t s) {
+  k_permute_out<<<grid_for(n, BLK), BLK, 0, s>>>(n, perm, xp, x);
+  HBGS_HIP(hipGetLastError());
+}
+
+constexpr int DOT_BLOCKS_MAX = 1024;
+int dot_blocks(int n) {
+  int64_t b = ((int64_t)n + BLK * 8 - 1) / (BLK * 8);
+  if (b < 1) b = 1;
+  if (b > DOT_BLOCKS_MAX) b = DOT_BLOCKS_MAX;
+  return (int)b;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = lanes_sum<double>(v, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < BLK / 64; ++q) t += sh[q];
+  return t;
+}
+
+// Classical Gram-Schmidt pass over rows: w holds column j+1 of V.
+//   UPD:  w -= sum_k h_k V_k           (k <= j)
+//   DOTS: part_k = sum V_k . w          (k <= j), after the update
+//   always: part_{j+1} = w . w
+template <int MAXV, bool UPD, bool DOTS>
+__global__ __launch_bounds__(BLK) void k_cgs(int n, int nv, const double* __restrict__ V, size_t ldv,
+                                             double* __restrict__ w, const double* __restrict__ h,
+                                             double* __restrict__ part) {
+  __shared__ double sh[BLK / 64];
+  double acc[DOTS ? MAXV : 1];
+  double hh[UPD ? MAXV : 1];
+#pragma unroll
+  for (int k = 0; k < (DOTS ? MAXV : 1); ++k) acc[k] = 0.0;
+  if (UPD) {
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) hh[k] = k < nv ? h[k < nv ? k : 0] : 0.0;
+  }
+  double ww = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
+    double vk[MAXV];
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) vk[k] = k < nv ? V[(size_t)(k < nv ? k : 0) * ldv + i] : 0.0;
+    double wi = w[i];
+    if (UPD) {
+#pragma unroll
+      for (int k = 0; k < MAXV; ++k) wi -= hh[k] * vk[k];
+      w[i] = wi;
+    }
+    if (DOTS) {
+#pragma unroll
+      for (int k = 0; k < MAXV; ++k) acc[k] += vk[k] * wi;
+    }
+    ww += wi * wi;
+  }
+  const int nb = gridDim.x;
+  if (DOTS) {
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) {
+      if (k < nv) {
+        double t = block_sum(acc[k], sh);
+        if (threadIdx.x == 0) part[(size_t)k * nb + blockIdx.x] = t;
+      }
+    }
+  }
+  double t = block_sum(ww, sh);
+  if (threadIdx.x == 0) part[(size_t)nv * nb + blockIdx.x] = t;
+}
+
+template <bool UPD, bool DOTS>
+static void launch_cgs(int n, int nv, const double* V, size_t ldv, double* w, const double* h, double* part,
+                       hipStream_t s) {
+  int nb = dot_blocks(n);
+  if (nv <= 8)
+    k_cgs<8, UPD, DOTS><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part);
+  else if (nv <= 16)
+    k_cgs<16, UPD, DOTS><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part);
+  else if (nv <= 32)
+    k_cgs<32, UPD, DOTS><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part);
+  else
+    k_cgs<64, UPD, DOTS><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part);
+  HBGS_HIP(hipGetLastError());
+}
+
+void mdot(int n, int j, const double* V, size_t ldv, const double* w, double* part, hipStream_t s) {
+  launch_cgs<false, true>(n, j + 1, V, ldv, const_cast<double*>(w), nullptr, part, s);
+}
+void upd_mdot(int n, int j, const double* V, size_t ldv, double* w, const double* h, double* part,
+              hipStream_t s) {
+  launch_cgs<true, true>(n, j + 1, V, ldv, w, h, part, s);
+}
+void upd_norm(int n, int j, const double* V, size_t ldv, double* w, const double* h, double* part,
+              hipStream_t s) {
+  launch_cgs<true, false>(n, j + 1, V, ldv, w, h, part, s);
+}
+
+// out[k] = sum over blocks of part[k*nb + b] (fixed order per k)
+__global__ __launch_bounds__(BLK) void k_reduce(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[BLK / 64];
+  const double* p = part + (size_t)blockIdx.x * nb;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += BLK) acc += p[b];
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+void mdot_reduce(int nvec, int nblocks, const double* part, double* out, hipStream_t s) {
+  k_reduce<<<nvec, BLK, 0, s>>>(nblocks, part, out);
+  HBGS_HIP(hipGetLastError());
+}
+
+// Givens rotation update of Hessenberg column j (H is (m+1) x m, row-major
+// with leading dimension m).  h1/h2: first and second Gram-Schmidt
+// coefficients (k <= j); hn2 = ||w||^2 after both passes; w0sq = ||w||^2
+// before orthogonalisation.
+__global__ void k_givens(int j, int m, const double* h1, const double* h2, const double* hn2, const double* w0sq,
+                         double* H, double* cs, double* sn, double* g, double* scal) {
+  if (threadIdx.x != 0) return;
+  for (int k = 0; k <= j; ++k) H[(size_t)k * m + j] = h1[k] + (h2 ? h2[k] : 0.0);
+  double hn = sqrt(*hn2);
+  H[(size_t)(j + 1) * m + j] = hn;
+  for (int k = 0; k < j; ++k) {
+    double a = H[(size_t)k * m + j], b = H[(size_t)(k + 1) * m + j];
+    H[(size_t)k * m + j] = cs[k] * a + sn[k] * b;
+    H[(size_t)(k + 1) * m + j] = -sn[k] * a + cs[k] * b;
+  }
+  double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+  double den = sqrt(a * a + b * b);
+  cs[j] = a / den;
+  sn[j] = b / den;
+  H[(size_t)j * m + j] = den;
+  H[(size_t)(j + 1) * m + j] = 0.0;
+  g[j + 1] = -sn[j] * g[j];
+  g[j] = cs[j] * g[j];
+  scal[0] = fabs(g[j + 1]);
+  scal[1] = hn;
+  scal[2] = sqrt(*w0sq);
+}
+void givens(int j, int m, const double* h1, const double* h2, const double* hn2, const double* w0sq, double* H,
+            double* cs, double* sn, double* g, double* scal, hipStream_t s) {
+  k_givens<<<1, 64, 0, s>>>(j, m, h1, h2, hn2, w0sq, H, cs, sn, g, scal);
+  HBGS_HIP(hipGetLastError());
+}
+
+__global__ void k_scale(int n, const double* __restrict__ w, const double* __restrict__ scal, double* __restrict__ v) {
+  int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+  double hn = scal[1];
+  if (i < n && hn > 0.0) v[i] = w[i] / hn;
+}
+void scale(int n, const double* w, const double* scal, double* v, hipStream_t s) {
+  k_scale<<<grid_for(n, BLK), BLK, 0, s>>>(n, w, scal, v);
+  HBGS_HIP(hipGetLastError());
+}
+
+__global__ void k_backsolve(int jend, int m, const double* H, const double* g, double* y) {
+  if (threadIdx.x != 0) return;
+  for (int i = jend - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int k = i + 1; k < jend; ++k) s -= H[(size_t)i * m + k] * y[k];
+    y[i] = s / H[(size_t)i * m + i];
+  }
+}
+void backsolve(int jend, int m, const double* H, const double* g, double* y, hipStream_t s) {
+  k_backsolve<<<1, 64, 0, s>>>(jend, m, H, g, y);
+  HBGS_HIP(hipGetLastError());
+}
+
+template <class TZ>
+__global__ void k_xupdate(int n, int jend, const TZ* __restrict__ Z, size_t ldz, const double* __restrict__ y,
+                          double* __restrict__ x) {
+  int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+  if (i >= n) return;
+  double xi = x[i];
+  for (int k = 0; k < jend; ++k) xi += y[k] * (double)Z[(size_t)k * ldz + i];
+  x[i] = xi;
+}
+template <class TZ>
+void xupdate(int n, int jend, const TZ* Z, size_t ldz, const double* y, double* x, hipStream_t s) {
+  k_xupdate<TZ><<<grid_for(n, BLK), BLK, 0, s>>>(n, jend, Z, ldz, y, x);
+  HBGS_HIP(hipGetLastError());
+}
+template void xupdate<float>(int, int, const float*, size_t, const double*, double*, hipStream_t);
+template void xupdate<double>(int, int, const double*, size_t, const double*, double*, hipStream_t);
+
+__global__ __launch_bounds__(BLK) void k_norm2_part(int n, const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double sh[BLK / 64];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK)
+    acc += x[i] * x[i];
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+void norm2_partial(int n, const double* x, double* part, hipStream_t s) {
+  k_norm2_part<<<dot_blocks(n), BLK, 0, s>>>(n, x, part);
+  HBGS_HIP(hipGetLastError());
+}
+
+__global__ void k_scale_copy(int n, const double* __restrict__ r, const double* __restrict__ ss,
+                             double* __restrict__ v) {
+  int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
+  double nr = sqrt(*ss);
+  if (i < n) v[i] = r[i] / nr;
+}
+void scale_copy(int n, const double* r, const double* part_sum, double* v, hipStream_t s) {
+  k_scale_copy<<<grid_for(n, BLK), BLK, 0, s>>>(n, r, part_sum, v);
+  HBGS_HIP(hipGetLastError());
+}
+
+__global__ void k_grad(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ lam,
+                       const double* __restrict__ x, double* __restrict__ g) {
+  int i = blockIdx.x * BLK + threadIdx.x;
+  if (i >= n) return;
+  double li = lam[i];
+  for (int k = rp[i]; k < rp[i + 1]; ++k) g[k] = -li * x[ci[k]];
+}
+void grad_values(int n, const int* rp, const int* ci, const double* lam, const double* x, double* g,
+                 hipStream_t s) {
+  k_grad<<<grid_for(n, BLK), BLK, 0, s>>>(n, rp, ci, lam, x, g);
+  HBGS_HIP(hipGetLastError());
+}
+
+}  // namespace solve
+}  // namespace hbgs
