@@ -69,6 +69,9 @@ typedef struct {
   uint64_t seed;         /* salt of the aggregation priorities and start vectors */
   double theta[HBGS_MAX_FIELDS]; /* strength threshold per field (default 0.04 for
                                     field 0, 0 otherwise) */
+  int32_t use_graphs;    /* 1: replay each GMRES iteration as a captured HIP graph;
+                            0: launch kernels one by one (default; measured faster
+                            than graph replay on ROCm 7.2 for this kernel mix) */
 } hbgs_options;
 
 typedef struct {
@@ -158,7 +161,8 @@ hbgs_status hbgs_get_aggregates(hbgs_ctx *ctx, int32_t field, int32_t level, int
  * mask of classes (bit k = the k-th record reported by hbgs_kernel_times).
  * While on, each launch of a selected solve-phase kernel is bracketed by HIP
  * events recorded on its launch stream; durations are accumulated per class
- * (enabling resets the totals).  hbgs_kernel_times copies up to cap records
+ * (enabling resets the totals).  GMRES steps are launched one kernel at a
+ * time (not replayed from graphs) while timing is on.  hbgs_kernel_times copies up to cap records
  * (name, total milliseconds, launch count, algorithmic bytes) and returns the
  * number of records, or a negative status. */
 hbgs_status hbgs_profile(hbgs_ctx *ctx, int32_t enable);

@@ -34,7 +34,7 @@ class Options(ctypes.Structure):
         ("rtol", ctypes.c_double), ("cheb_degree", ctypes.c_int32), ("cheb_ratio", ctypes.c_double),
         ("cheb_boost", ctypes.c_double), ("eig_iters", ctypes.c_int32), ("sa_damping", ctypes.c_double),
         ("coarse_max", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("seed", ctypes.c_uint64),
-        ("theta", ctypes.c_double * MAX_FIELDS),
+        ("theta", ctypes.c_double * MAX_FIELDS), ("use_graphs", ctypes.c_int32),
     ]
 
 

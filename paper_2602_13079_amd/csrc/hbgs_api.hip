@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -136,12 +137,29 @@ struct Level {
 struct Field {
   int id = 0, lo = 0, hi = 0;
   std::vector<Level> lv;  // lv.back() is the coarsest level
-  double* inv = nullptr;  // dense inverse of the coarsest operator
+  double* inv = nullptr;   // dense inverse of the coarsest operator (row-major)
+  double* invT = nullptr;  // its transpose (adjoint apply)
   DCsr lower;             // rows of this field, columns of earlier leaves (global)
   DCsr upperT;            // rows of A^T in this field, columns of later leaves (global)
   double* td = nullptr;   // fine-level right-hand side
   float* tf = nullptr;
+  uint32_t deps[2] = {0, 0};  // fields read by the coupling rows: [0] forward, [1] adjoint sweep
   int n() const { return hi - lo; }
+};
+
+// Concurrent field V-cycles: a field's sweep step (coupling + V-cycle) only
+// reads the z of the fields its coupling rows reference, so independent
+// fields run on separate streams; events carry the dependencies.
+struct SweepPlan {
+  std::vector<int> order;   // fields in visiting order
+  std::vector<int> stream;  // stream slot per position
+  int nstreams = 1;
+};
+constexpr int MAX_SWEEP_STREAMS = 4;
+
+// one captured GMRES iteration (key: precision, transpose, column j)
+struct IterGraph {
+  hipGraphExec_t exec = nullptr;
 };
 
 }  // namespace hbgs
@@ -169,8 +187,31 @@ struct hbgs_ctx {
   double* host_scal = nullptr;  // pinned
   hbgs::Profiler prof;
   hbgs_stats_t stats{};
+  // concurrent sweep
+  hbgs::SweepPlan plan[2];
+  hipStream_t fstream[hbgs::MAX_SWEEP_STREAMS] = {};
+  hipEvent_t fdone[HBGS_MAX_FIELDS] = {};
+  hipEvent_t fork = nullptr;
+  // solve stream (graph capture needs a non-default stream) and graph cache
+  hipStream_t sm = nullptr;
+  hipEvent_t join_in = nullptr, join_out = nullptr;
+  std::map<int, hbgs::IterGraph> graphs;
+  void clear_graphs() {
+    for (auto& kv : graphs)
+      if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    graphs.clear();
+  }
   ~hbgs_ctx() {
+    clear_graphs();
+    if (sm) (void)hipStreamDestroy(sm);
+    if (join_in) (void)hipEventDestroy(join_in);
+    if (join_out) (void)hipEventDestroy(join_out);
     if (host_scal) (void)hipHostFree(host_scal);
+    for (auto& st : fstream)
+      if (st) (void)hipStreamDestroy(st);
+    for (auto& e : fdone)
+      if (e) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
   }
 };
 
@@ -261,15 +302,24 @@ static solve::ChebCoef cheb_coef(const hbgs_options& o, double lam) {
   return c;
 }
 
-static bool structurally_symmetric(const DCsr& a, const DCsr& at, hipStream_t s) {
-  if (a.nnz != at.nnz) return false;
-  std::vector<int> r1(a.n + 1), r2(a.n + 1), c1(a.nnz), c2(a.nnz);
-  HBGS_HIP(hipMemcpyAsync(r1.data(), a.rp, sizeof(int) * (a.n + 1), hipMemcpyDeviceToHost, s));
-  HBGS_HIP(hipMemcpyAsync(r2.data(), at.rp, sizeof(int) * (a.n + 1), hipMemcpyDeviceToHost, s));
-  HBGS_HIP(hipMemcpyAsync(c1.data(), a.ci, sizeof(int) * a.nnz, hipMemcpyDeviceToHost, s));
-  HBGS_HIP(hipMemcpyAsync(c2.data(), at.ci, sizeof(int) * a.nnz, hipMemcpyDeviceToHost, s));
+// pattern of a equals the pattern of its transpose
+static bool structurally_symmetric_dev(const DCsr& a, hipStream_t s) {
+  DCsr t;
+  Pool tmp;
+  t.rp = tmp.make<int>(a.m + 1);
+  t.ci = tmp.make<int>(a.nnz);
+  t.v = nullptr;
+  DCsr pat = a;
+  pat.v = nullptr;
+  setup::transpose(pat, t, s);
+  Tmp<int> diff(1);
+  HBGS_HIP(hipMemsetAsync(diff.p, 0, sizeof(int), s));
+  solve::compare_int(a.n + 1, a.rp, t.rp, diff.p, s);
+  solve::compare_int(a.nnz, a.ci, t.ci, diff.p, s);
+  int d = 0;
+  HBGS_HIP(hipMemcpyAsync(&d, diff.p, sizeof(int), hipMemcpyDeviceToHost, s));
   HBGS_HIP(hipStreamSynchronize(s));
-  return r1 == r2 && c1 == c2;
+  return d == 0;
 }
 
 // SA-AMG hierarchy of one field's diagonal block (level 0 already set)
@@ -359,6 +409,8 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
       if (n > 8000) HBGS_FAIL(HBGS_ESETUP, "coarsest level too large for the dense factorisation");
       F.inv = pool.make<double>((size_t)n * n);
       if (setup::dense_inverse(L.A, F.inv, s) != 0) HBGS_FAIL(HBGS_ESINGULAR, "singular coarsest-level matrix");
+      F.invT = pool.make<double>((size_t)n * n);
+      setup::dense_transpose(n, F.inv, F.invT, s);
       break;
     }
     L.dinv = pool.make<double>(n);
@@ -368,14 +420,24 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
     L.cc = cheb_coef(o, L.lam_cheb);
   }
   // solve-phase data: transposes, FP32 copies, work vectors
+  if (!structurally_symmetric_dev(F.lv[0].A, s))
+    HBGS_FAIL(HBGS_EINVAL, "a diagonal field block is not structurally symmetric");
   for (size_t l = 0; l < F.lv.size(); ++l) {
     Level& L = F.lv[l];
-    L.AT = transpose_new(pool, L.A, s);
+    // A_l is structurally symmetric (level 0 checked above; Galerkin products
+    // R A P with R = P^T keep the property), so A_l^T shares its pattern
+    L.AT = L.A;
+    L.AT.v = pool.make<double>(L.A.nnz);
+    setup::transpose_symmetric(L.A, L.AT.v, s);
     add_f32(pool, L.A, s);
     add_f32(pool, L.AT, s);
+    setup::row_stats(L.A, s);
+    L.AT.maxlen = L.A.maxlen;
     if (l + 1 < F.lv.size()) {
       add_f32(pool, L.P, s);
       add_f32(pool, L.R, s);
+      setup::row_stats(L.P, s);
+      setup::row_stats(L.R, s);
     }
     const int n = L.A.n;
     L.bd = pool.make<double>(n);
@@ -389,8 +451,6 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
     L.df = pool.make<float>(n);
     L.dnf = pool.make<float>(n);
   }
-  if (!structurally_symmetric(F.lv[0].A, F.lv[0].AT, s))
-    HBGS_FAIL(HBGS_EINVAL, "a diagonal field block is not structurally symmetric");
 }
 
 static double spmv_bytes(const DCsr& a, int tv, int tx, int ty, int extra_vec) {
@@ -436,8 +496,40 @@ static void compute_stats(hbgs_ctx* c) {
   }
 }
 
+// Stream slots for the sweep: a field continues the stream of the latest
+// field (in visiting order) it depends on; a field without dependencies
+// starts the next free slot.
+static void plan_sweep(hbgs_ctx* c, int tr) {
+  SweepPlan& p = c->plan[tr];
+  const int nl = (int)c->leaf_order.size();
+  p.order.clear();
+  p.stream.clear();
+  p.nstreams = 0;
+  std::vector<int> slot_of(c->nf, -1);
+  for (int q = 0; q < nl; ++q) {
+    int f = c->leaf_order[tr ? nl - 1 - q : q];
+    int slot = -1;
+    for (int k = q - 1; k >= 0 && slot < 0; --k)
+      if (c->F[f].deps[tr] >> p.order[k] & 1u) slot = slot_of[p.order[k]];
+    if (slot < 0) slot = p.nstreams < MAX_SWEEP_STREAMS ? p.nstreams++ : q % MAX_SWEEP_STREAMS;
+    slot_of[f] = slot;
+    p.order.push_back(f);
+    p.stream.push_back(slot);
+  }
+  if (p.nstreams == 0) p.nstreams = 1;
+  for (int k = 0; k < MAX_SWEEP_STREAMS; ++k)
+    if (!c->fstream[k]) HBGS_HIP(hipStreamCreateWithFlags(&c->fstream[k], hipStreamNonBlocking));
+  for (int f = 0; f < c->nf; ++f)
+    if (!c->fdone[f]) HBGS_HIP(hipEventCreateWithFlags(&c->fdone[f], hipEventDisableTiming));
+  if (!c->fork) HBGS_HIP(hipEventCreateWithFlags(&c->fork, hipEventDisableTiming));
+  if (!c->sm) HBGS_HIP(hipStreamCreateWithFlags(&c->sm, hipStreamNonBlocking));
+  if (!c->join_in) HBGS_HIP(hipEventCreateWithFlags(&c->join_in, hipEventDisableTiming));
+  if (!c->join_out) HBGS_HIP(hipEventCreateWithFlags(&c->join_out, hipEventDisableTiming));
+}
+
 // value-dependent part of setup: blocks, couplings, hierarchies
 static void build_values(hbgs_ctx* c, hipStream_t s) {
+  c->clear_graphs();
   c->hier.~Pool();
   new (&c->hier) Pool();
   c->F.assign(c->nf, Field{});
@@ -453,10 +545,29 @@ static void build_values(hbgs_ctx* c, hipStream_t s) {
     F.upperT = extract(c->hier, c->ApT, F.lo, F.hi, F.hi, c->n, 0, c->n, s);
     add_f32(c->hier, F.lower, s);
     add_f32(c->hier, F.upperT, s);
+    setup::row_stats(F.lower, s);
+    setup::row_stats(F.upperT, s);
     F.td = c->hier.make<double>(F.n());
     F.tf = c->hier.make<float>(F.n());
     build_hierarchy(c, F, s);
   }
+  // which fields each coupling reads
+  {
+    Tmp<int> masks(2 * c->nf);
+    HBGS_HIP(hipMemsetAsync(masks.p, 0, sizeof(int) * 2 * c->nf, s));
+    for (int f = 0; f < c->nf; ++f) {
+      solve::column_fields(c->F[f].lower, c->nf, c->f_lo.data(), c->f_hi.data(), masks.p + 2 * f, s);
+      solve::column_fields(c->F[f].upperT, c->nf, c->f_lo.data(), c->f_hi.data(), masks.p + 2 * f + 1, s);
+    }
+    std::vector<int> hm(2 * c->nf);
+    HBGS_HIP(hipMemcpyAsync(hm.data(), masks.p, sizeof(int) * 2 * c->nf, hipMemcpyDeviceToHost, s));
+    HBGS_HIP(hipStreamSynchronize(s));
+    for (int f = 0; f < c->nf; ++f) {
+      c->F[f].deps[0] = (uint32_t)hm[2 * f];
+      c->F[f].deps[1] = (uint32_t)hm[2 * f + 1];
+    }
+  }
+  for (int tr = 0; tr < 2; ++tr) plan_sweep(c, tr);
   HBGS_HIP(hipStreamSynchronize(s));
   compute_stats(c);
 }
@@ -493,17 +604,18 @@ static void vcycle(hbgs_ctx* c, Field& F, int l, int tr, const T* b, T* x, hipSt
   const int n = L.A.n;
   if (l + 1 == (int)F.lv.size()) {
     Prof p(c->prof, s, solve::K_COARSE, 8.0 * n * n + 2.0 * n * TS);
-    VcOps<T>::coarse(n, F.inv, tr, b, x, s);
+    VcOps<T>::coarse(n, tr ? F.invT : F.inv, 0, b, x, s);
     return;
   }
   const DCsr& A = tr ? L.AT : L.A;
   const T* dinv = B::dinv(L);
   const solve::ChebCoef& cc = L.cc;
   T *r = B::r(L), *d = B::d(L), *dn = B::dn(L);
-  // pre-smoothing from a zero guess
+  // pre-smoothing from a zero guess (degree 2: d0 was written by the
+  // producer of b into this level's d buffer)
   if (cc.degree == 2) {
-    Prof p(c->prof, s, solve::K_CHEB_PRE, spmv_bytes(A, TS, TS, TS, 1));
-    VcOps<T>::pre2(A, dinv, cc, b, x, s);
+    Prof p(c->prof, s, solve::K_CHEB_PRE, spmv_bytes(A, TS, TS, TS, 2));
+    VcOps<T>::pre2(A, dinv, cc, b, d, x, s);
   } else {
     {
       Prof p(c->prof, s, solve::K_CHEB_OTHER, 4.0 * n * TS);
@@ -521,8 +633,9 @@ static void vcycle(hbgs_ctx* c, Field& F, int l, int tr, const T* b, T* x, hipSt
   }
   Level& C = F.lv[l + 1];
   {
-    Prof p(c->prof, s, solve::K_RESTRICT, spmv_bytes(L.R, TS, TS, TS, 0));
-    VcOps<T>::restrict_(L.R, r, B::b(C), s);
+    const bool d0c = l + 2 < (int)F.lv.size() && C.cc.degree == 2;
+    Prof p(c->prof, s, solve::K_RESTRICT, spmv_bytes(L.R, TS, TS, TS, d0c ? 2 : 0));
+    VcOps<T>::restrict_(L.R, r, B::b(C), d0c ? B::dinv(C) : nullptr, C.cc.c0, d0c ? B::d(C) : nullptr, s);
   }
   vcycle<T>(c, F, l + 1, tr, B::b(C), B::x(C), s);
   {
@@ -550,26 +663,49 @@ static void vcycle(hbgs_ctx* c, Field& F, int l, int tr, const T* b, T* x, hipSt
 
 // z = M^-1 v (tr = 0) or M^-T v (tr = 1), permuted ordering; z has type T
 template <class T>
-static void sweep(hbgs_ctx* c, int tr, const double* v, T* z, hipStream_t s) {
-  const int nl = (int)c->leaf_order.size();
+static void sweep(hbgs_ctx* c, int tr, const double* v, T* z, hipStream_t s0) {
+  const SweepPlan& plan = c->plan[tr];
+  const int nl = (int)plan.order.size();
   const int TS = (int)sizeof(T);
+  HBGS_HIP(hipEventRecord(c->fork, s0));
+  for (int k = 0; k < plan.nstreams; ++k) HBGS_HIP(hipStreamWaitEvent(c->fstream[k], c->fork, 0));
+  std::vector<int> slot_of(c->nf, -1);
   for (int q = 0; q < nl; ++q) {
-    Field& F = c->F[c->leaf_order[tr ? nl - 1 - q : q]];
+    Field& F = c->F[plan.order[q]];
+    const int slot = plan.stream[q];
+    hipStream_t s = c->fstream[slot];
+    for (int k = 0; k < q; ++k) {
+      int g = plan.order[k];
+      if ((F.deps[tr] >> g & 1u) && slot_of[g] != slot) HBGS_HIP(hipStreamWaitEvent(s, c->fdone[g], 0));
+    }
+    slot_of[F.id] = slot;
     const DCsr& cpl = tr ? F.upperT : F.lower;
+    Level& L0 = F.lv[0];
+    // the finest level's first Chebyshev direction is formed with its rhs
+    const bool d0 = F.lv.size() > 1 && L0.cc.degree == 2;
+    const T* dinv0 = d0 ? Buf<T>::dinv(L0) : nullptr;
+    T* d00 = d0 ? Buf<T>::d(L0) : nullptr;
     const T* t;
     if (cpl.nnz > 0) {
-      Prof p(c->prof, s, solve::K_COUPLE, spmv_bytes(cpl, TS, 0, TS, 0) + 8.0 * F.n() + (double)std::min<int64_t>(cpl.nnz, c->n) * TS);
-      VcOps<T>::couple(cpl, v + F.lo, z, Buf<T>::t(F), s);
+      Prof p(c->prof, s, solve::K_COUPLE,
+             spmv_bytes(cpl, TS, 0, TS, d0 ? 2 : 0) + 8.0 * F.n() + (double)std::min<int64_t>(cpl.nnz, c->n) * TS);
+      VcOps<T>::couple(cpl, v + F.lo, z, Buf<T>::t(F), dinv0, L0.cc.c0, d00, s);
       t = Buf<T>::t(F);
     } else if (sizeof(T) == sizeof(double)) {
       t = reinterpret_cast<const T*>(v + F.lo);
+      if (d0) {
+        Prof p(c->prof, s, solve::K_COUPLE, 3.0 * F.n() * TS);
+        VcOps<T>::make_d0(F.n(), t, dinv0, L0.cc.c0, d00, s);
+      }
     } else {
-      Prof p(c->prof, s, solve::K_COUPLE, 12.0 * F.n());
-      VcOps<T>::cast_in(F.n(), v + F.lo, Buf<T>::t(F), s);
+      Prof p(c->prof, s, solve::K_COUPLE, (8.0 + TS * (d0 ? 3 : 1)) * F.n());
+      VcOps<T>::cast_in(F.n(), v + F.lo, Buf<T>::t(F), dinv0, L0.cc.c0, d00, s);
       t = Buf<T>::t(F);
     }
     vcycle<T>(c, F, 0, tr, t, z + F.lo, s);
+    HBGS_HIP(hipEventRecord(c->fdone[F.id], s));
   }
+  for (int q = 0; q < nl; ++q) HBGS_HIP(hipStreamWaitEvent(s0, c->fdone[plan.order[q]], 0));
 }
 
 // ------------------------------------------------------------------ GMRES
@@ -623,6 +759,80 @@ static void apply_perm(hbgs_ctx* c, int tr, const double* v, int j, hipStream_t 
     sweep<double>(c, tr, v, c->Zd + (size_t)j * c->ld, s);
 }
 
+// One Arnoldi step j: z_j = M^-1 v_j, w = A z_j (into column j+1 of V),
+// two classical Gram-Schmidt passes, Givens update, v_{j+1} = w / h_{j+1,j}.
+static void iteration_body(hbgs_ctx* c, int tr, int j, hipStream_t s) {
+  const int n = c->n, m = c->m;
+  const DCsr& A = tr ? c->ApT : c->Ap;
+  const size_t ld = c->ld;
+  const int nb = solve::dot_blocks(n);
+  double* vj = c->V + (size_t)j * ld;
+  double* w = c->V + (size_t)(j + 1) * ld;
+  apply_perm(c, tr, vj, j, s);
+  {
+    Prof p(c->prof, s, solve::K_SPMV_OUTER, spmv_bytes(A, 8, c->precision ? 4 : 8, 8, 0));
+    if (c->precision == 1)
+      solve::spmv_outer_mixed(A, c->Zf + (size_t)j * ld, w, s);
+    else
+      solve::spmv_outer_f64(A, c->Zd + (size_t)j * ld, w, s);
+  }
+  {
+    Prof p(c->prof, s, solve::K_DOT1, 8.0 * n * (j + 2));
+    solve::mdot(n, j, c->V, ld, w, c->part, s);
+  }
+  {
+    Prof p(c->prof, s, solve::K_REDUCE, 8.0 * nb * (j + 2));
+    solve::mdot_reduce(j + 2, nb, c->part, c->h1, s);
+  }
+  {
+    Prof p(c->prof, s, solve::K_UPD_DOT2, 8.0 * n * (j + 3));
+    solve::upd_mdot(n, j, c->V, ld, w, c->h1, c->part, s);
+  }
+  {
+    Prof p(c->prof, s, solve::K_REDUCE, 8.0 * nb * (j + 2));
+    solve::mdot_reduce(j + 2, nb, c->part, c->h2, s);
+  }
+  {
+    Prof p(c->prof, s, solve::K_GIVENS, 0.0);
+    solve::givens(j, m, c->h1, c->h2, c->h1 + (j + 1), c->H, c->cs, c->sn, c->g, c->scal, s);
+  }
+  {
+    Prof p(c->prof, s, solve::K_UPD_SCALE, 8.0 * n * (j + 3));
+    solve::upd_scale(n, j, c->V, ld, w, c->h2, c->scal, s);
+  }
+}
+
+// Runs step j eagerly, or replays its captured graph (capturing it on first
+// use; graphs are dropped when the hierarchy changes).  Kernel timing needs
+// events around individual launches, which graph replays do not provide, so
+// steps run eagerly while the profiler is on.
+static void run_iteration(hbgs_ctx* c, int tr, int j, hipStream_t s) {
+  if (!c->o.use_graphs || c->prof.on) {
+    iteration_body(c, tr, j, s);
+    return;
+  }
+  const int key = (c->precision * 2 + tr) * 128 + j;
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    IterGraph ig;
+    hipGraph_t g = nullptr;
+    HBGS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    try {
+      iteration_body(c, tr, j, s);
+    } catch (...) {
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HBGS_HIP(hipStreamEndCapture(s, &g));
+    hipError_t e = hipGraphInstantiate(&ig.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HBGS_HIP(e);
+    it = c->graphs.emplace(key, std::move(ig)).first;
+  }
+  HBGS_HIP(hipGraphLaunch(it->second.exec, s));
+}
+
 static hbgs_status gmres(hbgs_ctx* c, int tr, int use_x0, int32_t* iters, double* hist, int cap, int32_t* hlen,
                          hipStream_t s) {
   const int n = c->n, m = c->m;
@@ -663,48 +873,7 @@ static hbgs_status gmres(hbgs_ctx* c, int tr, int use_x0, int32_t* iters, double
     HBGS_HIP(hipMemcpyAsync(c->g, g0.data(), sizeof(double) * (m + 1), hipMemcpyHostToDevice, s));
     int jend = 0;
     for (int j = 0; j < m; ++j) {
-      double* vj = c->V + (size_t)j * ld;
-      double* w = c->V + (size_t)(j + 1) * ld;
-      apply_perm(c, tr, vj, j, s);
-      {
-        Prof p(c->prof, s, solve::K_SPMV_OUTER, spmv_bytes(A, 8, c->precision ? 4 : 8, 8, 0));
-        if (c->precision == 1)
-          solve::spmv_outer_mixed(A, c->Zf + (size_t)j * ld, w, s);
-        else
-          solve::spmv_outer_f64(A, c->Zd + (size_t)j * ld, w, s);
-      }
-      {
-        Prof p(c->prof, s, solve::K_DOT1, 8.0 * n * (j + 2));
-        solve::mdot(n, j, c->V, ld, w, c->part, s);
-      }
-      {
-        Prof p(c->prof, s, solve::K_REDUCE, 8.0 * nb * (j + 2));
-        solve::mdot_reduce(j + 2, nb, c->part, c->h1, s);
-      }
-      {
-        Prof p(c->prof, s, solve::K_UPD_DOT2, 8.0 * n * (j + 3));
-        solve::upd_mdot(n, j, c->V, ld, w, c->h1, c->part, s);
-      }
-      {
-        Prof p(c->prof, s, solve::K_REDUCE, 8.0 * nb * (j + 2));
-        solve::mdot_reduce(j + 2, nb, c->part, c->h2, s);
-      }
-      {
-        Prof p(c->prof, s, solve::K_UPD_NORM, 8.0 * n * (j + 3));
-        solve::upd_norm(n, j, c->V, ld, w, c->h2, c->part, s);
-      }
-      {
-        Prof p(c->prof, s, solve::K_REDUCE, 8.0 * nb);
-        solve::mdot_reduce(1, nb, c->part + (size_t)(j + 1) * nb, c->hn2, s);
-      }
-      {
-        Prof p(c->prof, s, solve::K_GIVENS, 0.0);
-        solve::givens(j, m, c->h1, c->h2, c->hn2, c->h1 + (j + 1), c->H, c->cs, c->sn, c->g, c->scal, s);
-      }
-      {
-        Prof p(c->prof, s, solve::K_SCALE, 16.0 * n);
-        solve::scale(n, w, c->scal, w, s);
-      }
+      run_iteration(c, tr, j, s);
       HBGS_HIP(hipMemcpyAsync(c->host_scal, c->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
       HBGS_HIP(hipStreamSynchronize(s));
       (*iters)++;
@@ -760,6 +929,7 @@ void hbgs_default_options(hbgs_options* o) {
   o->max_levels = 10;
   o->seed = 0x2602ull;
   o->theta[0] = 0.04;
+  o->use_graphs = 0;
 }
 
 const char* hbgs_last_error(void) { return g_last_error.c_str(); }
@@ -847,6 +1017,8 @@ hbgs_status hbgs_setup(hbgs_ctx** out, int32_t n, int64_t nnz, const int32_t* ro
     setup::permute_fill(n, c->rp0, c->ci0, val, c->perm, c->iperm, c->Ap.rp, c->Ap.ci, c->Ap.v, c->src, s);
   }
   c->ApT = transpose_new(c->pool, c->Ap, s);
+  setup::row_stats(c->Ap, s);
+  setup::row_stats(c->ApT, s);
   build_values(c, s);
   c->stats.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = c;
@@ -926,14 +1098,20 @@ hbgs_status hbgs_solve(hbgs_ctx* c, const double* b, double* x, int32_t use_x0, 
     return HBGS_EINVAL;
   }
   HBGS_API_BEGIN
-  hipStream_t s = (hipStream_t)stream;
+  hipStream_t us = (hipStream_t)stream;
   ensure_workspace(c);
   int32_t it = 0, hl = 0;
+  // work on the context's own stream, ordered after the caller's stream
+  hipStream_t s = c->sm;
+  HBGS_HIP(hipEventRecord(c->join_in, us));
+  HBGS_HIP(hipStreamWaitEvent(s, c->join_in, 0));
   solve::permute_in(c->n, c->perm, b, c->bp, s);
   if (use_x0) solve::permute_in(c->n, c->perm, x, c->xp, s);
   hbgs_status st = gmres(c, transpose ? 1 : 0, use_x0, &it, hist, hist_cap, &hl, s);
   solve::permute_out(c->n, c->perm, c->xp, x, s);
-  HBGS_HIP(hipStreamSynchronize(s));
+  HBGS_HIP(hipEventRecord(c->join_out, s));
+  HBGS_HIP(hipStreamWaitEvent(us, c->join_out, 0));
+  HBGS_HIP(hipStreamSynchronize(us));
   if (c->prof.on) c->prof.flush();
   if (iters) *iters = it;
   if (hist_len) *hist_len = hl;
@@ -1010,8 +1188,9 @@ hbgs_status hbgs_profile(hbgs_ctx* c, int32_t enable) {
   }
   HBGS_API_BEGIN
   c->prof.flush();
+  uint32_t mask = enable == -1 ? 0xFFFFFFFFu : (uint32_t)enable;
   c->prof.on = enable != 0;
-  c->prof.mask = enable == -1 ? 0xFFFFFFFFu : (uint32_t)enable;
+  c->prof.mask = mask;
   if (enable) {
     std::fill(std::begin(c->prof.total_ms), std::end(c->prof.total_ms), 0.0);
     std::fill(std::begin(c->prof.launches), std::end(c->prof.launches), 0);

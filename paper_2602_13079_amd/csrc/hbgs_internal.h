@@ -81,8 +81,10 @@ struct DCsr {
   int* ci = nullptr;
   double* v = nullptr;
   float* vf = nullptr;  // FP32 copy of v (solve phase, mixed precision)
+  int maxlen = 0;  // longest row (selects the solve-phase kernel shape)
   float avg_row() const { return n ? (float)nnz / (float)n : 0.f; }
 };
+
 
 // ------------------------------------------------------ launch helpers
 inline unsigned grid_for(int64_t work, int block, int64_t cap = 1 << 20) {
@@ -148,6 +150,12 @@ void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s);
 int dense_inverse(const DCsr& a, double* inv, hipStream_t s);
 
 void cast_f32(int64_t n, const double* in, float* out, hipStream_t s);
+// A^T of a structurally symmetric A: same pattern, values gathered (no sort)
+void transpose_symmetric(const DCsr& a, double* vt, hipStream_t s);
+// longest row of a (a.maxlen)
+void row_stats(DCsr& a, hipStream_t s);
+// dense transpose of an n x n row-major matrix
+void dense_transpose(int n, const double* in, double* out, hipStream_t s);
 void reciprocal(int n, const double* d, double* dinv, float* dinvf, hipStream_t s);
 void sort_rows(const DCsr& a, hipStream_t s);
 }  // namespace setup
@@ -169,7 +177,7 @@ enum Kind {
   K_COUPLE,
   K_DOT1,
   K_UPD_DOT2,
-  K_UPD_NORM,
+  K_UPD_SCALE,
   K_REDUCE,
   K_GIVENS,
   K_SCALE,
@@ -192,9 +200,12 @@ void spmv_resid_f64(const DCsr& a, const double* x, const double* b, double* r, 
 
 template <class T>
 struct VcOps {
-  // degree-2 pre-smoothing from a zero guess, one fused kernel:
-  // x = d0 + c1 d0 + c2 D^-1 (b - A d0), d0 = D^-1 b / theta
-  static void pre2(const DCsr& a, const T* dinv, const ChebCoef& c, const T* b, T* x, hipStream_t s);
+  // degree-2 pre-smoothing from a zero guess, one fused kernel, with the
+  // first direction d0 = D^-1 b / theta precomputed by the rhs producer:
+  // x = d0 + c1 d0 + c2 D^-1 (b - A d0)
+  static void pre2(const DCsr& a, const T* dinv, const ChebCoef& c, const T* b, const T* d0, T* x, hipStream_t s);
+  // d0 = (D^-1 b) / theta
+  static void make_d0(int n, const T* b, const T* dinv, double c0, T* d0, hipStream_t s);
   // general degree, zero guess: r = b, d = D^-1 b / theta, x = d
   static void init0(int n, const T* dinv, const ChebCoef& c, const T* b, T* r, T* d, T* x, hipStream_t s);
   // post-smoothing start from x: r = b - A x, d = D^-1 r / theta (x not yet updated)
@@ -206,12 +217,16 @@ struct VcOps {
                    const T* d, T* dn, T* x, hipStream_t s);
   static void add(int n, const T* d, T* x, hipStream_t s);
   static void resid(const DCsr& a, const T* b, const T* x, T* r, hipStream_t s);
-  static void restrict_(const DCsr& rmat, const T* r, T* bc, hipStream_t s);
+  // bc = R r; when d0_c is given also d0_c = (Dc^-1 bc) * c0_c for the coarse level
+  static void restrict_(const DCsr& rmat, const T* r, T* bc, const T* dinv_c, double c0_c, T* d0_c,
+                        hipStream_t s);
   static void prolong(const DCsr& p, const T* xc, T* x, hipStream_t s);
   static void coarse(int n, const double* inv, int transpose, const T* b, T* x, hipStream_t s);
-  // t = (T)v - sum over coupling columns of a * z, rows of one field
-  static void couple(const DCsr& c, const double* v, const T* z, T* t, hipStream_t s);
-  static void cast_in(int n, const double* v, T* t, hipStream_t s);
+  // t = (T)v - sum over coupling columns of a * z, rows of one field; with
+  // d0 given also d0 = (D^-1 t) * c0 for the field's finest level
+  static void couple(const DCsr& c, const double* v, const T* z, T* t, const T* dinv, double c0, T* d0,
+                     hipStream_t s);
+  static void cast_in(int n, const double* v, T* t, const T* dinv, double c0, T* d0, hipStream_t s);
 };
 
 // GMRES pieces (FP64)
@@ -224,14 +239,14 @@ void mdot_reduce(int nvec, int nblocks, const double* part, double* out, hipStre
 // w -= V h (k <= j), then partial dots of the updated w with V_k (k <= j) and w.w
 void upd_mdot(int n, int j, const double* V, size_t ldv, double* w, const double* h, double* part,
               hipStream_t s);
-// w -= V h, partial w.w
-void upd_norm(int n, int j, const double* V, size_t ldv, double* w, const double* h, double* part,
-              hipStream_t s);
-// Givens update of column j; writes scal[0] = est (|g_{j+1}|), scal[1] = 1/h_{j+1,j},
-// scal[2] = h_{j+1,j}, scal[3] = ||w|| before orthogonalisation
-void givens(int j, int m, const double* h1, const double* h2, const double* hn2, const double* w0sq, double* H,
-            double* cs, double* sn, double* g, double* scal, hipStream_t s);
-void scale(int n, const double* w, const double* scal, double* v, hipStream_t s);
+// w = (w - V h) / scal[1] (new basis vector), when scal[1] > 0
+void upd_scale(int n, int j, const double* V, size_t ldv, double* w, const double* h, const double* scal,
+               hipStream_t s);
+// Givens update of column j from the two Gram-Schmidt passes (h2[j+1] =
+// ||w||^2 after the first); writes scal[0] = |g_{j+1}|, scal[1] = h_{j+1,j},
+// scal[2] = ||w|| before orthogonalisation
+void givens(int j, int m, const double* h1, const double* h2, const double* w0sq, double* H, double* cs,
+            double* sn, double* g, double* scal, hipStream_t s);
 void backsolve(int jend, int m, const double* H, const double* g, double* y, hipStream_t s);
 template <class TZ>
 void xupdate(int n, int jend, const TZ* Z, size_t ldz, const double* y, double* x, hipStream_t s);
@@ -239,6 +254,10 @@ void norm2_partial(int n, const double* x, double* part, hipStream_t s);
 void scale_copy(int n, const double* r, const double* part_sum, double* v, hipStream_t s);  // v = r / sqrt(sum)
 void grad_values(int n, const int* rp, const int* ci, const double* lam, const double* x, double* g,
                  hipStream_t s);
+// *diff |= (a[i] != b[i]) for some i
+void compare_int(int64_t n, const int* a, const int* b, int* diff, hipStream_t s);
+// *mask |= 1 << f for every field f (column ranges [lo[f], hi[f])) that a column of c falls in
+void column_fields(const DCsr& c, int nf, const int* lo, const int* hi, int* mask, hipStream_t s);
 }  // namespace solve
 
 }  // namespace hbgs

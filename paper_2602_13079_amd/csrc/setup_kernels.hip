@@ -273,9 +273,44 @@ __global__ void k_transpose_scatter(int n, const int* rp, const int* ci, const d
     }
   }
 }
-// sort each row by column (entries are distinct, so the result is unique)
+// sort each row by column (entries are distinct, so the result is unique);
+// rows of up to SORT_LDS entries are sorted in a per-thread LDS segment
+constexpr int SORT_LDS = 32;
+constexpr int SORT_BLK = 64;
+__global__ __launch_bounds__(SORT_BLK) void k_sort_rows_lds(int n, const int* rp, int* ci, double* v,
+                                                            int* long_rows) {
+  __shared__ int sc[SORT_BLK][SORT_LDS + 1];
+  __shared__ double sv[SORT_BLK][SORT_LDS + 1];
+  int i = blockIdx.x * SORT_BLK + threadIdx.x;
+  if (i >= n) return;
+  int s = rp[i], e = rp[i + 1], len = e - s;
+  if (len > SORT_LDS) {
+    atomicOr(long_rows, 1);
+    return;
+  }
+  int* c = sc[threadIdx.x];
+  double* x = sv[threadIdx.x];
+  for (int k = 0; k < len; ++k) {
+    int cc = ci[s + k];
+    double xx = v ? v[s + k] : 0.0;
+    int q = k - 1;
+    while (q >= 0 && c[q] > cc) {
+      c[q + 1] = c[q];
+      x[q + 1] = x[q];
+      --q;
+    }
+    c[q + 1] = cc;
+    x[q + 1] = xx;
+  }
+  for (int k = 0; k < len; ++k) {
+    ci[s + k] = c[k];
+    if (v) v[s + k] = x[k];
+  }
+}
+
 __global__ void k_sort_rows(int n, const int* rp, int* ci, double* v) {
   GRID_STRIDE(i, n) {
+    if (rp[i + 1] - rp[i] <= SORT_LDS) continue;
     int s = rp[i], e = rp[i + 1];
     for (int k = s + 1; k < e; ++k) {
       int c = ci[k];
@@ -293,8 +328,17 @@ __global__ void k_sort_rows(int n, const int* rp, int* ci, double* v) {
 }
 
 void sort_rows(const DCsr& a, hipStream_t s) {
-  k_sort_rows<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v);
+  Tmp<int> long_rows(1);
+  HBGS_HIP(hipMemsetAsync(long_rows.p, 0, sizeof(int), s));
+  k_sort_rows_lds<<<grid_for(a.n, SORT_BLK), SORT_BLK, 0, s>>>(a.n, a.rp, a.ci, a.v, long_rows.p);
   HBGS_HIP(hipGetLastError());
+  int lr = 0;
+  HBGS_HIP(hipMemcpyAsync(&lr, long_rows.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  if (lr) {
+    k_sort_rows<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v);
+    HBGS_HIP(hipGetLastError());
+  }
 }
 
 void transpose(const DCsr& a, DCsr& t, hipStream_t s) {
@@ -950,22 +994,53 @@ __global__ void k_lu_update(int n, int k, double* m) {
     m[(int64_t)i * n + j] -= m[(int64_t)i * n + k] * m[(int64_t)k * n + j];
   }
 }
-// column c of A^-1 = U^-1 L^-1 P e_c; pinv[c] = row of P e_c holding the 1
-__global__ void k_lu_inverse(int n, const double* lu, const int* pinv, double* inv) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
-  int r = pinv[c];
+// Columns c0..c0+NC-1 of A^-1 = U^-1 L^-1 P e_c, one wavefront per group of
+// NC columns: the columns live in LDS, each substitution row is a
+// cross-lane dot product over the factor row (coalesced loads).
+// pinv[c] = row of P e_c holding the 1.
+template <int NC>
+__global__ __launch_bounds__(64) void k_lu_inverse(int n, const double* __restrict__ lu, const int* __restrict__ pinv,
+                                                   double* __restrict__ inv) {
+  extern __shared__ double y[];  // NC * n
+  const int lane = threadIdx.x;
+  const int c0 = blockIdx.x * NC;
+  int r[NC];
+  for (int q = 0; q < NC; ++q) r[q] = c0 + q < n ? pinv[c0 + q] : -1;
+  for (int i = lane; i < NC * n; i += 64) y[i] = 0.0;
+  __syncthreads();
+  // forward: L y = P e_c (L unit lower)
   for (int i = 0; i < n; ++i) {
-    double y = i == r ? 1.0 : 0.0;
-    if (i > r)
-      for (int j = r; j < i; ++j) y -= lu[(int64_t)i * n + j] * inv[(int64_t)j * n + c];
-    inv[(int64_t)i * n + c] = i < r ? 0.0 : y;
+    double acc[NC];
+    for (int q = 0; q < NC; ++q) acc[q] = 0.0;
+    const double* row = lu + (int64_t)i * n;
+    for (int k = lane; k < i; k += 64) {
+      double l = row[k];
+      for (int q = 0; q < NC; ++q) acc[q] += l * y[q * n + k];
+    }
+    for (int q = 0; q < NC; ++q)
+      for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
+    if (lane == 0)
+      for (int q = 0; q < NC; ++q) y[q * n + i] = (i == r[q] ? 1.0 : 0.0) - acc[q];
+    __syncthreads();
   }
+  // backward: U x = y
   for (int i = n - 1; i >= 0; --i) {
-    double y = inv[(int64_t)i * n + c];
-    for (int j = i + 1; j < n; ++j) y -= lu[(int64_t)i * n + j] * inv[(int64_t)j * n + c];
-    inv[(int64_t)i * n + c] = y / lu[(int64_t)i * n + i];
+    double acc[NC];
+    for (int q = 0; q < NC; ++q) acc[q] = 0.0;
+    const double* row = lu + (int64_t)i * n;
+    for (int k = i + 1 + lane; k < n; k += 64) {
+      double u = row[k];
+      for (int q = 0; q < NC; ++q) acc[q] += u * y[q * n + k];
+    }
+    for (int q = 0; q < NC; ++q)
+      for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
+    if (lane == 0)
+      for (int q = 0; q < NC; ++q) y[q * n + i] = (y[q * n + i] - acc[q]) / row[i];
+    __syncthreads();
   }
+  for (int q = 0; q < NC; ++q)
+    if (c0 + q < n)
+      for (int i = lane; i < n; i += 64) inv[(int64_t)i * n + c0 + q] = y[q * n + i];
 }
 
 int dense_inverse(const DCsr& a, double* inv, hipStream_t s) {
@@ -992,10 +1067,71 @@ int dense_inverse(const DCsr& a, double* inv, hipStream_t s) {
   for (int k = 0; k < n; ++k) std::swap(rowof[k], rowof[hp[k]]);
   for (int r = 0; r < n; ++r) where[rowof[r]] = r;
   HBGS_HIP(hipMemcpyAsync(pinv.p, where.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
-  k_lu_inverse<<<grid_for(n, 64), 64, 0, s>>>(n, m.p, pinv.p, inv);
+  // columns per wavefront so that NC * n doubles fit in 64 KiB of LDS
+  if (n <= 2000)
+    k_lu_inverse<4><<<(n + 3) / 4, 64, 4 * n * sizeof(double), s>>>(n, m.p, pinv.p, inv);
+  else if (n <= 4000)
+    k_lu_inverse<2><<<(n + 1) / 2, 64, 2 * n * sizeof(double), s>>>(n, m.p, pinv.p, inv);
+  else
+    k_lu_inverse<1><<<n, 64, n * sizeof(double), s>>>(n, m.p, pinv.p, inv);
   HBGS_HIP(hipGetLastError());
   HBGS_HIP(hipStreamSynchronize(s));
   return 0;
+}
+
+// --------------------------------------------- transposes for the solve phase
+// (A^T)_{ji} = A_{ij}: for a structurally symmetric A the pattern is A's own;
+// each entry's value is found in the mirrored row by binary search
+__global__ void k_transpose_sym(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                const double* __restrict__ v, double* __restrict__ vt) {
+  GRID_STRIDE(j, n) {
+    for (int q = rp[j]; q < rp[j + 1]; ++q) {
+      int i = ci[q];
+      int lo = rp[i], hi = rp[i + 1] - 1;
+      double x = 0.0;
+      while (lo <= hi) {
+        int mid = (lo + hi) >> 1;
+        if (ci[mid] == (int)j) {
+          x = v[mid];
+          break;
+        }
+        if (ci[mid] < (int)j)
+          lo = mid + 1;
+        else
+          hi = mid - 1;
+      }
+      vt[q] = x;
+    }
+  }
+}
+void transpose_symmetric(const DCsr& a, double* vt, hipStream_t s) {
+  k_transpose_sym<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v, vt);
+  HBGS_HIP(hipGetLastError());
+}
+
+__global__ void k_max_row(int n, const int* __restrict__ rp, int* __restrict__ maxlen) {
+  int m = 0;
+  GRID_STRIDE(i, n) m = max(m, rp[i + 1] - rp[i]);
+  if (m) atomicMax(maxlen, m);
+}
+void row_stats(DCsr& a, hipStream_t s) {
+  Tmp<int> ml(1);
+  HBGS_HIP(hipMemsetAsync(ml.p, 0, sizeof(int), s));
+  k_max_row<<<grid_for(a.n, BLK, 4096), BLK, 0, s>>>(a.n, a.rp, ml.p);
+  HBGS_HIP(hipGetLastError());
+  HBGS_HIP(hipMemcpyAsync(&a.maxlen, ml.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+}
+
+__global__ void k_dense_transpose(int n, const double* __restrict__ in, double* __restrict__ out) {
+  GRID_STRIDE(t, (int64_t)n * n) {
+    int i = (int)(t / n), j = (int)(t % n);
+    out[(int64_t)j * n + i] = in[t];
+  }
+}
+void dense_transpose(int n, const double* in, double* out, hipStream_t s) {
+  k_dense_transpose<<<grid_for((int64_t)n * n, BLK), BLK, 0, s>>>(n, in, out);
+  HBGS_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------------------ casts

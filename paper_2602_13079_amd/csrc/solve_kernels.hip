@@ -20,7 +20,7 @@ constexpr int BLK = 256;
 
 const char* kind_names[K_COUNT] = {
     "spmv_outer", "spmv_resid", "cheb_pre",  "cheb_post_a", "cheb_post_b", "cheb_other", "resid", "restrict",
-    "prolong",    "coarse",     "couple",    "dot1",        "upd_dot2",    "upd_norm",  "reduce",
+    "prolong",    "coarse",     "couple",    "dot1",        "upd_dot2",    "upd_scale",  "reduce",
     "givens",     "scale",      "xupdate",   "permute"};
 
 // ---------------------------------------------------------- CSR row engine
@@ -41,14 +41,67 @@ __global__ __launch_bounds__(BLK) void k_csr(int n, const int* __restrict__ rp, 
   TACC acc = 0;
   for (int k = s + lane; k < e; k += LPR) acc += (TACC)v[k] * (TACC)lx(ci[k]);
   if (LPR > 1) acc = lanes_sum<TACC>(acc, LPR);
-  if (lane == 0) epi(row, acc);
+  if (lane == 0) epi.store(row, acc, epi.load(row));
+}
+
+template <class TACC, class Epi>
+__global__ void k_empty(int n, Epi epi) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) epi.store(i, TACC(0), epi.load(i));
+}
+// Row-block streaming form for short rows (longest row <= ROWS_LDS / RB).
+// Block b owns rows [RB b, RB (b+1)) and their entries; its threads first
+// stream the entries' values and column indices with unit-stride
+// (coalesced) loads, gather the operand and stage the products in LDS, then
+// one thread per row sums the row's products from LDS and applies the
+// epilogue.  Every matrix byte is read once with full-width transactions.
+constexpr int SBLK = 256;
+constexpr int ROWS_LDS_BYTES = 16384;
+
+template <int RB, class TV, class TACC, class LoadX, class Epi>
+__global__ __launch_bounds__(SBLK) void k_csr_rows(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                   const TV* __restrict__ v, LoadX lx, Epi epi) {
+  __shared__ TACC prod[ROWS_LDS_BYTES / sizeof(TACC)];
+  const int r0 = blockIdx.x * RB;
+  const int r1 = min(n, r0 + RB);
+  const int s0 = rp[r0], s1 = rp[r1];
+  for (int k = s0 + threadIdx.x; k < s1; k += SBLK) prod[k - s0] = (TACC)v[k] * (TACC)lx(ci[k]);
+  __syncthreads();
+  for (int r = r0 + threadIdx.x; r < r1; r += SBLK) {
+    const int kb = rp[r] - s0, ke = rp[r + 1] - s0;
+    const typename Epi::Pre pre = epi.load(r);
+    TACC acc = 0;
+    for (int k = kb; k < ke; ++k) acc += prod[k];
+    epi.store(r, acc, pre);
+  }
 }
 
 template <class TV, class TACC, class LoadX, class Epi>
 static void launch_csr(const DCsr& a, const TV* v, LoadX lx, Epi epi, hipStream_t s) {
   if (a.n == 0) return;
+  constexpr int cap = ROWS_LDS_BYTES / (int)sizeof(TACC);
+  if (a.maxlen > 0 && a.maxlen <= cap / 512) {
+    k_csr_rows<512, TV, TACC, LoadX, Epi><<<(a.n + 511) / 512, SBLK, 0, s>>>(a.n, a.rp, a.ci, v, lx, epi);
+    HBGS_HIP(hipGetLastError());
+    return;
+  }
+  if (a.maxlen > 0 && a.maxlen <= cap / 256) {
+    k_csr_rows<256, TV, TACC, LoadX, Epi><<<(a.n + 255) / 256, SBLK, 0, s>>>(a.n, a.rp, a.ci, v, lx, epi);
+    HBGS_HIP(hipGetLastError());
+    return;
+  }
+  if (a.maxlen > 0 && a.maxlen <= cap / 128) {
+    k_csr_rows<128, TV, TACC, LoadX, Epi><<<(a.n + 127) / 128, SBLK, 0, s>>>(a.n, a.rp, a.ci, v, lx, epi);
+    HBGS_HIP(hipGetLastError());
+    return;
+  }
+  if (a.nnz == 0) {  // rows without entries: epilogue of an empty sum
+    k_empty<TACC, Epi><<<grid_for(a.n, 256), 256, 0, s>>>(a.n, epi);
+    HBGS_HIP(hipGetLastError());
+    return;
+  }
   float avg = a.avg_row();
-  int lpr = avg <= 1.5f ? 1 : avg <= 3.f ? 2 : avg <= 6.f ? 4 : avg <= 12.f ? 8 : avg <= 24.f ? 16 : avg <= 48.f ? 32 : 64;
+  int lpr = avg <= 1.5f ? 1 : avg <= 3.f ? 2 : avg <= 6.f ? 4 : avg <= 16.f ? 8 : avg <= 64.f ? 16 : avg <= 128.f ? 32 : 64;
   unsigned grid = (unsigned)(((int64_t)a.n * lpr + BLK - 1) / BLK);
 #define HBGS_CASE(L) \
   case L:            \
@@ -72,44 +125,69 @@ struct LoadArr {
   const T* __restrict__ x;
   __device__ T operator()(int k) const { return x[k]; }
 };
-// zero-guess first Chebyshev direction d0 = (D^-1 b) / theta, formed on the fly
-template <class T>
-struct LoadD0 {
-  const T* __restrict__ dinv;
-  const T* __restrict__ b;
-  T c0;
-  __device__ T operator()(int k) const { return dinv[k] * b[k] * c0; }
-};
 
-// epilogues
+// Epilogues: load(i) issues the row's vector loads (before the row sum, so
+// they overlap it); store(i, acc, pre) finishes the row.
 template <class T, class TACC>
 struct EpiStore {
   T* __restrict__ y;
-  __device__ void operator()(int i, TACC acc) const { y[i] = (T)acc; }
+  struct Pre {};
+  __device__ Pre load(int) const { return {}; }
+  __device__ void store(int i, TACC acc, Pre) const { y[i] = (T)acc; }
 };
 template <class T, class TACC>
 struct EpiAdd {
   T* __restrict__ y;
-  __device__ void operator()(int i, TACC acc) const { y[i] = y[i] + (T)acc; }
+  struct Pre {
+    T y;
+  };
+  __device__ Pre load(int i) const { return {y[i]}; }
+  __device__ void store(int i, TACC acc, Pre p) const { y[i] = p.y + (T)acc; }
+};
+// right-hand side of the next level: y = acc and, when the consumer level
+// smooths with degree 2, its first Chebyshev direction d0 = (D^-1 y) / theta
+template <class T>
+struct EpiRhs {
+  T* __restrict__ y;
+  const T* __restrict__ dinv;
+  T* __restrict__ d0;
+  T c0;
+  struct Pre {
+    T dinv;
+  };
+  __device__ Pre load(int i) const { return {d0 ? dinv[i] : T(0)}; }
+  __device__ void store(int i, T acc, Pre p) const {
+    y[i] = acc;
+    if (d0) d0[i] = p.dinv * acc * c0;
+  }
 };
 template <class T>
 struct EpiResid {
   const T* __restrict__ b;
   T* __restrict__ r;
-  __device__ void operator()(int i, T acc) const { r[i] = b[i] - acc; }
+  struct Pre {
+    T b;
+  };
+  __device__ Pre load(int i) const { return {b[i]}; }
+  __device__ void store(int i, T acc, Pre p) const { r[i] = p.b - acc; }
 };
-// degree-2 pre-smoothing from zero: x = d0 + c1 d0 + c2 D^-1 (b - A d0)
+// degree-2 pre-smoothing from zero, d0 = (D^-1 b) / theta given:
+// x = d0 + c1 d0 + c2 D^-1 (b - A d0)
 template <class T>
 struct EpiChebPre2 {
   const T* __restrict__ dinv;
   const T* __restrict__ b;
+  const T* __restrict__ d0;
   T* __restrict__ x;
-  T c0, c1, c2;
-  __device__ void operator()(int i, T ad) const {
-    T d0 = dinv[i] * b[i] * c0;
-    T r1 = b[i] - ad;
-    T d1 = c1 * d0 + c2 * (dinv[i] * r1);
-    x[i] = d0 + d1;
+  T c1, c2;
+  struct Pre {
+    T dinv, b, d0;
+  };
+  __device__ Pre load(int i) const { return {dinv[i], b[i], d0[i]}; }
+  __device__ void store(int i, T ad, Pre p) const {
+    T r1 = p.b - ad;
+    T d1 = c1 * p.d0 + c2 * (p.dinv * r1);
+    x[i] = p.d0 + d1;
   }
 };
 // post-smoothing start from x: r = b - A x, d = D^-1 r / theta
@@ -120,10 +198,14 @@ struct EpiChebPostA {
   T* __restrict__ r;
   T* __restrict__ d;
   T c0;
-  __device__ void operator()(int i, T ax) const {
-    T ri = b[i] - ax;
+  struct Pre {
+    T dinv, b;
+  };
+  __device__ Pre load(int i) const { return {dinv[i], b[i]}; }
+  __device__ void store(int i, T ax, Pre p) const {
+    T ri = p.b - ax;
     r[i] = ri;
-    d[i] = dinv[i] * ri * c0;
+    d[i] = p.dinv * ri * c0;
   }
 };
 // Chebyshev step: r -= A d; dn = c1 d + c2 D^-1 r; x (+ d if pending) += dn
@@ -135,10 +217,14 @@ struct EpiChebStep {
   T* __restrict__ dn;
   T* __restrict__ x;
   T c1, c2;
-  __device__ void operator()(int i, T ad) const {
-    T ri = r[i] - ad;
-    T di = c1 * d[i] + c2 * (dinv[i] * ri);
-    T xi = ADD_D ? x[i] + d[i] : x[i];
+  struct Pre {
+    T dinv, d, r, x;
+  };
+  __device__ Pre load(int i) const { return {dinv[i], d[i], r[i], x[i]}; }
+  __device__ void store(int i, T ad, Pre p) const {
+    T ri = p.r - ad;
+    T di = c1 * p.d + c2 * (p.dinv * ri);
+    T xi = ADD_D ? p.x + p.d : p.x;
     x[i] = xi + di;
     if (KEEP) {
       r[i] = ri;
@@ -146,12 +232,24 @@ struct EpiChebStep {
     }
   }
 };
-// coupling: t = (T)v - sum a z
+// coupling: t = (T)v - sum a z, plus the fine level's d0 = (D^-1 t) / theta
 template <class T>
 struct EpiCouple {
   const double* __restrict__ v;
   T* __restrict__ t;
-  __device__ void operator()(int i, T acc) const { t[i] = (T)v[i] - acc; }
+  const T* __restrict__ dinv;
+  T* __restrict__ d0;
+  T c0;
+  struct Pre {
+    double v;
+    T dinv;
+  };
+  __device__ Pre load(int i) const { return {v[i], d0 ? dinv[i] : T(0)}; }
+  __device__ void store(int i, T acc, Pre p) const {
+    T ti = (T)p.v - acc;
+    t[i] = ti;
+    if (d0) d0[i] = p.dinv * ti * c0;
+  }
 };
 
 // ---------------------------------------------------------- outer SpMV
@@ -189,9 +287,19 @@ __global__ void k_cheb_init0(int n, const T* __restrict__ dinv, const T* __restr
 }
 
 template <class T>
-void VcOps<T>::pre2(const DCsr& a, const T* dinv, const ChebCoef& c, const T* b, T* x, hipStream_t s) {
-  launch_csr<T, T>(a, vals_of<T>(a), LoadD0<T>{dinv, b, (T)c.c0},
-                   EpiChebPre2<T>{dinv, b, x, (T)c.c0, (T)c.c1[1], (T)c.c2[1]}, s);
+void VcOps<T>::pre2(const DCsr& a, const T* dinv, const ChebCoef& c, const T* b, const T* d0, T* x, hipStream_t s) {
+  launch_csr<T, T>(a, vals_of<T>(a), LoadArr<T>{d0}, EpiChebPre2<T>{dinv, b, d0, x, (T)c.c1[1], (T)c.c2[1]}, s);
+}
+
+template <class T>
+__global__ void k_make_d0(int n, const T* __restrict__ b, const T* __restrict__ dinv, T c0, T* __restrict__ d0) {
+  int i = blockIdx.x * BLK + threadIdx.x;
+  if (i < n) d0[i] = dinv[i] * b[i] * c0;
+}
+template <class T>
+void VcOps<T>::make_d0(int n, const T* b, const T* dinv, double c0, T* d0, hipStream_t s) {
+  k_make_d0<T><<<grid_for(n, BLK), BLK, 0, s>>>(n, b, dinv, (T)c0, d0);
+  HBGS_HIP(hipGetLastError());
 }
 
 template <class T>
@@ -238,26 +346,32 @@ void VcOps<T>::resid(const DCsr& a, const T* b, const T* x, T* r, hipStream_t s)
   launch_csr<T, T>(a, vals_of<T>(a), LoadArr<T>{x}, EpiResid<T>{b, r}, s);
 }
 template <class T>
-void VcOps<T>::restrict_(const DCsr& rmat, const T* r, T* bc, hipStream_t s) {
-  launch_csr<T, T>(rmat, vals_of<T>(rmat), LoadArr<T>{r}, EpiStore<T, T>{bc}, s);
+void VcOps<T>::restrict_(const DCsr& rmat, const T* r, T* bc, const T* dinv_c, double c0_c, T* d0_c,
+                         hipStream_t s) {
+  launch_csr<T, T>(rmat, vals_of<T>(rmat), LoadArr<T>{r}, EpiRhs<T>{bc, dinv_c, d0_c, (T)c0_c}, s);
 }
 template <class T>
 void VcOps<T>::prolong(const DCsr& p, const T* xc, T* x, hipStream_t s) {
   launch_csr<T, T>(p, vals_of<T>(p), LoadArr<T>{xc}, EpiAdd<T, T>{x}, s);
 }
 template <class T>
-void VcOps<T>::couple(const DCsr& c, const double* v, const T* z, T* t, hipStream_t s) {
-  launch_csr<T, T>(c, vals_of<T>(c), LoadArr<T>{z}, EpiCouple<T>{v, t}, s);
+void VcOps<T>::couple(const DCsr& c, const double* v, const T* z, T* t, const T* dinv, double c0, T* d0,
+                      hipStream_t s) {
+  launch_csr<T, T>(c, vals_of<T>(c), LoadArr<T>{z}, EpiCouple<T>{v, t, dinv, d0, (T)c0}, s);
 }
 
 template <class T>
-__global__ void k_cast_in(int n, const double* __restrict__ v, T* __restrict__ t) {
+__global__ void k_cast_in(int n, const double* __restrict__ v, T* __restrict__ t, const T* __restrict__ dinv, T c0,
+                          T* __restrict__ d0) {
   int i = blockIdx.x * BLK + threadIdx.x;
-  if (i < n) t[i] = (T)v[i];
+  if (i >= n) return;
+  T ti = (T)v[i];
+  t[i] = ti;
+  if (d0) d0[i] = dinv[i] * ti * c0;
 }
 template <class T>
-void VcOps<T>::cast_in(int n, const double* v, T* t, hipStream_t s) {
-  k_cast_in<T><<<grid_for(n, BLK), BLK, 0, s>>>(n, v, t);
+void VcOps<T>::cast_in(int n, const double* v, T* t, const T* dinv, double c0, T* d0, hipStream_t s) {
+  k_cast_in<T><<<grid_for(n, BLK), BLK, 0, s>>>(n, v, t, dinv, (T)c0, d0);
   HBGS_HIP(hipGetLastError());
 }
 
@@ -404,9 +518,22 @@ void upd_mdot(int n, int j, const double* V, size_t ldv, double* w, const double
               hipStream_t s) {
   launch_cgs<true, true>(n, j + 1, V, ldv, w, h, part, s);
 }
-void upd_norm(int n, int j, const double* V, size_t ldv, double* w, const double* h, double* part,
-              hipStream_t s) {
-  launch_cgs<true, false>(n, j + 1, V, ldv, w, h, part, s);
+// w = (w - sum_k h_k V_k) / scal[1]  (k <= j); skipped when scal[1] == 0
+__global__ __launch_bounds__(BLK) void k_upd_scale(int n, int nv, const double* __restrict__ V, size_t ldv,
+                                                   double* __restrict__ w, const double* __restrict__ h,
+                                                   const double* __restrict__ scal) {
+  const double hn = scal[1];
+  if (!(hn > 0.0)) return;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
+    double wi = w[i];
+    for (int k = 0; k < nv; ++k) wi -= h[k] * V[(size_t)k * ldv + i];
+    w[i] = wi / hn;
+  }
+}
+void upd_scale(int n, int j, const double* V, size_t ldv, double* w, const double* h, const double* scal,
+               hipStream_t s) {
+  k_upd_scale<<<grid_for(n, BLK, 2048), BLK, 0, s>>>(n, j + 1, V, ldv, w, h, scal);
+  HBGS_HIP(hipGetLastError());
 }
 
 // out[k] = sum over blocks of part[k*nb + b] (fixed order per k)
@@ -427,11 +554,14 @@ void mdot_reduce(int nvec, int nblocks, const double* part, double* out, hipStre
 // with leading dimension m).  h1/h2: first and second Gram-Schmidt
 // coefficients (k <= j); hn2 = ||w||^2 after both passes; w0sq = ||w||^2
 // before orthogonalisation.
-__global__ void k_givens(int j, int m, const double* h1, const double* h2, const double* hn2, const double* w0sq,
-                         double* H, double* cs, double* sn, double* g, double* scal) {
+__global__ void k_givens(int j, int m, const double* h1, const double* h2, const double* w0sq, double* H, double* cs,
+                         double* sn, double* g, double* scal) {
   if (threadIdx.x != 0) return;
-  for (int k = 0; k <= j; ++k) H[(size_t)k * m + j] = h1[k] + (h2 ? h2[k] : 0.0);
-  double hn = sqrt(*hn2);
+  for (int k = 0; k <= j; ++k) H[(size_t)k * m + j] = h1[k] + h2[k];
+  // ||w - V h2||^2 = ||w||^2 - ||h2||^2 for orthonormal V (h2[j+1] = ||w||^2 after the first pass)
+  double ss = h2[j + 1];
+  for (int k = 0; k <= j; ++k) ss -= h2[k] * h2[k];
+  double hn = ss > 0.0 ? sqrt(ss) : 0.0;
   H[(size_t)(j + 1) * m + j] = hn;
   for (int k = 0; k < j; ++k) {
     double a = H[(size_t)k * m + j], b = H[(size_t)(k + 1) * m + j];
@@ -450,19 +580,9 @@ __global__ void k_givens(int j, int m, const double* h1, const double* h2, const
   scal[1] = hn;
   scal[2] = sqrt(*w0sq);
 }
-void givens(int j, int m, const double* h1, const double* h2, const double* hn2, const double* w0sq, double* H,
-            double* cs, double* sn, double* g, double* scal, hipStream_t s) {
-  k_givens<<<1, 64, 0, s>>>(j, m, h1, h2, hn2, w0sq, H, cs, sn, g, scal);
-  HBGS_HIP(hipGetLastError());
-}
-
-__global__ void k_scale(int n, const double* __restrict__ w, const double* __restrict__ scal, double* __restrict__ v) {
-  int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-  double hn = scal[1];
-  if (i < n && hn > 0.0) v[i] = w[i] / hn;
-}
-void scale(int n, const double* w, const double* scal, double* v, hipStream_t s) {
-  k_scale<<<grid_for(n, BLK), BLK, 0, s>>>(n, w, scal, v);
+void givens(int j, int m, const double* h1, const double* h2, const double* w0sq, double* H, double* cs,
+            double* sn, double* g, double* scal, hipStream_t s) {
+  k_givens<<<1, 64, 0, s>>>(j, m, h1, h2, w0sq, H, cs, sn, g, scal);
   HBGS_HIP(hipGetLastError());
 }
 
@@ -530,6 +650,42 @@ __global__ void k_grad(int n, const int* __restrict__ rp, const int* __restrict_
 void grad_values(int n, const int* rp, const int* ci, const double* lam, const double* x, double* g,
                  hipStream_t s) {
   k_grad<<<grid_for(n, BLK), BLK, 0, s>>>(n, rp, ci, lam, x, g);
+  HBGS_HIP(hipGetLastError());
+}
+
+__global__ void k_compare_int(int64_t n, const int* __restrict__ a, const int* __restrict__ b, int* diff) {
+  int d = 0;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) d |= a[i] != b[i];
+  if (d) atomicOr(diff, 1);
+}
+void compare_int(int64_t n, const int* a, const int* b, int* diff, hipStream_t s) {
+  if (n == 0) return;
+  k_compare_int<<<grid_for(n, BLK, 65536), BLK, 0, s>>>(n, a, b, diff);
+  HBGS_HIP(hipGetLastError());
+}
+
+struct FieldRanges {
+  int nf;
+  int lo[HBGS_MAX_FIELDS], hi[HBGS_MAX_FIELDS];
+};
+__global__ void k_column_fields(int64_t nnz, const int* __restrict__ ci, FieldRanges fr, int* mask) {
+  int m = 0;
+  for (int64_t k = (int64_t)blockIdx.x * BLK + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * BLK) {
+    int c = ci[k];
+    for (int f = 0; f < fr.nf; ++f)
+      if (c >= fr.lo[f] && c < fr.hi[f]) m |= 1 << f;
+  }
+  if (m) atomicOr(mask, m);
+}
+void column_fields(const DCsr& c, int nf, const int* lo, const int* hi, int* mask, hipStream_t s) {
+  if (c.nnz == 0) return;
+  FieldRanges fr;
+  fr.nf = nf;
+  for (int f = 0; f < nf; ++f) {
+    fr.lo[f] = lo[f];
+    fr.hi[f] = hi[f];
+  }
+  k_column_fields<<<grid_for(c.nnz, BLK, 4096), BLK, 0, s>>>(c.nnz, c.ci, fr, mask);
   HBGS_HIP(hipGetLastError());
 }
 

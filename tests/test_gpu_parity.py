@@ -185,10 +185,15 @@ def test_preconditioner_duality(torch_dev, case):
 
 
 def test_gradient_values_and_autograd(torch_dev):
+    """Differentiable solve: dL/dval and dL/db from the adjoint solve match
+    dense linear algebra; the j0 gradient assembled through the derivative
+    map equals its closed form.  rtol = 1e-11 is the attainable accuracy of
+    this cond ~1e8 system (its true residual stalls near 1e-12)."""
     torch, dev = torch_dev
     import paper_2602_13079_amd as H
     s = synth.make_system(4, 3, 6, 3, seed=20)
-    g = _solver(torch, dev, s, coarse_max=30, rtol=1e-13)
+    rtol = 1e-11
+    g = _solver(torch, dev, s, coarse_max=30, rtol=rtol)
     val = torch.from_numpy(s.val).to(dev).requires_grad_(True)
     b = torch.from_numpy(s.b).to(dev).requires_grad_(True)
     x = H.hbgs_solve(val, b, g)
@@ -197,24 +202,25 @@ def test_gradient_values_and_autograd(torch_dev):
     loss.backward()
     A = sp.csr_matrix((s.val, s.col, s.rowptr), shape=(s.n, s.n)).toarray()
     xd = np.linalg.solve(A, s.b)
-    lam = np.linalg.solve(A.T, xd - s.x_t)
+    lam_d = np.linalg.solve(A.T, xd - s.x_t)
     row = np.repeat(np.arange(s.n), np.diff(s.rowptr))
-    gv_ref = -lam[row] * xd[s.col]
+    gv_ref = -lam_d[row] * xd[s.col]
     k = np.linalg.cond(A)
     gv = val.grad.cpu().numpy()
-    assert np.linalg.norm(gv - gv_ref) <= 100 * k * 1e-13 * np.linalg.norm(gv_ref)
-    assert np.linalg.norm(b.grad.cpu().numpy() - lam) <= 100 * k * 1e-13 * np.linalg.norm(lam)
+    lam = b.grad.cpu().numpy()
+    assert np.linalg.norm(lam - lam_d) <= k * rtol * np.linalg.norm(lam_d)
+    assert np.linalg.norm(gv - gv_ref) <= 2 * k * rtol * np.linalg.norm(gv_ref)
     # grad_values is exactly -lambda[row] * x[col]
-    lt, xx = torch.from_numpy(lam).to(dev), torch.from_numpy(xd).to(dev)
-    assert np.array_equal(g.grad_values(lt, xx).cpu().numpy(), -lam[row] * xd[s.col])
+    xg = x.detach().cpu().numpy()
+    assert np.array_equal(gv, -lam[row] * xg[s.col])
     # j0 gradient via the derivative map equals the closed form per cell
     m = s.dcell >= 0
     gj = np.bincount(s.dcell[m], weights=gv[m] * s.dcoef[m], minlength=len(s.j0))
     nf = s.nf
-    for c in np.flatnonzero((s.layer == 1) | (s.layer == 3))[:6]:
-        cf = (xd[nf * c] - xd[nf * c + 1]) * (-(lam[nf * c] - lam[nf * c + 1])
+    for c in np.flatnonzero((s.layer == 1) | (s.layer == 3)):
+        cf = (xg[nf * c] - xg[nf * c + 1]) * (-(lam[nf * c] - lam[nf * c + 1])
                                               + 0.5 * sum(lam[nf * c + 3 + q] for q in range(3)))
-        assert gj[c] == pytest.approx(cf, rel=1e-6, abs=1e-12)
+        assert gj[c] == pytest.approx(cf, rel=1e-12, abs=1e-14 * np.abs(gj).max())
 
 
 def test_edge_cases(torch_dev):
@@ -338,3 +344,29 @@ def test_full_size_solve_cfg2(torch_dev, precision):
     assert st == 0
     assert _true_res(s, lam.cpu().numpy(), s.x_t, transpose=True) <= 1e-8
     g.set_precision(0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replays_match_eager(torch_dev, precision):
+    """Each GMRES step is replayed from a captured HIP graph: every replay
+    (across solves, forward and adjoint, with eager library work and host
+    synchronisation in between) gives bitwise the eager result."""
+    torch, dev = torch_dev
+    s = _system("ragged7x5x9_6f_cm40")
+    ge = _solver(torch, dev, s, coarse_max=40, use_graphs=0, precision=precision)
+    gg = _solver(torch, dev, s, coarse_max=40, use_graphs=1, precision=precision)
+    b = torch.from_numpy(s.b).to(dev)
+    xt = torch.from_numpy(s.x_t).to(dev)
+    xe, ste, ite, he = ge.solve(b)
+    le, _, _, _ = ge.solve(xt, transpose=True)
+    r = torch.from_numpy(np.random.default_rng(5).standard_normal(s.n)).to(dev)
+    for rep in range(3):
+        xg, stg, itg, hg = gg.solve(b)
+        assert stg == ste and itg == ite
+        assert torch.equal(xg, xe), rep
+        assert np.array_equal(hg, he)
+        zg = gg.apply(r)  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(zg, ge.apply(r))
+        lg, _, _, _ = gg.solve(xt, transpose=True)
+        assert torch.equal(lg, le), rep
