@@ -106,12 +106,19 @@ hbgs_status hbgs_setup(hbgs_ctx **out, int32_t n, int64_t nnz, const int32_t *ro
                        const int32_t *field_of_row, int32_t tree_len, const int32_t *group_tree,
                        const hbgs_options *opt, void *stream);
 
-/* Replace A's values (same pattern as at setup; device pointer, nnz entries)
- * and rebuild the hierarchy. */
-hbgs_status hbgs_set_values(hbgs_ctx *ctx, const double *val, void *stream);
+/* Replace A's values (same pattern as at setup; device pointer, nnz entries).
+ * rebuild_hierarchy != 0 rebuilds the whole preconditioner from the new
+ * values; 0 replaces only the operator GMRES iterates with (and its
+ * transpose) and keeps the current preconditioner, which then acts as a
+ * preconditioner for the new matrix (e.g. for small perturbations). */
+hbgs_status hbgs_set_values(hbgs_ctx *ctx, const double *val, int32_t rebuild_hierarchy, void *stream);
 
 /* Select the precision mode of later apply/solve calls (0 FP64, 1 mixed). */
 hbgs_status hbgs_set_precision(hbgs_ctx *ctx, int32_t precision);
+
+/* Change the stopping rule of later solves: true relative residual rtol
+ * (>= 0) and the cap on Arnoldi steps (>= 0). */
+hbgs_status hbgs_set_tolerance(hbgs_ctx *ctx, double rtol, int32_t max_iters);
 
 /* z = M^-1 r (transpose = 0) or z = M^-T r (transpose = 1): one block
  * Gauss-Seidel sweep (forward: lower, leaves in order; transposed: upper,

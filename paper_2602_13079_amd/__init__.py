@@ -53,8 +53,9 @@ class Stats(ctypes.Structure):
 EXPORTS = {
     "hbgs_default_options": (None, ["opt*"]),
     "hbgs_setup": ("i32", ["ctx**", "i32", "i64", "p", "p", "p", "i32", "p", "i32", "p", "opt*", "p"]),
-    "hbgs_set_values": ("i32", ["p", "p", "p"]),
+    "hbgs_set_values": ("i32", ["p", "p", "i32", "p"]),
     "hbgs_set_precision": ("i32", ["p", "i32"]),
+    "hbgs_set_tolerance": ("i32", ["p", "f64", "i32"]),
     "hbgs_apply": ("i32", ["p", "p", "p", "i32", "p"]),
     "hbgs_solve": ("i32", ["p", "p", "p", "i32", "i32", "i32*", "p", "i32", "i32*", "p"]),
     "hbgs_grad_values": ("i32", ["p", "p", "p", "p", "p"]),
@@ -70,7 +71,8 @@ EXPORTS = {
 
 def _ctype(t):
     return {
-        "i32": ctypes.c_int32, "i64": ctypes.c_int64, "p": ctypes.c_void_p, "str": ctypes.c_char_p,
+        "i32": ctypes.c_int32, "i64": ctypes.c_int64, "f64": ctypes.c_double, "p": ctypes.c_void_p,
+        "str": ctypes.c_char_p,
         "ctx**": ctypes.POINTER(ctypes.c_void_p), "opt*": ctypes.POINTER(Options),
         "stats*": ctypes.POINTER(Stats), "i32*": ctypes.POINTER(ctypes.c_int32),
         "i64*": ctypes.POINTER(ctypes.c_int64), None: None,
@@ -159,9 +161,14 @@ class Solver:
     def set_precision(self, p: int):
         _check(self.lib.hbgs_set_precision(self.h, p))
 
-    def set_values(self, val):
+    def set_tolerance(self, rtol, max_iters=2000):
+        _check(self.lib.hbgs_set_tolerance(self.h, float(rtol), int(max_iters)))
+        self.opts.rtol, self.opts.max_iters = rtol, max_iters
+
+    def set_values(self, val, rebuild=True):
+        """New values on the same pattern; rebuild=False keeps the preconditioner."""
         val = _dev(val, self._torch.float64, self._torch)
-        _check(self.lib.hbgs_set_values(self.h, val.data_ptr(), _stream(self._torch)))
+        _check(self.lib.hbgs_set_values(self.h, val.data_ptr(), int(rebuild), _stream(self._torch)))
 
     def apply(self, r, transpose=False):
         torch = self._torch

@@ -1040,7 +1040,7 @@ __global__ void k_gather_vals(int64_t nnz, const double* v, const int* src, doub
   if (k < nnz) vp[k] = v[src[k]];
 }
 
-hbgs_status hbgs_set_values(hbgs_ctx* c, const double* val, void* stream) {
+hbgs_status hbgs_set_values(hbgs_ctx* c, const double* val, int32_t rebuild_hierarchy, void* stream) {
   if (!c || !val) {
     set_error("NULL argument");
     return HBGS_EINVAL;
@@ -1052,8 +1052,12 @@ hbgs_status hbgs_set_values(hbgs_ctx* c, const double* val, void* stream) {
   HBGS_HIP(hipGetLastError());
   // A^T values: transpose again (same pattern)
   setup::transpose(c->Ap, c->ApT, s);
-  build_values(c, s);
-  c->stats.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (rebuild_hierarchy) {
+    build_values(c, s);
+    c->stats.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  } else {
+    HBGS_HIP(hipStreamSynchronize(s));
+  }
   return HBGS_OK;
   HBGS_API_END
 }
@@ -1064,6 +1068,16 @@ hbgs_status hbgs_set_precision(hbgs_ctx* c, int32_t precision) {
     return HBGS_EINVAL;
   }
   c->precision = precision;
+  return HBGS_OK;
+}
+
+hbgs_status hbgs_set_tolerance(hbgs_ctx* c, double rtol, int32_t max_iters) {
+  if (!c || !(rtol >= 0.0) || max_iters < 0) {
+    set_error("invalid tolerance");
+    return HBGS_EINVAL;
+  }
+  c->o.rtol = rtol;
+  c->o.max_iters = max_iters;
   return HBGS_OK;
 }
 

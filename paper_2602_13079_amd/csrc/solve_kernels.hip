@@ -35,7 +35,7 @@ template <int LPR, class TV, class TACC, class LoadX, class Epi>
 __global__ __launch_bounds__(BLK) void k_csr(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                              const TV* __restrict__ v, LoadX lx, Epi epi) {
   const int lane = threadIdx.x & (LPR - 1);
-  const int row = (int)((blockIdx.x * (unsigned)BLK + threadIdx.x) / LPR);
+  const int row = (int)(((int64_t)blockIdx.x * BLK + threadIdx.x) / LPR);
   if (row >= n) return;
   const int s = rp[row], e = rp[row + 1];
   TACC acc = 0;
