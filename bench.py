@@ -22,7 +22,8 @@ sys.path.insert(0, ROOT)
 METRIC = "solve s to 1e-8 rel resid (fp64 vs mixed), V-cycle HBM GB/s, at 4.2M DOF"
 HBM_PEAK_GBS = 8000.0
 VCYCLE_KINDS = ("cheb_pre", "cheb_post_a", "cheb_post_b", "cheb_other", "resid", "restrict", "prolong", "coarse",
-                "couple")
+                "couple", "cheb_pre_c", "cheb_post_a_c", "cheb_post_b_c", "cheb_other_c", "resid_c", "restrict_c",
+                "prolong_c")
 
 
 def log(*a):
@@ -60,7 +61,9 @@ def main():
     st0 = solver.stats()
     log("levels", st0["levels"], "rows", st0["rows"])
 
-    def step():
+    def step(prof_kinds=None):
+        """One pass of the hot path.  prof_kinds: kernel classes to time with
+        events during the mixed forward solve only (None: no timing)."""
         r = {}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -68,7 +71,11 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         solver.set_precision(1)
+        if prof_kinds is not None:
+            solver.profile(True, kinds=prof_kinds)
         x, stm, itm, hm = solver.solve(b)
+        if prof_kinds is not None:
+            solver.profile(False)
         t2 = time.perf_counter()
         solver.set_precision(0)
         x64, st64, it64, h64 = solver.solve(b)
@@ -76,34 +83,42 @@ def main():
         solver.set_precision(1)
         lam, sta, ita, _ = solver.solve(x - xt, transpose=True)
         t4 = time.perf_counter()
+        solver.set_precision(0)
+        lam64, sta64, ita64, _ = solver.solve(x64 - xt, transpose=True)
+        t5 = time.perf_counter()
         g = solver.grad_values(lam, x)
         torch.cuda.synchronize()
-        t5 = time.perf_counter()
-        assert stm == 0 and st64 == 0 and sta == 0, (stm, st64, sta)
-        r.update(setup_s=t1 - t0, mixed_s=t2 - t1, fp64_s=t3 - t2, adjoint_s=t4 - t3, grad_s=t5 - t4,
-                 it_mixed=itm, it_fp64=it64, it_adjoint=ita, res_mixed=hm[-1], res_fp64=h64[-1],
+        t6 = time.perf_counter()
+        assert stm == 0 and st64 == 0 and sta == 0 and sta64 == 0, (stm, st64, sta, sta64)
+        r.update(setup_s=t1 - t0, mixed_s=t2 - t1, fp64_s=t3 - t2, adjoint_s=t4 - t3, adjoint64_s=t5 - t4,
+                 grad_s=t6 - t5, it_mixed=itm, it_fp64=it64, it_adjoint=ita, it_adjoint64=ita64,
+                 res_mixed=hm[-1], res_fp64=h64[-1],
                  err_mixed_vs_fp64=float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64)),
+                 err_adjoint_mixed_vs_fp64=float(torch.linalg.norm(lam - lam64) / torch.linalg.norm(lam64)),
                  grad_finite=bool(torch.isfinite(g).all()))
         return r
 
-    # warmup; the first warmup step is profiled for every kernel class
-    solver.profile(True)
+    # plain device copy of a known size: the practical HBM ceiling, and the
+    # reference kernel that scales the PMC byte counters
+    copy_gbs = copy_probe(torch, dev)
+    log(f"copy probe: {copy_gbs:.1f} GB/s")
+
+    # warmup; the first warmup step times every kernel class of the mixed solve
     prof_steps = []
     for w in range(max(1, args.warmup)):
-        r = step()
+        r = step(prof_kinds=list(solver.kernel_times()) if w == 0 else None)
         if w == 0:
             kt = solver.kernel_times()
-            solver.profile(False)
         log(f"warmup {w}: " + ", ".join(f"{k}={v:.4g}" if isinstance(v, float) else f"{k}={v}" for k, v in r.items()))
         prof_steps.append(r)
     tot_ms = {k: v["ms"] for k, v in kt.items()}
     dominant = max(tot_ms, key=tot_ms.get)
     vc_ms = sum(kt[k]["ms"] for k in VCYCLE_KINDS)
     vc_bytes = sum(kt[k]["bytes"] for k in VCYCLE_KINDS)
-    log("kernel classes (profiled warmup step):")
+    log("kernel classes (mixed solve of the first warmup step, launches timed one by one):")
     for k, v in sorted(kt.items(), key=lambda kv: -kv[1]["ms"]):
         if v["launches"]:
-            log(f"  {k:12s} {v['ms']:9.3f} ms {v['launches']:7d} launches "
+            log(f"  {k:14s} {v['ms']:9.3f} ms {v['launches']:7d} launches "
                 f"{v['bytes'] / max(v['ms'], 1e-9) / 1e6:8.1f} GB/s")
 
     # timed region
@@ -114,12 +129,10 @@ def main():
     elapsed = time.perf_counter() - t0
     for i, r in enumerate(rs):
         log(f"step {i}: " + ", ".join(f"{k}={v:.4g}" if isinstance(v, float) else f"{k}={v}" for k, v in r.items()))
-    # dominant kernel: every launch of its class bracketed by HIP events on its
-    # stream during one more step (kernel-by-kernel launches while timing)
-    solver.profile(True, kinds=[dominant])
-    rp_ = step()
+    # dominant kernel: every launch of its class in the mixed solve bracketed
+    # by HIP events on its stream, during one more step
+    rp_ = step(prof_kinds=[dominant])
     dk = solver.kernel_times()[dominant]
-    solver.profile(False)
     log(f"profiled step: {dominant}: {dk['launches']} launches, {dk['ms']:.3f} ms, mixed solve {rp_['mixed_s']:.4f}s")
 
     def mean(k):
@@ -141,6 +154,7 @@ def main():
     vbytes = st["vcycle_bytes"][1]
 
     achieved = dk["bytes"] / (dk["ms"] * 1e-3) / 1e9 if dk["ms"] > 0 else 0.0
+    traffic, traffic_src = measured_traffic(dominant)
     out = {
         "metric": METRIC,
         "value": round(mean("mixed_s"), 6),
@@ -172,7 +186,11 @@ def main():
         "err_mixed_vs_fp64": float(rs[-1]["err_mixed_vs_fp64"]),
         "setup_s": round(mean("setup_s"), 4),
         "adjoint_mixed_s": round(mean("adjoint_s"), 6),
+        "adjoint_fp64_s": round(mean("adjoint64_s"), 6),
         "iters_adjoint": int(rs[-1]["it_adjoint"]),
+        "iters_adjoint_fp64": int(rs[-1]["it_adjoint64"]),
+        "err_adjoint_mixed_vs_fp64": float(rs[-1]["err_adjoint_mixed_vs_fp64"]),
+        "copy_gbs": round(copy_gbs, 1),
         "grad_s": round(mean("grad_s"), 6),
         "vcycle_gbs_kernels": round(vc_bytes / (vc_ms * 1e-3) / 1e9, 1) if vc_ms > 0 else None,
         "vcycle_gbs_apply": round(vbytes / apply_s / 1e9, 1),
@@ -186,14 +204,56 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "launches": dk["launches"],
             "avg_launch_us": round(dk["ms"] / max(dk["launches"], 1) * 1e3, 3),
+            "bytes_per_launch": round(dk["bytes"] / max(dk["launches"], 1)),
+            "traffic_source": traffic_src,
         },
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(out), flush=True)
+
+
+def copy_probe(torch, dev, mib=512, reps=5):
+    """y = -x over `mib` MiB of float32 (read once, written once); returns GB/s
+    of the best of `reps` launches."""
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        torch.neg(x, out=y)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del x, y
+    return 2 * n * 4 / best / 1e9
+
+
+def measured_traffic(kind):
+    """HBM bytes per launch of the `kind` kernel from the committed PMC summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading for
+    the copy probe of known size), or None when the summary does not cover
+    this kind or the solve kernels have changed since it was taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_2602_13079_amd", "csrc", "solve_kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "pmc_*.md"))):
+        text = open(path).read()
+        if "```json" not in text:
+            continue
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        if rec.get("kind") != kind:
+            continue
+        if rec.get("solve_kernels_sha256") != digest:
+            return None, f"{os.path.relpath(path, ROOT)} is stale (solve kernels changed since)"
+        return round(rec["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, "no PMC summary for this kernel class"
 
 
 def cpu_baseline(s):

@@ -596,6 +596,21 @@ struct Buf<float> {
   static float* t(Field& F) { return F.tf; }
 };
 
+// profiler class of a V-cycle operation on level l (finest level or below)
+static int lk(int kind, int l) {
+  if (l == 0) return kind;
+  switch (kind) {
+    case solve::K_CHEB_PRE: return solve::K_CHEB_PRE_C;
+    case solve::K_CHEB_POST_A: return solve::K_CHEB_POST_A_C;
+    case solve::K_CHEB_POST_B: return solve::K_CHEB_POST_B_C;
+    case solve::K_CHEB_OTHER: return solve::K_CHEB_OTHER_C;
+    case solve::K_RESID: return solve::K_RESID_C;
+    case solve::K_RESTRICT: return solve::K_RESTRICT_C;
+    case solve::K_PROLONG: return solve::K_PROLONG_C;
+    default: return kind;
+  }
+}
+
 template <class T>
 static void vcycle(hbgs_ctx* c, Field& F, int l, int tr, const T* b, T* x, hipStream_t s) {
   using B = Buf<T>;
@@ -614,48 +629,48 @@ static void vcycle(hbgs_ctx* c, Field& F, int l, int tr, const T* b, T* x, hipSt
   // pre-smoothing from a zero guess (degree 2: d0 was written by the
   // producer of b into this level's d buffer)
   if (cc.degree == 2) {
-    Prof p(c->prof, s, solve::K_CHEB_PRE, spmv_bytes(A, TS, TS, TS, 2));
+    Prof p(c->prof, s, lk(solve::K_CHEB_PRE, l), spmv_bytes(A, TS, TS, TS, 2));
     VcOps<T>::pre2(A, dinv, cc, b, d, x, s);
   } else {
     {
-      Prof p(c->prof, s, solve::K_CHEB_OTHER, 4.0 * n * TS);
+      Prof p(c->prof, s, lk(solve::K_CHEB_OTHER, l), 4.0 * n * TS);
       VcOps<T>::init0(n, dinv, cc, b, r, d, x, s);
     }
     for (int k = 1; k < cc.degree; ++k) {
-      Prof p(c->prof, s, solve::K_CHEB_OTHER, spmv_bytes(A, TS, TS, 3 * TS, 2));
+      Prof p(c->prof, s, lk(solve::K_CHEB_OTHER, l), spmv_bytes(A, TS, TS, 3 * TS, 2));
       VcOps<T>::step(A, dinv, cc, k, false, k + 1 < cc.degree, r, d, dn, x, s);
       std::swap(d, dn);
     }
   }
   {
-    Prof p(c->prof, s, solve::K_RESID, spmv_bytes(A, TS, TS, TS, 1));
+    Prof p(c->prof, s, lk(solve::K_RESID, l), spmv_bytes(A, TS, TS, TS, 1));
     VcOps<T>::resid(A, b, x, r, s);
   }
   Level& C = F.lv[l + 1];
   {
     const bool d0c = l + 2 < (int)F.lv.size() && C.cc.degree == 2;
-    Prof p(c->prof, s, solve::K_RESTRICT, spmv_bytes(L.R, TS, TS, TS, d0c ? 2 : 0));
+    Prof p(c->prof, s, lk(solve::K_RESTRICT, l), spmv_bytes(L.R, TS, TS, TS, d0c ? 2 : 0));
     VcOps<T>::restrict_(L.R, r, B::b(C), d0c ? B::dinv(C) : nullptr, C.cc.c0, d0c ? B::d(C) : nullptr, s);
   }
   vcycle<T>(c, F, l + 1, tr, B::b(C), B::x(C), s);
   {
-    Prof p(c->prof, s, solve::K_PROLONG, spmv_bytes(L.P, TS, TS, TS, 1));
+    Prof p(c->prof, s, lk(solve::K_PROLONG, l), spmv_bytes(L.P, TS, TS, TS, 1));
     VcOps<T>::prolong(L.P, B::x(C), x, s);
   }
   // post-smoothing from x
   d = B::d(L);
   dn = B::dn(L);
   {
-    Prof p(c->prof, s, solve::K_CHEB_POST_A, spmv_bytes(A, TS, TS, 2 * TS, 2));
+    Prof p(c->prof, s, lk(solve::K_CHEB_POST_A, l), spmv_bytes(A, TS, TS, 2 * TS, 2));
     VcOps<T>::post_start(A, dinv, cc, b, x, r, d, s);
   }
   if (cc.degree == 1) {
-    Prof p(c->prof, s, solve::K_CHEB_OTHER, 3.0 * n * TS);
+    Prof p(c->prof, s, lk(solve::K_CHEB_OTHER, l), 3.0 * n * TS);
     VcOps<T>::add(n, d, x, s);
   }
   for (int k = 1; k < cc.degree; ++k) {
     bool keep = k + 1 < cc.degree;
-    Prof p(c->prof, s, keep ? solve::K_CHEB_OTHER : solve::K_CHEB_POST_B, spmv_bytes(A, TS, TS, TS, 3));
+    Prof p(c->prof, s, lk(keep ? solve::K_CHEB_OTHER : solve::K_CHEB_POST_B, l), spmv_bytes(A, TS, TS, TS, 3));
     VcOps<T>::step(A, dinv, cc, k, k == 1, keep, r, d, dn, x, s);
     std::swap(d, dn);
   }

@@ -183,6 +183,14 @@ enum Kind {
   K_SCALE,
   K_XUPDATE,
   K_PERMUTE,
+  // the same V-cycle operations on levels below the finest one
+  K_CHEB_PRE_C,
+  K_CHEB_POST_A_C,
+  K_CHEB_POST_B_C,
+  K_CHEB_OTHER_C,
+  K_RESID_C,
+  K_RESTRICT_C,
+  K_PROLONG_C,
   K_COUNT
 };
 extern const char* kind_names[K_COUNT];

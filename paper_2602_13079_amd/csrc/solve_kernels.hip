@@ -21,7 +21,8 @@ constexpr int BLK = 256;
 const char* kind_names[K_COUNT] = {
     "spmv_outer", "spmv_resid", "cheb_pre",  "cheb_post_a", "cheb_post_b", "cheb_other", "resid", "restrict",
     "prolong",    "coarse",     "couple",    "dot1",        "upd_dot2",    "upd_scale",  "reduce",
-    "givens",     "scale",      "xupdate",   "permute"};
+    "givens",     "scale",      "xupdate",   "permute",     "cheb_pre_c", "cheb_post_a_c", "cheb_post_b_c",
+    "cheb_other_c", "resid_c",  "restrict_c", "prolong_c"};
 
 // ---------------------------------------------------------- CSR row engine
 template <class T>
