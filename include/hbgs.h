@@ -72,6 +72,10 @@ typedef struct {
   int32_t use_graphs;    /* 1: replay each GMRES iteration as a captured HIP graph;
                             0: launch kernels one by one (default; measured faster
                             than graph replay on ROCm 7.2 for this kernel mix) */
+  int32_t setup_concurrent; /* 1 (default): the fields' blocks and hierarchies are
+                               built concurrently, one host thread and HIP stream per
+                               field (the results do not depend on it); 0: one after
+                               another on the caller's stream */
 } hbgs_options;
 
 typedef struct {
@@ -85,6 +89,8 @@ typedef struct {
                                (all field V-cycles + couplings), [0] FP64, [1] mixed */
   double spmv_bytes[2];     /* algorithmic bytes of one outer SpMV, [0] FP64 x, [1] FP32 x */
   double setup_seconds;     /* wall time of the last setup */
+  double setup_field_seconds[HBGS_MAX_FIELDS]; /* wall time of each field's block
+                               extraction and hierarchy build in the last setup */
 } hbgs_stats_t;
 
 /* Fill *opt with the defaults listed above. */

@@ -35,6 +35,7 @@ class Options(ctypes.Structure):
         ("cheb_boost", ctypes.c_double), ("eig_iters", ctypes.c_int32), ("sa_damping", ctypes.c_double),
         ("coarse_max", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("theta", ctypes.c_double * MAX_FIELDS), ("use_graphs", ctypes.c_int32),
+        ("setup_concurrent", ctypes.c_int32),
     ]
 
 
@@ -46,7 +47,7 @@ class Stats(ctypes.Structure):
         ("nnz_a", (ctypes.c_int64 * MAX_LEVELS) * MAX_FIELDS),
         ("nnz_p", (ctypes.c_int64 * MAX_LEVELS) * MAX_FIELDS),
         ("vcycle_bytes", ctypes.c_double * 2), ("spmv_bytes", ctypes.c_double * 2),
-        ("setup_seconds", ctypes.c_double),
+        ("setup_seconds", ctypes.c_double), ("setup_field_seconds", ctypes.c_double * MAX_FIELDS),
     ]
 
 
@@ -209,7 +210,8 @@ class Solver:
             nnz_a=[[st.nnz_a[f][l] for l in range(st.levels[f])] for f in range(nf)],
             nnz_p=[[st.nnz_p[f][l] for l in range(st.levels[f])] for f in range(nf)],
             vcycle_bytes=list(st.vcycle_bytes), spmv_bytes=list(st.spmv_bytes),
-            setup_seconds=st.setup_seconds)
+            setup_seconds=st.setup_seconds,
+            setup_field_seconds=[st.setup_field_seconds[f] for f in range(nf)])
 
     def get_level(self, field, level, which="A"):
         """Host copy (rowptr, col, val, ncols) of A_l / P_l / R_l / A_l^T."""

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "hbgs_internal.h"
@@ -19,27 +20,61 @@ namespace hbgs {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-Pool::~Pool() {
-  for (auto& b : blocks_) (void)hipFree(b.first);
+static std::mutex g_alloc_mu;
+static Allocator g_alloc;
+Allocator current_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc;
+}
+
+hipStream_t& tmp_stream() {
+  static thread_local hipStream_t s = nullptr;
+  return s;
+}
+
+static void free_block(void* p, const Allocator& a) {
+  if (a.free)
+    a.free(p, a.user);
+  else
+    (void)hipFree(p);
+}
+
+Pool::~Pool() { clear(); }
+void Pool::clear() {
+  std::lock_guard<std::mutex> lk(mu_);
+  for (auto& b : blocks_) free_block(b.p, b.a);
+  blocks_.clear();
+  total_ = 0;
 }
 void* Pool::get(size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 8;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    set_error(std::string("device allocation of ") + std::to_string(bytes) + " bytes failed: " +
-              hipGetErrorString(e));
-    throw Error{HBGS_ENOMEM};
+  const Allocator a = current_allocator();
+  if (a.alloc) {
+    p = a.alloc(bytes, a.user);
+    if (!p) {
+      set_error("device allocation of " + std::to_string(bytes) + " bytes failed in the user allocator");
+      throw Error{HBGS_ENOMEM};
+    }
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      set_error(std::string("device allocation of ") + std::to_string(bytes) + " bytes failed: " +
+                hipGetErrorString(e));
+      throw Error{HBGS_ENOMEM};
+    }
   }
-  blocks_.push_back({p, bytes});
+  std::lock_guard<std::mutex> lk(mu_);
+  blocks_.push_back({p, bytes, a});
   total_ += bytes;
   return p;
 }
 void Pool::release(void* p) {
+  std::lock_guard<std::mutex> lk(mu_);
   for (size_t i = 0; i < blocks_.size(); ++i)
-    if (blocks_[i].first == p) {
-      (void)hipFree(p);
-      total_ -= blocks_[i].second;
+    if (blocks_[i].p == p) {
+      free_block(p, blocks_[i].a);
+      total_ -= blocks_[i].bytes;
       blocks_.erase(blocks_.begin() + i);
       return;
     }
@@ -144,6 +179,7 @@ struct Field {
   double* td = nullptr;   // fine-level right-hand side
   float* tf = nullptr;
   uint32_t deps[2] = {0, 0};  // fields read by the coupling rows: [0] forward, [1] adjoint sweep
+  double setup_seconds = 0.0;  // wall time of this field's part of the last setup
   int n() const { return hi - lo; }
 };
 
@@ -184,7 +220,8 @@ struct hbgs_ctx {
   double *bp = nullptr, *xp = nullptr, *r = nullptr, *part = nullptr, *h1 = nullptr, *h2 = nullptr,
          *hn2 = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *scal = nullptr,
          *tmp = nullptr;
-  double* host_scal = nullptr;  // pinned
+  double* host_scal = nullptr;      // pinned
+  double* host_scal_dev = nullptr;  // its device-side address
   hbgs::Profiler prof;
   hbgs_stats_t stats{};
   // concurrent sweep
@@ -192,6 +229,9 @@ struct hbgs_ctx {
   hipStream_t fstream[hbgs::MAX_SWEEP_STREAMS] = {};
   hipEvent_t fdone[HBGS_MAX_FIELDS] = {};
   hipEvent_t fork = nullptr;
+  // concurrent setup: one stream per field
+  hipStream_t sstream[HBGS_MAX_FIELDS] = {};
+  hipEvent_t setup_in = nullptr;
   // solve stream (graph capture needs a non-default stream) and graph cache
   hipStream_t sm = nullptr;
   hipEvent_t join_in = nullptr, join_out = nullptr;
@@ -212,6 +252,9 @@ struct hbgs_ctx {
     for (auto& e : fdone)
       if (e) (void)hipEventDestroy(e);
     if (fork) (void)hipEventDestroy(fork);
+    for (auto& st : sstream)
+      if (st) (void)hipStreamDestroy(st);
+    if (setup_in) (void)hipEventDestroy(setup_in);
   }
 };
 
@@ -488,6 +531,7 @@ static void compute_stats(hbgs_ctx* c) {
   for (int f = 0; f < c->nf && f < HBGS_MAX_FIELDS; ++f) {
     const Field& F = c->F[f];
     st.levels[f] = (int)F.lv.size();
+    st.setup_field_seconds[f] = F.setup_seconds;
     for (size_t l = 0; l < F.lv.size() && l < HBGS_MAX_LEVELS; ++l) {
       st.rows[f][l] = F.lv[l].A.n;
       st.nnz_a[f][l] = F.lv[l].A.nnz;
@@ -527,29 +571,80 @@ static void plan_sweep(hbgs_ctx* c, int tr) {
   if (!c->join_out) HBGS_HIP(hipEventCreateWithFlags(&c->join_out, hipEventDisableTiming));
 }
 
-// value-dependent part of setup: blocks, couplings, hierarchies
+// per-field part of the value-dependent setup: diagonal block, couplings,
+// SA-AMG hierarchy
+static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  F.lv.clear();
+  F.lv.emplace_back();
+  F.lv[0].A = extract(c->hier, c->Ap, F.lo, F.hi, F.lo, F.hi, F.lo, F.n(), s);
+  F.lower = extract(c->hier, c->Ap, F.lo, F.hi, 0, F.lo, 0, c->n, s);
+  F.upperT = extract(c->hier, c->ApT, F.lo, F.hi, F.hi, c->n, 0, c->n, s);
+  add_f32(c->hier, F.lower, s);
+  add_f32(c->hier, F.upperT, s);
+  setup::row_stats(F.lower, s);
+  setup::row_stats(F.upperT, s);
+  F.td = c->hier.make<double>(F.n());
+  F.tf = c->hier.make<float>(F.n());
+  build_hierarchy(c, F, s);
+  HBGS_HIP(hipStreamSynchronize(s));
+  F.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// value-dependent part of setup: blocks, couplings, hierarchies.  The
+// fields are independent here, so each is built by its own host thread on
+// its own stream (the latency-bound steps of one field, such as the
+// aggregation rounds and the factorisation steps, overlap the others').
 static void build_values(hbgs_ctx* c, hipStream_t s) {
   c->clear_graphs();
-  c->hier.~Pool();
-  new (&c->hier) Pool();
+  c->hier.clear();
   c->F.assign(c->nf, Field{});
   for (int f = 0; f < c->nf; ++f) {
     Field& F = c->F[f];
     F.id = f;
     F.lo = c->f_lo[f];
     F.hi = c->f_hi[f];
-    F.lv.clear();
-    F.lv.emplace_back();
-    F.lv[0].A = extract(c->hier, c->Ap, F.lo, F.hi, F.lo, F.hi, F.lo, F.n(), s);
-    F.lower = extract(c->hier, c->Ap, F.lo, F.hi, 0, F.lo, 0, c->n, s);
-    F.upperT = extract(c->hier, c->ApT, F.lo, F.hi, F.hi, c->n, 0, c->n, s);
-    add_f32(c->hier, F.lower, s);
-    add_f32(c->hier, F.upperT, s);
-    setup::row_stats(F.lower, s);
-    setup::row_stats(F.upperT, s);
-    F.td = c->hier.make<double>(F.n());
-    F.tf = c->hier.make<float>(F.n());
-    build_hierarchy(c, F, s);
+  }
+  if (c->nf == 1 || !c->o.setup_concurrent) {
+    StreamScope scope(s);
+    for (int f = 0; f < c->nf; ++f) build_field(c, c->F[f], s);
+  } else {
+    int dev = 0;
+    HBGS_HIP(hipGetDevice(&dev));
+    if (!c->setup_in) HBGS_HIP(hipEventCreateWithFlags(&c->setup_in, hipEventDisableTiming));
+    for (int f = 0; f < c->nf; ++f)
+      if (!c->sstream[f]) HBGS_HIP(hipStreamCreateWithFlags(&c->sstream[f], hipStreamNonBlocking));
+    HBGS_HIP(hipEventRecord(c->setup_in, s));
+    std::vector<int> code(c->nf, HBGS_OK);
+    std::vector<std::string> msg(c->nf);
+    std::vector<std::thread> th;
+    auto work = [&](int f) {
+      hipStream_t sf = c->sstream[f];
+      try {
+        HBGS_HIP(hipSetDevice(dev));
+        HBGS_HIP(hipStreamWaitEvent(sf, c->setup_in, 0));
+        StreamScope scope(sf);
+        build_field(c, c->F[f], sf);
+      } catch (const Error& e) {
+        code[f] = e.code;
+        msg[f] = g_last_error;
+      } catch (const std::exception& e) {
+        code[f] = HBGS_EHIP;
+        msg[f] = std::string("exception: ") + e.what();
+      }
+    };
+    try {
+      for (int f = 0; f < c->nf; ++f) th.emplace_back(work, f);
+    } catch (...) {
+      for (auto& t : th) t.join();
+      throw;
+    }
+    for (auto& t : th) t.join();
+    for (int f = 0; f < c->nf; ++f)
+      if (code[f] != HBGS_OK) {
+        set_error(msg[f]);
+        throw Error{(hbgs_status)code[f]};
+      }
   }
   // which fields each coupling reads
   {
@@ -752,7 +847,10 @@ static void ensure_workspace(hbgs_ctx* c) {
   c->g = c->pool.make<double>(m + 1);
   c->y = c->pool.make<double>(m);
   c->scal = c->pool.make<double>(4);
-  if (!c->host_scal) HBGS_HIP(hipHostMalloc((void**)&c->host_scal, 8 * sizeof(double), hipHostMallocDefault));
+  if (!c->host_scal) {
+    HBGS_HIP(hipHostMalloc((void**)&c->host_scal, 8 * sizeof(double), hipHostMallocDefault));
+    HBGS_HIP(hipHostGetDevicePointer((void**)&c->host_scal_dev, c->host_scal, 0));
+  }
 }
 
 static double norm2(hbgs_ctx* c, const double* x, hipStream_t s) {
@@ -793,7 +891,7 @@ static void iteration_body(hbgs_ctx* c, int tr, int j, hipStream_t s) {
   }
   {
     Prof p(c->prof, s, solve::K_DOT1, 8.0 * n * (j + 2));
-    solve::mdot(n, j, c->V, ld, w, c->part, s);
+    solve::cgs_dots(n, j, c->V, ld, w, c->part, s);
   }
   {
     Prof p(c->prof, s, solve::K_REDUCE, 8.0 * nb * (j + 2));
@@ -801,15 +899,21 @@ static void iteration_body(hbgs_ctx* c, int tr, int j, hipStream_t s) {
   }
   {
     Prof p(c->prof, s, solve::K_UPD_DOT2, 8.0 * n * (j + 3));
-    solve::upd_mdot(n, j, c->V, ld, w, c->h1, c->part, s);
+    solve::cgs_update_dots(n, j, c->V, ld, w, c->h1, c->part, s);
   }
   {
-    Prof p(c->prof, s, solve::K_REDUCE, 8.0 * nb * (j + 2));
-    solve::mdot_reduce(j + 2, nb, c->part, c->h2, s);
-  }
-  {
-    Prof p(c->prof, s, solve::K_GIVENS, 0.0);
-    solve::givens(j, m, c->h1, c->h2, c->h1 + (j + 1), c->H, c->cs, c->sn, c->g, c->scal, s);
+    solve::GivensArgs ga;
+    ga.j = j;
+    ga.m = m;
+    ga.h1 = c->h1;
+    ga.H = c->H;
+    ga.cs = c->cs;
+    ga.sn = c->sn;
+    ga.g = c->g;
+    ga.scal = c->scal;
+    ga.host_scal = c->host_scal_dev;
+    Prof p(c->prof, s, solve::K_GIVENS, 8.0 * nb * (j + 2));
+    solve::reduce_givens(n, j, c->part, c->h2, ga, s);
   }
   {
     Prof p(c->prof, s, solve::K_UPD_SCALE, 8.0 * n * (j + 3));
@@ -888,8 +992,7 @@ static hbgs_status gmres(hbgs_ctx* c, int tr, int use_x0, int32_t* iters, double
     HBGS_HIP(hipMemcpyAsync(c->g, g0.data(), sizeof(double) * (m + 1), hipMemcpyHostToDevice, s));
     int jend = 0;
     for (int j = 0; j < m; ++j) {
-      run_iteration(c, tr, j, s);
-      HBGS_HIP(hipMemcpyAsync(c->host_scal, c->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+      run_iteration(c, tr, j, s);  // its Givens step writes the estimate to host_scal
       HBGS_HIP(hipStreamSynchronize(s));
       (*iters)++;
       double est = c->host_scal[0] / bnorm, hn = c->host_scal[1], w0 = c->host_scal[2];
@@ -945,6 +1048,7 @@ void hbgs_default_options(hbgs_options* o) {
   o->seed = 0x2602ull;
   o->theta[0] = 0.04;
   o->use_graphs = 0;
+  o->setup_concurrent = 1;
 }
 
 const char* hbgs_last_error(void) { return g_last_error.c_str(); }

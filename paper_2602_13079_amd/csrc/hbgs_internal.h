@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "hbgs.h"
@@ -34,13 +35,24 @@ struct Error {
   } while (0)
 
 // ----------------------------------------------------- device memory owner
+// Allocation hook for a context's persistent device memory (null: hipMalloc
+// and hipFree).  Each allocation remembers the hook that made it.
+struct Allocator {
+  void* (*alloc)(size_t bytes, void* user) = nullptr;
+  void (*free)(void* p, void* user) = nullptr;
+  void* user = nullptr;
+};
+Allocator current_allocator();
+
 // All device memory of a context goes through a Pool: persistent buffers
 // live until the pool is destroyed, temporaries are released explicitly.
+// Safe to use from several host threads.
 class Pool {
  public:
   ~Pool();
   void* get(size_t bytes);  // persistent
   void release(void* p);    // free one persistent allocation early
+  void clear();             // free everything
   template <class T>
   T* make(size_t count) {
     return static_cast<T*>(get(count * sizeof(T) + (count == 0 ? sizeof(T) : 0)));
@@ -48,24 +60,60 @@ class Pool {
   size_t bytes() const { return total_; }
 
  private:
-  std::vector<std::pair<void*, size_t>> blocks_;
+  struct Block {
+    void* p;
+    size_t bytes;
+    Allocator a;
+  };
+  std::mutex mu_;
+  std::vector<Block> blocks_;
   size_t total_ = 0;
 };
 
-// Temporary device buffer (setup only).
+// Setup work of one host thread runs on one stream; while a StreamScope is
+// alive on a thread, that thread's temporaries are stream-ordered on it.
+hipStream_t& tmp_stream();
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s) : prev(tmp_stream()) { tmp_stream() = s; }
+  ~StreamScope() { tmp_stream() = prev; }
+};
+
+// Temporary device buffer (setup only): stream-ordered on the thread's
+// setup stream when one is set, else hipMalloc / hipFree.
 template <class T>
 struct Tmp {
   T* p = nullptr;
   size_t count = 0;
+  hipStream_t s = nullptr;
+  bool async = false;
   Tmp() = default;
   explicit Tmp(size_t n) { alloc(n); }
   void alloc(size_t n) {
     release();
     count = n;
-    HBGS_HIP(hipMalloc(&p, (n ? n : 1) * sizeof(T)));
+    const size_t bytes = (n ? n : 1) * sizeof(T);
+    s = tmp_stream();
+    async = false;
+    if (s) {
+      hipError_t e = hipMallocAsync((void**)&p, bytes, s);
+      if (e == hipSuccess) {
+        async = true;
+        return;
+      }
+      if (e == hipErrorOutOfMemory) HBGS_HIP(e);
+      (void)hipGetLastError();  // stream-ordered allocation unavailable: plain allocation
+      p = nullptr;
+    }
+    HBGS_HIP(hipMalloc(&p, bytes));
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (async)
+        (void)hipFreeAsync(p, s);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
   }
   ~Tmp() { release(); }
@@ -241,20 +289,35 @@ struct VcOps {
 void permute_in(int n, const int* perm, const double* x, double* xp, hipStream_t s);   // xp[perm[i]] = x[i]
 void permute_out(int n, const int* perm, const double* xp, double* x, hipStream_t s);  // x[i] = xp[perm[i]]
 int dot_blocks(int n);
-// h[k] = V_k . w for k <= j, plus w.w (h[j+1]); partial sums per block
-void mdot(int n, int j, const double* V, size_t ldv, const double* w, double* part, hipStream_t s);
+// Givens step inputs: column j of the (m+1) x m Hessenberg matrix H, the
+// rotations cs/sn, the rotated right-hand side g, and where to put the
+// residual estimate (scal on the device, host_scal in pinned host memory
+// or null)
+struct GivensArgs {
+  int j = 0, m = 0;
+  const double* h1 = nullptr;
+  double* H = nullptr;
+  double* cs = nullptr;
+  double* sn = nullptr;
+  double* g = nullptr;
+  double* scal = nullptr;
+  double* host_scal = nullptr;
+};
+// Gram-Schmidt passes over the basis V_0..V_j (w = column j+1 of V), as
+// per-block partial sums part[k * dot_blocks(n) + block]:
+//   cgs_dots:        V_k . w (k <= j) and w . w
+//   cgs_update_dots: w -= V h1, then V_k . w (k <= j) and w . w
+void cgs_dots(int n, int j, const double* V, size_t ldv, const double* w, double* part, hipStream_t s);
+void cgs_update_dots(int n, int j, const double* V, size_t ldv, double* w, const double* h1, double* part,
+                     hipStream_t s);
+// reduce the second pass into h2[0..j+1], then the Givens update of column
+// j (scal[0] = |g_{j+1}|, scal[1] = h_{j+1,j}, scal[2] = ||w|| before
+// orthogonalisation, also written to host_scal)
+void reduce_givens(int n, int j, const double* part, double* h2, const GivensArgs& ga, hipStream_t s);
 void mdot_reduce(int nvec, int nblocks, const double* part, double* out, hipStream_t s);
-// w -= V h (k <= j), then partial dots of the updated w with V_k (k <= j) and w.w
-void upd_mdot(int n, int j, const double* V, size_t ldv, double* w, const double* h, double* part,
-              hipStream_t s);
 // w = (w - V h) / scal[1] (new basis vector), when scal[1] > 0
 void upd_scale(int n, int j, const double* V, size_t ldv, double* w, const double* h, const double* scal,
                hipStream_t s);
-// Givens update of column j from the two Gram-Schmidt passes (h2[j+1] =
-// ||w||^2 after the first); writes scal[0] = |g_{j+1}|, scal[1] = h_{j+1,j},
-// scal[2] = ||w|| before orthogonalisation
-void givens(int j, int m, const double* h1, const double* h2, const double* w0sq, double* H, double* cs,
-            double* sn, double* g, double* scal, hipStream_t s);
 void backsolve(int jend, int m, const double* H, const double* g, double* y, hipStream_t s);
 template <class TZ>
 void xupdate(int n, int jend, const TZ* Z, size_t ldz, const double* y, double* x, hipStream_t s);

@@ -274,18 +274,20 @@ __global__ void k_transpose_scatter(int n, const int* rp, const int* ci, const d
   }
 }
 // sort each row by column (entries are distinct, so the result is unique);
-// rows of up to SORT_LDS entries are sorted in a per-thread LDS segment
+// rows of up to SORT_LDS entries are sorted in a per-thread LDS segment,
+// longer rows are listed and sorted one block per row
 constexpr int SORT_LDS = 32;
 constexpr int SORT_BLK = 64;
+constexpr int LONG_LDS = 2048;
 __global__ __launch_bounds__(SORT_BLK) void k_sort_rows_lds(int n, const int* rp, int* ci, double* v,
-                                                            int* long_rows) {
+                                                            int* n_long, int* long_rows) {
   __shared__ int sc[SORT_BLK][SORT_LDS + 1];
   __shared__ double sv[SORT_BLK][SORT_LDS + 1];
   int i = blockIdx.x * SORT_BLK + threadIdx.x;
   if (i >= n) return;
   int s = rp[i], e = rp[i + 1], len = e - s;
   if (len > SORT_LDS) {
-    atomicOr(long_rows, 1);
+    long_rows[atomicAdd(n_long, 1)] = i;
     return;
   }
   int* c = sc[threadIdx.x];
@@ -308,10 +310,34 @@ __global__ __launch_bounds__(SORT_BLK) void k_sort_rows_lds(int n, const int* rp
   }
 }
 
-__global__ void k_sort_rows(int n, const int* rp, int* ci, double* v) {
-  GRID_STRIDE(i, n) {
-    if (rp[i + 1] - rp[i] <= SORT_LDS) continue;
+// one block per listed row of up to LONG_LDS entries: every entry's
+// destination is its rank (the number of smaller columns in the row)
+__global__ __launch_bounds__(BLK) void k_sort_long_rows(const int* rows, const int* rp, int* ci, double* v) {
+  __shared__ int sc[LONG_LDS];
+  __shared__ double sv[LONG_LDS];
+  const int row = rows[blockIdx.x];
+  const int s = rp[row], len = rp[row + 1] - s;
+  if (len > LONG_LDS) return;
+  for (int k = threadIdx.x; k < len; k += BLK) {
+    sc[k] = ci[s + k];
+    sv[k] = v ? v[s + k] : 0.0;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < len; k += BLK) {
+    const int c = sc[k];
+    int rank = 0;
+    for (int q = 0; q < len; ++q) rank += sc[q] < c;
+    ci[s + rank] = c;
+    if (v) v[s + rank] = sv[k];
+  }
+}
+
+// rows longer than LONG_LDS: insertion sort by one thread per listed row
+__global__ void k_sort_huge_rows(int cnt, const int* rows, const int* rp, int* ci, double* v) {
+  GRID_STRIDE(t, cnt) {
+    const int i = rows[t];
     int s = rp[i], e = rp[i + 1];
+    if (e - s <= LONG_LDS) continue;
     for (int k = s + 1; k < e; ++k) {
       int c = ci[k];
       double x = v ? v[k] : 0.0;
@@ -328,15 +354,18 @@ __global__ void k_sort_rows(int n, const int* rp, int* ci, double* v) {
 }
 
 void sort_rows(const DCsr& a, hipStream_t s) {
-  Tmp<int> long_rows(1);
-  HBGS_HIP(hipMemsetAsync(long_rows.p, 0, sizeof(int), s));
-  k_sort_rows_lds<<<grid_for(a.n, SORT_BLK), SORT_BLK, 0, s>>>(a.n, a.rp, a.ci, a.v, long_rows.p);
+  if (a.n == 0) return;
+  Tmp<int> n_long(1), long_rows(a.n);
+  HBGS_HIP(hipMemsetAsync(n_long.p, 0, sizeof(int), s));
+  k_sort_rows_lds<<<grid_for(a.n, SORT_BLK), SORT_BLK, 0, s>>>(a.n, a.rp, a.ci, a.v, n_long.p, long_rows.p);
   HBGS_HIP(hipGetLastError());
-  int lr = 0;
-  HBGS_HIP(hipMemcpyAsync(&lr, long_rows.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  int nl = 0;
+  HBGS_HIP(hipMemcpyAsync(&nl, n_long.p, sizeof(int), hipMemcpyDeviceToHost, s));
   HBGS_HIP(hipStreamSynchronize(s));
-  if (lr) {
-    k_sort_rows<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v);
+  if (nl > 0) {
+    k_sort_long_rows<<<nl, BLK, 0, s>>>(long_rows.p, a.rp, a.ci, a.v);
+    HBGS_HIP(hipGetLastError());
+    k_sort_huge_rows<<<grid_for(nl, BLK), BLK, 0, s>>>(nl, long_rows.p, a.rp, a.ci, a.v);
     HBGS_HIP(hipGetLastError());
   }
 }

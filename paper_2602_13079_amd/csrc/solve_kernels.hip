@@ -50,30 +50,45 @@ __global__ void k_empty(int n, Epi epi) {
   int i = blockIdx.x * 256 + threadIdx.x;
   if (i < n) epi.store(i, TACC(0), epi.load(i));
 }
-// Row-block streaming form for short rows (longest row <= ROWS_LDS / RB).
-// Block b owns rows [RB b, RB (b+1)) and their entries; its threads first
-// stream the entries' values and column indices with unit-stride
-// (coalesced) loads, gather the operand and stage the products in LDS, then
-// one thread per row sums the row's products from LDS and applies the
-// epilogue.  Every matrix byte is read once with full-width transactions.
+// Row-block streaming form for short and medium rows (longest row <=
+// ROWS_LDS / RB).  Block b owns rows [RB b, RB (b+1)) and their entries: the
+// row epilogues' vector loads are issued first, so they overlap the entry
+// stream; the threads then stream the entries' values and column indices
+// with unit-stride (coalesced) loads, gather the operand and stage the
+// products in LDS; finally SBLK/RB lanes per row (or one thread per row when
+// RB >= SBLK) sum each row's products from LDS and apply the epilogue.
 constexpr int SBLK = 256;
 constexpr int ROWS_LDS_BYTES = 16384;
 
 template <int RB, class TV, class TACC, class LoadX, class Epi>
 __global__ __launch_bounds__(SBLK) void k_csr_rows(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                                    const TV* __restrict__ v, LoadX lx, Epi epi) {
+  constexpr int LPR = RB >= SBLK ? 1 : SBLK / RB;  // lanes per row in the row sums
+  constexpr int RPT = RB >= SBLK ? RB / SBLK : 1;  // rows per thread
   __shared__ TACC prod[ROWS_LDS_BYTES / sizeof(TACC)];
   const int r0 = blockIdx.x * RB;
   const int r1 = min(n, r0 + RB);
+  const int lane = threadIdx.x & (LPR - 1);
+  const int rbase = r0 + (int)threadIdx.x / LPR;
+  typename Epi::Pre pre[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = rbase + q * SBLK;
+    if (r < r1 && lane == 0) pre[q] = epi.load(r);
+  }
   const int s0 = rp[r0], s1 = rp[r1];
   for (int k = s0 + threadIdx.x; k < s1; k += SBLK) prod[k - s0] = (TACC)v[k] * (TACC)lx(ci[k]);
   __syncthreads();
-  for (int r = r0 + threadIdx.x; r < r1; r += SBLK) {
-    const int kb = rp[r] - s0, ke = rp[r + 1] - s0;
-    const typename Epi::Pre pre = epi.load(r);
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = rbase + q * SBLK;
     TACC acc = 0;
-    for (int k = kb; k < ke; ++k) acc += prod[k];
-    epi.store(r, acc, pre);
+    if (r < r1) {
+      const int kb = rp[r] - s0, ke = rp[r + 1] - s0;
+      for (int k = kb + lane; k < ke; k += LPR) acc += prod[k];
+    }
+    if (LPR > 1) acc = lanes_sum<TACC>(acc, LPR);
+    if (r < r1 && lane == 0) epi.store(r, acc, pre[q]);
   }
 }
 
@@ -81,21 +96,18 @@ template <class TV, class TACC, class LoadX, class Epi>
 static void launch_csr(const DCsr& a, const TV* v, LoadX lx, Epi epi, hipStream_t s) {
   if (a.n == 0) return;
   constexpr int cap = ROWS_LDS_BYTES / (int)sizeof(TACC);
-  if (a.maxlen > 0 && a.maxlen <= cap / 512) {
-    k_csr_rows<512, TV, TACC, LoadX, Epi><<<(a.n + 511) / 512, SBLK, 0, s>>>(a.n, a.rp, a.ci, v, lx, epi);
-    HBGS_HIP(hipGetLastError());
-    return;
+#define HBGS_ROWS(RB)                                                                                    \
+  if (a.maxlen > 0 && a.maxlen <= cap / RB) {                                                            \
+    k_csr_rows<RB, TV, TACC, LoadX, Epi><<<(a.n + RB - 1) / RB, SBLK, 0, s>>>(a.n, a.rp, a.ci, v, lx, epi); \
+    HBGS_HIP(hipGetLastError());                                                                         \
+    return;                                                                                              \
   }
-  if (a.maxlen > 0 && a.maxlen <= cap / 256) {
-    k_csr_rows<256, TV, TACC, LoadX, Epi><<<(a.n + 255) / 256, SBLK, 0, s>>>(a.n, a.rp, a.ci, v, lx, epi);
-    HBGS_HIP(hipGetLastError());
-    return;
-  }
-  if (a.maxlen > 0 && a.maxlen <= cap / 128) {
-    k_csr_rows<128, TV, TACC, LoadX, Epi><<<(a.n + 127) / 128, SBLK, 0, s>>>(a.n, a.rp, a.ci, v, lx, epi);
-    HBGS_HIP(hipGetLastError());
-    return;
-  }
+  HBGS_ROWS(512)
+  HBGS_ROWS(256)
+  HBGS_ROWS(128)
+  HBGS_ROWS(64)
+  HBGS_ROWS(32)
+#undef HBGS_ROWS
   if (a.nnz == 0) {  // rows without entries: epilogue of an empty sum
     k_empty<TACC, Epi><<<grid_for(a.n, 256), 256, 0, s>>>(a.n, epi);
     HBGS_HIP(hipGetLastError());
@@ -376,33 +388,32 @@ void VcOps<T>::cast_in(int n, const double* v, T* t, const T* dinv, double c0, T
   HBGS_HIP(hipGetLastError());
 }
 
-// coarsest level: x = A^-1 b with the dense FP64 inverse (row-major)
+// coarsest level: x = A^-1 b with the dense FP64 inverse (row-major; the
+// transposed solve passes the stored transpose).  One block per row: the
+// row's 8 n bytes are streamed by 256 threads and reduced in fixed order.
 template <class T>
-__global__ __launch_bounds__(BLK) void k_gemv_rows(int n, const double* __restrict__ inv, const T* __restrict__ b,
-                                                   T* __restrict__ x) {
-  const int wave = (blockIdx.x * BLK + threadIdx.x) >> 6, lane = threadIdx.x & 63;
-  if (wave >= n) return;
-  const double* row = inv + (int64_t)wave * n;
+__global__ __launch_bounds__(BLK) void k_gemv_block(int n, const double* __restrict__ inv, const T* __restrict__ b,
+                                                    T* __restrict__ x) {
+  __shared__ double sh[BLK / 64];
+  const int row = blockIdx.x;
+  const double* m = inv + (int64_t)row * n;
   double acc = 0.0;
-  for (int j = lane; j < n; j += 64) acc += row[j] * (double)b[j];
+  for (int j = threadIdx.x; j < n; j += BLK) acc += m[j] * (double)b[j];
   acc = lanes_sum<double>(acc, 64);
-  if (lane == 0) x[wave] = (T)acc;
-}
-template <class T>
-__global__ __launch_bounds__(BLK) void k_gemv_cols(int n, const double* __restrict__ inv, const T* __restrict__ b,
-                                                   T* __restrict__ x) {
-  const int i = blockIdx.x * BLK + threadIdx.x;
-  if (i >= n) return;
-  double acc = 0.0;
-  for (int j = 0; j < n; ++j) acc += inv[(int64_t)j * n + i] * (double)b[j];
-  x[i] = (T)acc;
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < BLK / 64; ++q) t += sh[q];
+    x[row] = (T)t;
+  }
 }
 template <class T>
 void VcOps<T>::coarse(int n, const double* inv, int transpose, const T* b, T* x, hipStream_t s) {
-  if (!transpose)
-    k_gemv_rows<T><<<grid_for((int64_t)n * 64, BLK), BLK, 0, s>>>(n, inv, b, x);
-  else
-    k_gemv_cols<T><<<grid_for(n, BLK), BLK, 0, s>>>(n, inv, b, x);
+  (void)transpose;  // the caller passes the stored transpose of the inverse
+  if (n <= 0) return;
+  k_gemv_block<T><<<n, BLK, 0, s>>>(n, inv, b, x);
   HBGS_HIP(hipGetLastError());
 }
 
@@ -449,10 +460,50 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// Givens rotation update of Hessenberg column j (H is (m+1) x m, row-major
+// with leading dimension m) by one thread.  h1/h2: first and second
+// Gram-Schmidt coefficients (k <= j); h2[j+1] = ||w||^2 after the first
+// pass; h1[j+1] = ||w||^2 before orthogonalisation.  scal (device) and
+// host_scal (pinned host memory) receive |g_{j+1}|, h_{j+1,j} and ||w||.
+__device__ void givens_update(const GivensArgs& ga, const double* h2) {
+  const int j = ga.j, m = ga.m;
+  double* H = ga.H;
+  for (int k = 0; k <= j; ++k) H[(size_t)k * m + j] = ga.h1[k] + h2[k];
+  // ||w - V h2||^2 = ||w||^2 - ||h2||^2 for orthonormal V
+  double ss = h2[j + 1];
+  for (int k = 0; k <= j; ++k) ss -= h2[k] * h2[k];
+  double hn = ss > 0.0 ? sqrt(ss) : 0.0;
+  H[(size_t)(j + 1) * m + j] = hn;
+  for (int k = 0; k < j; ++k) {
+    double a = H[(size_t)k * m + j], b = H[(size_t)(k + 1) * m + j];
+    H[(size_t)k * m + j] = ga.cs[k] * a + ga.sn[k] * b;
+    H[(size_t)(k + 1) * m + j] = -ga.sn[k] * a + ga.cs[k] * b;
+  }
+  double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+  double den = sqrt(a * a + b * b);
+  ga.cs[j] = a / den;
+  ga.sn[j] = b / den;
+  H[(size_t)j * m + j] = den;
+  H[(size_t)(j + 1) * m + j] = 0.0;
+  ga.g[j + 1] = -ga.sn[j] * ga.g[j];
+  ga.g[j] = ga.cs[j] * ga.g[j];
+  const double est = fabs(ga.g[j + 1]), w0 = sqrt(ga.h1[j + 1]);
+  ga.scal[0] = est;
+  ga.scal[1] = hn;
+  ga.scal[2] = w0;
+  if (ga.host_scal) {
+    ga.host_scal[0] = est;
+    ga.host_scal[1] = hn;
+    ga.host_scal[2] = w0;
+  }
+}
+
 // Classical Gram-Schmidt pass over rows: w holds column j+1 of V.
 //   UPD:  w -= sum_k h_k V_k           (k <= j)
 //   DOTS: part_k = sum V_k . w          (k <= j), after the update
 //   always: part_{j+1} = w . w
+// (per-block partial sums; the reduction over blocks is a separate launch,
+// since a grid-wide completion fence costs more than the launch)
 template <int MAXV, bool UPD, bool DOTS>
 __global__ __launch_bounds__(BLK) void k_cgs(int n, int nv, const double* __restrict__ V, size_t ldv,
                                              double* __restrict__ w, const double* __restrict__ h,
@@ -512,12 +563,51 @@ static void launch_cgs(int n, int nv, const double* V, size_t ldv, double* w, co
   HBGS_HIP(hipGetLastError());
 }
 
-void mdot(int n, int j, const double* V, size_t ldv, const double* w, double* part, hipStream_t s) {
+// out[k] = sum over blocks of part[k*nb + b] (fixed order per k)
+__global__ __launch_bounds__(BLK) void k_reduce(int nb, const double* __restrict__ part, double* __restrict__ out) {
+  __shared__ double sh[BLK / 64];
+  const double* p = part + (size_t)blockIdx.x * nb;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nb; b += BLK) acc += p[b];
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+void mdot_reduce(int nvec, int nblocks, const double* part, double* out, hipStream_t s) {
+  k_reduce<<<nvec, BLK, 0, s>>>(nblocks, part, out);
+  HBGS_HIP(hipGetLastError());
+}
+
+// one block: out[k] = sum over blocks of part[k*nb + b] for k < nvec (one
+// wave per vector, fixed order), then the Givens update from out
+constexpr int RG_BLK = 1024;
+constexpr int RG_MAXV = 66;
+__global__ __launch_bounds__(RG_BLK) void k_reduce_givens(int nvec, int nb, const double* __restrict__ part,
+                                                          double* __restrict__ out, GivensArgs ga) {
+  __shared__ double red[RG_MAXV];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int k = wave; k < nvec; k += RG_BLK / 64) {
+    const double* p = part + (size_t)k * nb;
+    double a = 0.0;
+    for (int b = lane; b < nb; b += 64) a += p[b];
+    a = lanes_sum<double>(a, 64);
+    if (lane == 0) red[k] = a;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nvec) out[threadIdx.x] = red[threadIdx.x];
+  if (threadIdx.x == 0) givens_update(ga, red);
+}
+
+void cgs_dots(int n, int j, const double* V, size_t ldv, const double* w, double* part, hipStream_t s) {
   launch_cgs<false, true>(n, j + 1, V, ldv, const_cast<double*>(w), nullptr, part, s);
 }
-void upd_mdot(int n, int j, const double* V, size_t ldv, double* w, const double* h, double* part,
-              hipStream_t s) {
-  launch_cgs<true, true>(n, j + 1, V, ldv, w, h, part, s);
+void cgs_update_dots(int n, int j, const double* V, size_t ldv, double* w, const double* h1, double* part,
+                     hipStream_t s) {
+  launch_cgs<true, true>(n, j + 1, V, ldv, w, h1, part, s);
+}
+void reduce_givens(int n, int j, const double* part, double* h2, const GivensArgs& ga, hipStream_t s) {
+  if (j + 2 > RG_MAXV) HBGS_FAIL(HBGS_EINVAL, "Gram-Schmidt basis too large");
+  k_reduce_givens<<<1, RG_BLK, 0, s>>>(j + 2, dot_blocks(n), part, h2, ga);
+  HBGS_HIP(hipGetLastError());
 }
 // w = (w - sum_k h_k V_k) / scal[1]  (k <= j); skipped when scal[1] == 0
 __global__ __launch_bounds__(BLK) void k_upd_scale(int n, int nv, const double* __restrict__ V, size_t ldv,
@@ -534,56 +624,6 @@ __global__ __launch_bounds__(BLK) void k_upd_scale(int n, int nv, const double* 
 void upd_scale(int n, int j, const double* V, size_t ldv, double* w, const double* h, const double* scal,
                hipStream_t s) {
   k_upd_scale<<<grid_for(n, BLK, 2048), BLK, 0, s>>>(n, j + 1, V, ldv, w, h, scal);
-  HBGS_HIP(hipGetLastError());
-}
-
-// out[k] = sum over blocks of part[k*nb + b] (fixed order per k)
-__global__ __launch_bounds__(BLK) void k_reduce(int nb, const double* __restrict__ part, double* __restrict__ out) {
-  __shared__ double sh[BLK / 64];
-  const double* p = part + (size_t)blockIdx.x * nb;
-  double acc = 0.0;
-  for (int b = threadIdx.x; b < nb; b += BLK) acc += p[b];
-  double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) out[blockIdx.x] = t;
-}
-void mdot_reduce(int nvec, int nblocks, const double* part, double* out, hipStream_t s) {
-  k_reduce<<<nvec, BLK, 0, s>>>(nblocks, part, out);
-  HBGS_HIP(hipGetLastError());
-}
-
-// Givens rotation update of Hessenberg column j (H is (m+1) x m, row-major
-// with leading dimension m).  h1/h2: first and second Gram-Schmidt
-// coefficients (k <= j); hn2 = ||w||^2 after both passes; w0sq = ||w||^2
-// before orthogonalisation.
-__global__ void k_givens(int j, int m, const double* h1, const double* h2, const double* w0sq, double* H, double* cs,
-                         double* sn, double* g, double* scal) {
-  if (threadIdx.x != 0) return;
-  for (int k = 0; k <= j; ++k) H[(size_t)k * m + j] = h1[k] + h2[k];
-  // ||w - V h2||^2 = ||w||^2 - ||h2||^2 for orthonormal V (h2[j+1] = ||w||^2 after the first pass)
-  double ss = h2[j + 1];
-  for (int k = 0; k <= j; ++k) ss -= h2[k] * h2[k];
-  double hn = ss > 0.0 ? sqrt(ss) : 0.0;
-  H[(size_t)(j + 1) * m + j] = hn;
-  for (int k = 0; k < j; ++k) {
-    double a = H[(size_t)k * m + j], b = H[(size_t)(k + 1) * m + j];
-    H[(size_t)k * m + j] = cs[k] * a + sn[k] * b;
-    H[(size_t)(k + 1) * m + j] = -sn[k] * a + cs[k] * b;
-  }
-  double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
-  double den = sqrt(a * a + b * b);
-  cs[j] = a / den;
-  sn[j] = b / den;
-  H[(size_t)j * m + j] = den;
-  H[(size_t)(j + 1) * m + j] = 0.0;
-  g[j + 1] = -sn[j] * g[j];
-  g[j] = cs[j] * g[j];
-  scal[0] = fabs(g[j + 1]);
-  scal[1] = hn;
-  scal[2] = sqrt(*w0sq);
-}
-void givens(int j, int m, const double* h1, const double* h2, const double* w0sq, double* H, double* cs,
-            double* sn, double* g, double* scal, hipStream_t s) {
-  k_givens<<<1, 64, 0, s>>>(j, m, h1, h2, w0sq, H, cs, sn, g, scal);
   HBGS_HIP(hipGetLastError());
 }
 
