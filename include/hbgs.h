@@ -182,6 +182,19 @@ hbgs_status hbgs_profile(hbgs_ctx *ctx, int32_t enable);
 int32_t hbgs_kernel_times(hbgs_ctx *ctx, char (*names)[48], double *total_ms, int64_t *launches,
                           double *bytes, int32_t cap);
 
+/* Route the persistent device memory of contexts created afterwards (the
+ * hierarchy and the GMRES workspace) through a caller's allocator, e.g. a
+ * framework's caching allocator: alloc(bytes, user) returns device memory of
+ * the current device or NULL (setup then fails with HBGS_ENOMEM);
+ * free(ptr, user) releases it.  alloc may be called from the library's setup
+ * threads (one per field) concurrently.  NULL for both restores hipMalloc /
+ * hipFree.  Each allocation is freed with the hook that made it, so the hook
+ * may change while contexts are alive; setup temporaries stay with HIP's
+ * stream-ordered allocator.  Returns HBGS_EINVAL if exactly one of the two is
+ * NULL.  Process-wide; not to be called concurrently with hbgs_setup. */
+hbgs_status hbgs_set_allocator(void *(*alloc)(size_t bytes, void *user), void (*free)(void *ptr, void *user),
+                               void *user);
+
 void hbgs_destroy(hbgs_ctx *ctx);
 const char *hbgs_last_error(void);
 

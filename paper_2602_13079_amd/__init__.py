@@ -65,6 +65,7 @@ EXPORTS = {
     "hbgs_get_aggregates": ("i32", ["p", "i32", "i32", "p", "p"]),
     "hbgs_profile": ("i32", ["p", "i32"]),
     "hbgs_kernel_times": ("i32", ["p", "p", "p", "p", "p", "i32"]),
+    "hbgs_set_allocator": ("i32", ["p", "p", "p"]),
     "hbgs_destroy": (None, ["p"]),
     "hbgs_last_error": ("str", []),
 }
@@ -126,6 +127,44 @@ def _dev(t, dtype, torch):
     if t.dtype != dtype:
         raise TypeError(f"expected {dtype}, got {t.dtype}")
     return t.contiguous()
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_alloc_hooks = []  # every installed pair stays alive: live contexts free through the hook that allocated
+
+
+def set_allocator(alloc=None, free=None):
+    """Route the persistent device memory of Solvers created afterwards
+    through alloc(nbytes) -> int pointer (0 on failure) and free(pointer);
+    no arguments restores hipMalloc / hipFree."""
+    lib = load()
+    if alloc is None and free is None:
+        _check(lib.hbgs_set_allocator(None, None, None))
+        return
+
+    def _a(nbytes, user):
+        try:
+            return int(alloc(int(nbytes))) or None
+        except Exception:  # reported to the library as an allocation failure
+            return None
+
+    def _f(ptr, user):
+        free(int(ptr))
+
+    hooks = (_ALLOC_FN(_a), _FREE_FN(_f))
+    _check(lib.hbgs_set_allocator(ctypes.cast(hooks[0], ctypes.c_void_p), ctypes.cast(hooks[1], ctypes.c_void_p),
+                                  None))
+    _alloc_hooks.append(hooks)
+
+
+def use_torch_allocator(enable=True):
+    """Serve Solver memory from torch's caching allocator (or stop doing so)."""
+    if not enable:
+        set_allocator()
+        return
+    import torch
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n), torch.cuda.caching_allocator_delete)
 
 
 class Solver:

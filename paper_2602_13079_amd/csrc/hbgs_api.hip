@@ -1355,6 +1355,18 @@ int32_t hbgs_kernel_times(hbgs_ctx* c, char (*names)[48], double* total_ms, int6
   return k;
 }
 
+hbgs_status hbgs_set_allocator(void* (*alloc)(size_t, void*), void (*free_fn)(void*, void*), void* user) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) {
+    set_error("hbgs_set_allocator: give both functions or neither");
+    return HBGS_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc.alloc = alloc;
+  g_alloc.free = free_fn;
+  g_alloc.user = alloc ? user : nullptr;
+  return HBGS_OK;
+}
+
 void hbgs_destroy(hbgs_ctx* c) { delete c; }
 
 }  // extern "C"

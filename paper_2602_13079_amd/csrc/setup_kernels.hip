@@ -827,10 +827,17 @@ void psmooth_fill(const DCsr& af, const int* agg, const double* dabs, double ome
 
 // ------------------------------------------------------------------ SpGEMM
 // C = A B, Gustavson row by row.  Each row of C owns an open-addressing
-// table (in a scratch buffer) whose slots accumulate the products a_ik b_kj
-// in the order they are generated, i.e. ascending k, starting from 0.0; the
-// occupied slots are then written out and sorted by column.  The pattern is
-// structural (entries that cancel to zero are kept).
+// table whose slots accumulate the products a_ik b_kj in the order they are
+// generated, i.e. ascending k, starting from 0.0; the occupied slots are
+// then written out in column order.  The pattern is structural (entries
+// that cancel to zero are kept).
+//
+// Rows whose tables fit in LDS are done by one wavefront each: the wave
+// walks the row of A in order and its lanes take the entries of one row of
+// B at a time.  The columns of one B row are distinct, so no two lanes
+// update the same slot in one step, and a wave's LDS operations complete in
+// program order, so each slot still sums its products in ascending k.  The
+// remaining rows use one thread each and a table in global scratch memory.
 __global__ void k_spgemm_ub(int n, const int* arp, const int* aci, const int* brp, int64_t* ub) {
   GRID_STRIDE(i, n) {
     int64_t u = 0;
@@ -838,22 +845,128 @@ __global__ void k_spgemm_ub(int n, const int* arp, const int* aci, const int* br
     ub[i] = u;
   }
 }
-__device__ __forceinline__ int64_t table_size(int64_t ub) {
+__host__ __device__ __forceinline__ int64_t table_size(int64_t ub) {
   if (ub == 0) return 0;
   int64_t t = 16;
   while (t < 2 * ub) t <<= 1;
   return t;
 }
-__global__ void k_spgemm_tsize(int n, const int64_t* ub, int64_t* ts) {
-  GRID_STRIDE(i, n) ts[i] = table_size(ub[i]);
-}
 __device__ __forceinline__ uint32_t hslot(int c, uint32_t mask) { return ((uint32_t)c * 2654435761u) & mask; }
 
+constexpr int SPG_WAVES = 4;          // rows (waves) per block
+constexpr int SPG_SYM_SLOTS = 4096;   // symbolic: keys per wave (16 KB)
+constexpr int SPG_NUM_SLOTS = 1024;   // numeric: keys and values per wave (12 KB)
+__device__ __forceinline__ int wave_table(int64_t need) {  // power of two >= 2 need, at least 64
+  int t = 64;
+  while (t < 2 * need) t <<= 1;
+  return t;
+}
+__device__ __forceinline__ bool sym_fits(int64_t ub) { return 2 * ub <= SPG_SYM_SLOTS; }
+__device__ __forceinline__ bool num_fits(int64_t cnt) { return 2 * cnt <= SPG_NUM_SLOTS; }
+
+// slot holding key c (claimed if absent); -1 if the table is full, which
+// the table sizes rule out (the caller reports it instead of looping)
+__device__ __forceinline__ int lds_claim(int* keys, uint32_t mask, int c, bool* fresh) {
+  uint32_t h = hslot(c, mask);
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    int prev = atomicCAS(&keys[h], -1, c);
+    if (prev == -1 || prev == c) {
+      *fresh = prev == -1;
+      return (int)h;
+    }
+    h = (h + 1) & mask;
+  }
+  *fresh = false;
+  return -1;
+}
+
+__global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_sym_wave(int n, const int* arp, const int* aci,
+                                                                   const int* brp, const int* bci,
+                                                                   const int64_t* ub, int* cnt, int* overflow) {
+  __shared__ int tab[SPG_WAVES][SPG_SYM_SLOTS];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * SPG_WAVES + wave;
+  if (i >= n || !sym_fits(ub[i])) return;
+  const int T = wave_table(ub[i]);
+  int* keys = tab[wave];
+  for (int q = lane; q < T; q += 64) keys[q] = -1;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint32_t mask = (uint32_t)(T - 1);
+  int u = 0;
+  for (int k = arp[i]; k < arp[i + 1]; ++k) {
+    const int kk = aci[k];
+    for (int q = brp[kk] + lane; q < brp[kk + 1]; q += 64) {
+      bool fresh;
+      if (lds_claim(keys, mask, bci[q], &fresh) < 0) atomicOr(overflow, 1);
+      u += fresh;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off, 64);
+  if (lane == 0) cnt[i] = u;
+}
+
+__global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_num_wave(int n, const int* arp, const int* aci,
+                                                                   const double* av, const int* brp,
+                                                                   const int* bci, const double* bv,
+                                                                   const int* crp, int* cci, double* cv,
+                                                                   int* overflow) {
+  __shared__ int tk[SPG_WAVES][SPG_NUM_SLOTS];
+  __shared__ double tv[SPG_WAVES][SPG_NUM_SLOTS];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = blockIdx.x * SPG_WAVES + wave;
+  if (i >= n) return;
+  const int o = crp[i], cnt = crp[i + 1] - o;
+  if (!num_fits(cnt)) return;
+  const int T = wave_table(cnt);
+  int* keys = tk[wave];
+  double* vals = tv[wave];
+  for (int q = lane; q < T; q += 64) {
+    keys[q] = -1;
+    vals[q] = 0.0;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  const uint32_t mask = (uint32_t)(T - 1);
+  for (int k = arp[i]; k < arp[i + 1]; ++k) {
+    const int kk = aci[k];
+    const double a = av[k];
+    for (int q = brp[kk] + lane; q < brp[kk + 1]; q += 64) {
+      bool fresh;
+      const int h = lds_claim(keys, mask, bci[q], &fresh);
+      if (h >= 0)
+        vals[h] += a * bv[q];
+      else
+        atomicOr(overflow, 1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  // each occupied slot goes to its rank among the row's columns
+  for (int q = lane; q < T; q += 64) {
+    const int c = keys[q];
+    if (c < 0) continue;
+    int rank = 0;
+    for (int p = 0; p < T; ++p) {
+      const int d = keys[p];
+      rank += (d >= 0) & (d < c);
+    }
+    cci[o + rank] = c;
+    cv[o + rank] = vals[q];
+  }
+}
+
+// one thread per row with its table in global scratch (rows with ts == 0
+// are done by the wave kernels)
 __global__ void k_spgemm_symbolic(int r0, int r1, const int* arp, const int* aci, const int* brp, const int* bci,
                                   const int64_t* toff, int64_t tbase, int* keys, int* cnt) {
   GRID_STRIDE(t, r1 - r0) {
     int i = r0 + (int)t;
     int64_t ts = toff[i + 1] - toff[i];
+    if (ts == 0) continue;
     int* tk = keys + (toff[i] - tbase);
     for (int64_t q = 0; q < ts; ++q) tk[q] = -1;
     int u = 0;
@@ -879,6 +992,7 @@ __global__ void k_spgemm_numeric(int r0, int r1, const int* arp, const int* aci,
   GRID_STRIDE(t, r1 - r0) {
     int i = r0 + (int)t;
     int64_t ts = toff[i + 1] - toff[i];
+    if (ts == 0) continue;
     int* tk = keys + (toff[i] - tbase);
     double* tv = vals + (toff[i] - tbase);
     for (int64_t q = 0; q < ts; ++q) {
@@ -919,51 +1033,85 @@ __global__ void k_spgemm_numeric(int r0, int r1, const int* arp, const int* aci,
     }
   }
 }
+// global table sizes of the rows the wave kernels leave over
+__global__ void k_spgemm_tsize_sym(int n, const int64_t* ub, int64_t* ts) {
+  GRID_STRIDE(i, n) ts[i] = sym_fits(ub[i]) ? 0 : table_size(ub[i]);
+}
+__global__ void k_spgemm_tsize_num(int n, const int64_t* ub, const int* crp, int64_t* ts) {
+  GRID_STRIDE(i, n) ts[i] = num_fits(crp[i + 1] - crp[i]) ? 0 : table_size(ub[i]);
+}
+
+// row batches whose global tables fit the scratch budget; returns the largest batch
+static int64_t batch_rows(const std::vector<int64_t>& off, int n, std::vector<int>& cuts) {
+  const int64_t budget = int64_t(64) << 20;  // table slots
+  cuts.assign(1, 0);
+  int64_t maxbatch = 0;
+  while (cuts.back() < n) {
+    int r0 = cuts.back();
+    int r1 = (int)(std::upper_bound(off.begin() + r0 + 1, off.end(), off[r0] + budget) - off.begin()) - 1;
+    if (r1 <= r0) r1 = r0 + 1;
+    if (r1 > n) r1 = n;
+    maxbatch = std::max(maxbatch, off[r1] - off[r0]);
+    cuts.push_back(r1);
+  }
+  return maxbatch;
+}
 
 void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
   const int n = a.n;
   c.n = n;
   c.m = b.m;
   Tmp<int64_t> ub(n), ts(n), toff(n + 1);
+  Tmp<int> cnt(n), overflow(1);
+  HBGS_HIP(hipMemsetAsync(overflow.p, 0, sizeof(int), s));
   k_spgemm_ub<<<grid_for(n, BLK), BLK, 0, s>>>(n, a.rp, a.ci, b.rp, ub.p);
-  k_spgemm_tsize<<<grid_for(n, BLK), BLK, 0, s>>>(n, ub.p, ts.p);
   HBGS_HIP(hipGetLastError());
-  scan_i64(ts.p, toff.p, n, s);
+  const unsigned wgrid = (unsigned)(((int64_t)n + SPG_WAVES - 1) / SPG_WAVES);
+  // symbolic: distinct columns per row
+  k_spgemm_sym_wave<<<wgrid, 64 * SPG_WAVES, 0, s>>>(n, a.rp, a.ci, b.rp, b.ci, ub.p, cnt.p, overflow.p);
+  k_spgemm_tsize_sym<<<grid_for(n, BLK), BLK, 0, s>>>(n, ub.p, ts.p);
+  HBGS_HIP(hipGetLastError());
   std::vector<int64_t> h_off(n + 1);
-  HBGS_HIP(hipMemcpyAsync(h_off.data(), toff.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
-  HBGS_HIP(hipStreamSynchronize(s));
-  // batches of rows whose tables fit the scratch budget
-  const int64_t budget = std::max<int64_t>(int64_t(64) << 20, (int64_t)1 << 26);  // table slots
-  std::vector<int> cuts{0};
-  int64_t maxbatch = 0;
-  while (cuts.back() < n) {
-    int r0 = cuts.back();
-    int r1 = (int)(std::upper_bound(h_off.begin() + r0 + 1, h_off.end(), h_off[r0] + budget) - h_off.begin()) - 1;
-    if (r1 <= r0) r1 = r0 + 1;
-    if (r1 > n) r1 = n;
-    maxbatch = std::max(maxbatch, h_off[r1] - h_off[r0]);
-    cuts.push_back(r1);
-  }
-  Tmp<int> keys(maxbatch);
-  Tmp<int> cnt(n);
-  for (size_t q = 0; q + 1 < cuts.size(); ++q) {
-    int r0 = cuts[q], r1 = cuts[q + 1];
-    k_spgemm_symbolic<<<grid_for(r1 - r0, 64), 64, 0, s>>>(r0, r1, a.rp, a.ci, b.rp, b.ci, toff.p, h_off[r0],
-                                                           keys.p, cnt.p);
-    HBGS_HIP(hipGetLastError());
+  std::vector<int> cuts;
+  if (scan_i64(ts.p, toff.p, n, s) > 0) {
+    HBGS_HIP(hipMemcpyAsync(h_off.data(), toff.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+    HBGS_HIP(hipStreamSynchronize(s));
+    Tmp<int> keys(batch_rows(h_off, n, cuts));
+    for (size_t q = 0; q + 1 < cuts.size(); ++q) {
+      int r0 = cuts[q], r1 = cuts[q + 1];
+      if (h_off[r1] == h_off[r0]) continue;
+      k_spgemm_symbolic<<<grid_for(r1 - r0, 64), 64, 0, s>>>(r0, r1, a.rp, a.ci, b.rp, b.ci, toff.p, h_off[r0],
+                                                             keys.p, cnt.p);
+      HBGS_HIP(hipGetLastError());
+    }
   }
   c.rp = pool.make<int>(n + 1);
   c.nnz = counts_to_rowptr(cnt.p, c.rp, n, s);
   c.ci = pool.make<int>(c.nnz);
   c.v = pool.make<double>(c.nnz);
-  Tmp<double> vals(maxbatch);
-  for (size_t q = 0; q + 1 < cuts.size(); ++q) {
-    int r0 = cuts[q], r1 = cuts[q + 1];
-    k_spgemm_numeric<<<grid_for(r1 - r0, 64), 64, 0, s>>>(r0, r1, a.rp, a.ci, a.v, b.rp, b.ci, b.v, toff.p,
-                                                          h_off[r0], keys.p, vals.p, c.rp, c.ci, c.v);
-    HBGS_HIP(hipGetLastError());
+  // numeric
+  k_spgemm_num_wave<<<wgrid, 64 * SPG_WAVES, 0, s>>>(n, a.rp, a.ci, a.v, b.rp, b.ci, b.v, c.rp, c.ci, c.v,
+                                                     overflow.p);
+  k_spgemm_tsize_num<<<grid_for(n, BLK), BLK, 0, s>>>(n, ub.p, c.rp, ts.p);
+  HBGS_HIP(hipGetLastError());
+  if (scan_i64(ts.p, toff.p, n, s) > 0) {
+    HBGS_HIP(hipMemcpyAsync(h_off.data(), toff.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+    HBGS_HIP(hipStreamSynchronize(s));
+    const int64_t maxbatch = batch_rows(h_off, n, cuts);
+    Tmp<int> keys(maxbatch);
+    Tmp<double> vals(maxbatch);
+    for (size_t q = 0; q + 1 < cuts.size(); ++q) {
+      int r0 = cuts[q], r1 = cuts[q + 1];
+      if (h_off[r1] == h_off[r0]) continue;
+      k_spgemm_numeric<<<grid_for(r1 - r0, 64), 64, 0, s>>>(r0, r1, a.rp, a.ci, a.v, b.rp, b.ci, b.v, toff.p,
+                                                            h_off[r0], keys.p, vals.p, c.rp, c.ci, c.v);
+      HBGS_HIP(hipGetLastError());
+    }
   }
+  int ovf = 0;
+  HBGS_HIP(hipMemcpyAsync(&ovf, overflow.p, sizeof(int), hipMemcpyDeviceToHost, s));
   HBGS_HIP(hipStreamSynchronize(s));
+  if (ovf) HBGS_FAIL(HBGS_ESETUP, "sparse product: accumulator table overflow");
 }
 
 // ------------------------------------------------------- dense coarsest LU

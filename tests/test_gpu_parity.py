@@ -296,6 +296,60 @@ def test_setup_deterministic(torch_dev):
             assert all(np.array_equal(p, q) for p, q in zip(a[:3], b[:3]))
 
 
+def test_setup_concurrent_matches_sequential(torch_dev):
+    """Building the field hierarchies on concurrent threads/streams gives the
+    same hierarchy and the same solve, bit for bit."""
+    torch, dev = torch_dev
+    s = _system("ragged7x5x9_6f_cm40")
+    g1 = _solver(torch, dev, s, coarse_max=40, setup_concurrent=1)
+    g0 = _solver(torch, dev, s, coarse_max=40, setup_concurrent=0)
+    for f in range(s.nf):
+        assert g1.stats()["levels"][f] == g0.stats()["levels"][f]
+        for l in range(g1.stats()["levels"][f]):
+            for w in ("A", "P", "R", "AT") if l + 1 < g1.stats()["levels"][f] else ("A", "AT"):
+                a, b = g1.get_level(f, l, w), g0.get_level(f, l, w)
+                assert all(np.array_equal(p, q) for p, q in zip(a[:3], b[:3])), (f, l, w)
+    b = torch.from_numpy(s.b).to(dev)
+    x1, st1, it1, _ = g1.solve(b)
+    x0, st0, it0, _ = g0.solve(b)
+    assert st1 == st0 == 0 and it1 == it0
+    assert torch.equal(x1, x0)
+
+
+def test_allocator_hook(torch_dev):
+    """Solver memory served by torch's caching allocator through
+    hbgs_set_allocator: same results, and every block handed back."""
+    torch, dev = torch_dev
+    import paper_2602_13079_amd as H
+    s = _system("cfg0_cm64")
+    ref = _solver(torch, dev, s, coarse_max=64)
+    b = torch.from_numpy(s.b).to(dev)
+    xr, _, itr, _ = ref.solve(b)
+    live = {}
+
+    def alloc(n):
+        p = torch.cuda.caching_allocator_alloc(n)
+        live[p] = n
+        return p
+
+    def free(p):
+        del live[p]
+        torch.cuda.caching_allocator_delete(p)
+
+    H.set_allocator(alloc, free)
+    try:
+        g = _solver(torch, dev, s, coarse_max=64)
+    finally:
+        H.set_allocator()
+    assert len(live) > 0
+    x, st, it, _ = g.solve(b)  # workspace allocated after the reset: hipMalloc
+    assert st == 0 and it == itr
+    assert torch.equal(x, xr)
+    del g
+    torch.cuda.synchronize()
+    assert not live
+
+
 @pytest.mark.parametrize("field", [0, 2])
 def test_full_size_hierarchy_cfg2(torch_dev, field):
     """4.2M-DOF system: the complete hierarchy of a field block, built by the
