@@ -77,7 +77,16 @@ __global__ __launch_bounds__(SBLK) void k_csr_rows(int n, const int* __restrict_
     if (r < r1 && lane == 0) pre[q] = epi.load(r);
   }
   const int s0 = rp[r0], s1 = rp[r1];
-  for (int k = s0 + threadIdx.x; k < s1; k += SBLK) prod[k - s0] = (TACC)v[k] * (TACC)lx(ci[k]);
+  // two independent entries per step keep more gathers in flight
+  int k = s0 + threadIdx.x;
+  for (; k + SBLK < s1; k += 2 * SBLK) {
+    const int c0 = ci[k], c1 = ci[k + SBLK];
+    const TV w0 = v[k], w1 = v[k + SBLK];
+    const TACC x0 = (TACC)lx(c0), x1 = (TACC)lx(c1);
+    prod[k - s0] = (TACC)w0 * x0;
+    prod[k + SBLK - s0] = (TACC)w1 * x1;
+  }
+  if (k < s1) prod[k - s0] = (TACC)v[k] * (TACC)lx(ci[k]);
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
