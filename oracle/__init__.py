@@ -25,6 +25,9 @@ class Options(ctypes.Structure):
         ("cheb_boost", ctypes.c_double), ("eig_iters", ctypes.c_int32), ("sa_damping", ctypes.c_double),
         ("omega_override", ctypes.c_double), ("coarse_max", ctypes.c_int32), ("max_levels", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("theta", ctypes.c_double * 16), ("exact_leaves", ctypes.c_int32),
+        ("block_jacobi", ctypes.c_int32), ("nested", ctypes.c_int32), ("inner_restart", ctypes.c_int32),
+        ("inner_max_iters", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
+        ("field_cheb_degree", ctypes.c_int32 * 16),
     ]
 
 
@@ -103,6 +106,11 @@ def options(**kw) -> Options:
                 o.theta[i] = 0.0
             for i, t in enumerate(v):
                 o.theta[i] = t
+        elif k == "field_cheb_degree":
+            for i in range(16):
+                o.field_cheb_degree[i] = 0
+            for i, t in enumerate(v):
+                o.field_cheb_degree[i] = t
         else:
             setattr(o, k, v)
     return o

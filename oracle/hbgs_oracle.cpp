@@ -34,6 +34,7 @@
 // Setup reductions over long vectors use 256-element chunks summed in order,
 // then the chunk sums in order.
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
@@ -114,6 +115,13 @@ typedef struct {
   uint64_t seed;        // salt for aggregation priorities and start vectors
   double theta[16];     // strength-of-connection threshold per field
   int32_t exact_leaves; // tests: leaf solve = dense LU of the diagonal block
+  int32_t block_jacobi; // 1: every coupling dropped (block Jacobi: each field on its own)
+  int32_t nested;       // 1: each child of the outermost group is solved by an inner
+                        //    flexible GMRES preconditioned by that child's own sweep
+  int32_t inner_restart;   // inner GMRES restart length
+  int32_t inner_max_iters; // cap on inner Arnoldi steps per solve
+  double inner_rtol;       // inner target ||t - A_GG y|| / ||t||
+  int32_t field_cheb_degree[16]; // > 0: Chebyshev degree of that field's V-cycle
 } or_options;
 }
 
@@ -659,6 +667,8 @@ struct Ctx {
   std::vector<DenseLU> exact;  // per field (exact_leaves)
   std::vector<Node> nodes;     // nodes[0] = root
   std::vector<int> leaf_order;
+  std::vector<or_options> fo;  // per-field options (Chebyshev degree)
+  std::vector<CsrD> gA, gAT;   // nested form: diagonal block of each child of the root (and transpose)
 };
 
 int parse_tree(Ctx& c, const int* tree, int len) {
@@ -735,7 +745,7 @@ void leaf_solve(const Ctx& c, int f, int transpose, const T* t, T* z) {
     for (int i = 0; i < n; ++i) z[i] = (T)zd[i];
     return;
   }
-  vcycle<T>(c.amg[f], c.o, 0, transpose, t, z);
+  vcycle<T>(c.amg[f], c.fo[f], 0, transpose, t, z);
 }
 
 template <class T>
@@ -772,8 +782,9 @@ void bgs_node(const Ctx& c, int id, int transpose, const T* r, T* z) {
     std::vector<T> t(c.n, (T)0);
     for (int i = ch.lo; i < ch.hi; ++i) {
       T s = r[i];
-      for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
-        if (A.ci[k] >= clo && A.ci[k] < chi) s = s - A.v[k] * z[A.ci[k]];
+      if (!c.o.block_jacobi)
+        for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
+          if (A.ci[k] >= clo && A.ci[k] < chi) s = s - A.v[k] * z[A.ci[k]];
       t[i] = s;
     }
     int cid = nd.kids[transpose ? nk - 1 - q : q];
@@ -781,16 +792,17 @@ void bgs_node(const Ctx& c, int id, int transpose, const T* r, T* z) {
   }
 }
 
-// z = M^-1 r in permuted ordering (T-precision sweep, result in double)
-void precond(const Ctx& c, int transpose, const double* r, double* z) {
+// z = sweep of node `id` applied to r, in T precision (vectors of length n
+// in the permuted ordering; only the node's rows are read and written)
+void node_sweep(const Ctx& c, int id, int transpose, const double* r, double* z) {
   if (c.o.precision == 1) {
-    std::vector<float> rf(c.n), zf(c.n, 0.0f);
+    std::vector<float> rf(c.n, 0.0f), zf(c.n, 0.0f);
     for (int i = 0; i < c.n; ++i) rf[i] = (float)r[i];
-    bgs_node<float>(c, 0, transpose, rf.data(), zf.data());
+    bgs_node<float>(c, id, transpose, rf.data(), zf.data());
     for (int i = 0; i < c.n; ++i) z[i] = (double)zf[i];
   } else {
     std::vector<double> zz(c.n, 0.0);
-    bgs_node<double>(c, 0, transpose, r, zz.data());
+    bgs_node<double>(c, id, transpose, r, zz.data());
     for (int i = 0; i < c.n; ++i) z[i] = zz[i];
   }
 }
@@ -801,15 +813,18 @@ double dot(const std::vector<double>& x, const std::vector<double>& y) {
   return s;
 }
 
-// Flexible right-preconditioned GMRES(m) in the permuted ordering.
-int gmres(const Ctx& c, int transpose, const std::vector<double>& b, std::vector<double>& x,
-          int* iters, double* hist, int cap, int* hlen) {
-  const int n = c.n, m = c.o.restart;
-  const CsrD& A = transpose ? c.ApT : c.Ap;
+// Flexible right-preconditioned GMRES(m) for A x = b (x holds the start):
+// z_j = M(v_j) is stored, so M may change from step to step (Sec. 3.2, last
+// paragraph).  Classical Gram-Schmidt applied twice; Givens rotations; the
+// residual estimate |g_{j+1}| / ||b|| is checked after every step and the
+// true residual at the end of every cycle.  Returns 0 converged, 1 cap hit.
+int fgmres(const CsrD& A, int m, double rtol, int max_iters, const std::function<void(const double*, double*)>& M,
+           const std::vector<double>& b, std::vector<double>& x, int* iters, double* hist, int cap, int* hlen) {
+  const int n = A.n;
   *iters = 0;
   *hlen = 0;
   auto push = [&](double v) {
-    if (*hlen < cap) hist[*hlen] = v;
+    if (hist && *hlen < cap) hist[*hlen] = v;
     (*hlen)++;
   };
   double bnorm = std::sqrt(dot(b, b));
@@ -830,14 +845,14 @@ int gmres(const Ctx& c, int transpose, const std::vector<double>& b, std::vector
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), w(n), h1(m + 1), h2(m + 1);
   auto Hs = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
   for (;;) {
-    if (beta / bnorm <= c.o.rtol) return 0;
-    if (*iters >= c.o.max_iters) return 1;
+    if (beta / bnorm <= rtol) return 0;
+    if (*iters >= max_iters) return 1;
     for (int i = 0; i < n; ++i) V[0][i] = r[i] / beta;
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int jend = 0;
     for (int j = 0; j < m; ++j) {
-      precond(c, transpose, V[j].data(), Z[j].data());
+      M(V[j].data(), Z[j].data());
       spmv(A, Z[j].data(), w.data());
       double w0 = std::sqrt(dot(w, w));
       for (int pass = 0; pass < 2; ++pass) {
@@ -869,7 +884,7 @@ int gmres(const Ctx& c, int transpose, const std::vector<double>& b, std::vector
       double est = std::fabs(g[j + 1]) / bnorm;
       push(est);
       jend = j + 1;
-      if (est <= c.o.rtol || hn <= 1e-14 * w0 || *iters >= c.o.max_iters) break;
+      if (est <= rtol || hn <= 1e-14 * w0 || *iters >= max_iters) break;
     }
     std::vector<double> y(jend);
     for (int i = jend - 1; i >= 0; --i) {
@@ -880,8 +895,63 @@ int gmres(const Ctx& c, int transpose, const std::vector<double>& b, std::vector
     for (int k = 0; k < jend; ++k)
       for (int i = 0; i < n; ++i) x[i] += y[k] * Z[k][i];
     beta = true_resid();
-    if (*hlen - 1 < cap) hist[*hlen - 1] = beta / bnorm;
+    if (hist && *hlen - 1 < cap) hist[*hlen - 1] = beta / bnorm;
   }
+}
+
+// Nested form (Sec. 3.2: the blocks of the outermost sweep are inverted by
+// an inner GMRES(30) to a 1e-6 relative residual, preconditioned by their
+// own block Gauss-Seidel sweeps): the children of the root are visited as in
+// the sweep, child q receiving its right-hand side minus the couplings to
+// the children already solved, and its block is solved by an inner flexible
+// GMRES from a zero start, preconditioned by the child's sweep.  In the
+// mixed mode each child's result is rounded to single precision, as the
+// stored Krylov direction is.
+void nested_precond(const Ctx& c, int transpose, const double* r, double* z) {
+  const Node& root = c.nodes[0];
+  const CsrD& A = transpose ? c.ApT : c.Ap;
+  const int nk = (int)root.kids.size();
+  std::fill(z, z + c.n, 0.0);
+  for (int q = 0; q < nk; ++q) {
+    const int kq = transpose ? nk - 1 - q : q;
+    const int cid = root.kids[kq];
+    const Node& ch = c.nodes[cid];
+    const int clo = transpose ? ch.hi : root.lo, chi = transpose ? root.hi : ch.lo;
+    const int m = ch.hi - ch.lo;
+    std::vector<double> t(m), y(m, 0.0);
+    for (int i = ch.lo; i < ch.hi; ++i) {
+      double s = r[i];
+      if (!c.o.block_jacobi)
+        for (int k = A.rp[i]; k < A.rp[i + 1]; ++k)
+          if (A.ci[k] >= clo && A.ci[k] < chi) s = s - A.v[k] * z[A.ci[k]];
+      t[i - ch.lo] = s;
+    }
+    auto M = [&](const double* v, double* out) {
+      std::vector<double> vf(c.n, 0.0), zf(c.n, 0.0);
+      std::copy(v, v + m, vf.begin() + ch.lo);
+      node_sweep(c, cid, transpose, vf.data(), zf.data());
+      std::copy(zf.begin() + ch.lo, zf.begin() + ch.hi, out);
+    };
+    int it = 0, hl = 0;
+    fgmres(transpose ? c.gAT[kq] : c.gA[kq], c.o.inner_restart, c.o.inner_rtol, c.o.inner_max_iters, M, t, y, &it,
+           nullptr, 0, &hl);
+    for (int i = 0; i < m; ++i) z[ch.lo + i] = c.o.precision == 1 ? (double)(float)y[i] : y[i];
+  }
+}
+
+// z = M^-1 r in permuted ordering (result in double)
+void precond(const Ctx& c, int transpose, const double* r, double* z) {
+  if (c.o.nested)
+    nested_precond(c, transpose, r, z);
+  else
+    node_sweep(c, 0, transpose, r, z);
+}
+
+// the outer solve: flexible GMRES on the permuted system
+int gmres(const Ctx& c, int transpose, const std::vector<double>& b, std::vector<double>& x, int* iters,
+          double* hist, int cap, int* hlen) {
+  auto M = [&](const double* v, double* out) { precond(c, transpose, v, out); };
+  return fgmres(transpose ? c.ApT : c.Ap, c.o.restart, c.o.rtol, c.o.max_iters, M, b, x, iters, hist, cap, hlen);
 }
 
 }  // namespace
@@ -910,6 +980,12 @@ void or_default_options(or_options* o) {
   for (int f = 0; f < 16; ++f) o->theta[f] = 0.0;
   o->theta[0] = 0.04;
   o->exact_leaves = 0;
+  o->block_jacobi = 0;
+  o->nested = 0;
+  o->inner_restart = 30;
+  o->inner_max_iters = 300;
+  o->inner_rtol = 1e-6;
+  for (int f = 0; f < 16; ++f) o->field_cheb_degree[f] = 0;
 }
 
 const char* or_last_error(void) { return g_err.msg.c_str(); }
@@ -1087,6 +1163,19 @@ or_ctx* or_setup(int n, const int* rp, const int* ci, const double* v, int nf, c
   c->Apf = cast_csr<float>(ap);
   c->ApTf = cast_csr<float>(c->ApT);
   node_ranges(*c, 0);
+  if (o->inner_restart < 1 || o->inner_restart > 64 || o->inner_max_iters < 0 || !(o->inner_rtol >= 0.0)) {
+    g_err = {-1, "invalid inner solver options"};
+    delete c;
+    return nullptr;
+  }
+  c->fo.assign(nf, *o);
+  for (int f = 0; f < nf && f < 16; ++f)
+    if (o->field_cheb_degree[f] > 0) c->fo[f].cheb_degree = o->field_cheb_degree[f];
+  if (o->nested)
+    for (int k : c->nodes[0].kids) {
+      c->gA.push_back(block(ap, c->nodes[k].lo, c->nodes[k].hi));
+      c->gAT.push_back(block(c->ApT, c->nodes[k].lo, c->nodes[k].hi));
+    }
   c->amg.resize(nf);
   c->exact.resize(nf);
   for (int f = 0; f < nf; ++f) {
@@ -1098,7 +1187,7 @@ or_ctx* or_setup(int n, const int* rp, const int* ci, const double* v, int nf, c
         return nullptr;
       }
     } else {
-      int rc = setup_amg(blk, o->theta[f], *o, field_salt(o->seed, f), c->amg[f]);
+      int rc = setup_amg(blk, o->theta[f], c->fo[f], field_salt(o->seed, f), c->amg[f]);
       if (rc != 0) {
         delete c;
         return nullptr;
