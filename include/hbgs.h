@@ -76,6 +76,18 @@ typedef struct {
                                built concurrently, one host thread and HIP stream per
                                field (the results do not depend on it); 0: one after
                                another on the caller's stream */
+  int32_t block_jacobi;  /* 1: every coupling block is dropped, each field is solved on
+                            its own (block Jacobi; all fields run concurrently); 0
+                            (default): block Gauss-Seidel */
+  int32_t nested;        /* 1: nested form of Sec. 3.2 -- each child of the outermost
+                            group (e.g. the voltage and the non-voltage block) is solved
+                            by an inner flexible GMRES preconditioned by that child's own
+                            sweep, from a zero start; 0 (default): one sweep */
+  int32_t inner_restart;   /* inner GMRES restart length, 1..64 (default 30) */
+  int32_t inner_max_iters; /* cap on inner Arnoldi steps per inner solve (default 300) */
+  double inner_rtol;       /* inner stopping test ||t - A_GG y|| / ||t|| (default 1e-6) */
+  int32_t field_cheb_degree[HBGS_MAX_FIELDS]; /* > 0: Chebyshev degree of that field's
+                            V-cycle (e.g. 4 on the voltage leaves, Sec. 4); 0: cheb_degree */
 } hbgs_options;
 
 typedef struct {

@@ -35,7 +35,9 @@ class Options(ctypes.Structure):
         ("cheb_boost", ctypes.c_double), ("eig_iters", ctypes.c_int32), ("sa_damping", ctypes.c_double),
         ("coarse_max", ctypes.c_int32), ("max_levels", ctypes.c_int32), ("seed", ctypes.c_uint64),
         ("theta", ctypes.c_double * MAX_FIELDS), ("use_graphs", ctypes.c_int32),
-        ("setup_concurrent", ctypes.c_int32),
+        ("setup_concurrent", ctypes.c_int32), ("block_jacobi", ctypes.c_int32), ("nested", ctypes.c_int32),
+        ("inner_restart", ctypes.c_int32), ("inner_max_iters", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
+        ("field_cheb_degree", ctypes.c_int32 * MAX_FIELDS),
     ]
 
 
@@ -101,11 +103,12 @@ def default_options(**kw) -> Options:
     o = Options()
     load().hbgs_default_options(ctypes.byref(o))
     for k, v in kw.items():
-        if k == "theta":
+        if k in ("theta", "field_cheb_degree"):
+            arr = getattr(o, k)
             for i in range(MAX_FIELDS):
-                o.theta[i] = 0.0
+                arr[i] = 0
             for i, t in enumerate(v):
-                o.theta[i] = t
+                arr[i] = t
         else:
             setattr(o, k, v)
     return o

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <thread>
 #include <vector>
@@ -198,6 +199,71 @@ struct IterGraph {
   hipGraphExec_t exec = nullptr;
 };
 
+// Workspace of one flexible GMRES (the outer solve, or the inner solve of a
+// group in the nested form): basis V ((m+1) x n, FP64, leading dimension ld),
+// stored directions Z (m x n; FP32 in the mixed mode), right-hand side bp,
+// iterate xp, Gram-Schmidt partial sums, Hessenberg data, and a pinned host
+// slot that the Givens step writes the residual estimate to.
+struct Krylov {
+  int n = 0, m = 0;
+  size_t ld = 0;
+  double *V = nullptr, *Zd = nullptr;
+  float* Zf = nullptr;
+  double *bp = nullptr, *xp = nullptr, *r = nullptr, *tmp = nullptr, *part = nullptr, *h1 = nullptr, *h2 = nullptr,
+         *hn2 = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *scal = nullptr;
+  double* host = nullptr;      // pinned
+  double* host_dev = nullptr;  // its device-side address
+  Krylov() = default;
+  Krylov(const Krylov&) = delete;
+  Krylov& operator=(const Krylov&) = delete;
+  ~Krylov() {
+    if (host) (void)hipHostFree(host);
+  }
+  void ensure(Pool& pool, int n_, int m_, int precision) {
+    if (V) {
+      if (precision == 1 && !Zf) Zf = pool.make<float>((size_t)m * ld);
+      if (precision == 0 && !Zd) Zd = pool.make<double>((size_t)m * ld);
+      return;
+    }
+    n = n_;
+    m = m_;
+    ld = ((size_t)n + 63) / 64 * 64;
+    V = pool.make<double>((size_t)(m + 1) * ld);
+    if (precision == 1)
+      Zf = pool.make<float>((size_t)m * ld);
+    else
+      Zd = pool.make<double>((size_t)m * ld);
+    bp = pool.make<double>(n);
+    xp = pool.make<double>(n);
+    r = pool.make<double>(n);
+    tmp = pool.make<double>(n);
+    part = pool.make<double>((size_t)(m + 2) * solve::dot_blocks(n));
+    h1 = pool.make<double>(m + 2);
+    h2 = pool.make<double>(m + 2);
+    hn2 = pool.make<double>(2);
+    H = pool.make<double>((size_t)(m + 1) * m);
+    cs = pool.make<double>(m);
+    sn = pool.make<double>(m);
+    g = pool.make<double>(m + 1);
+    y = pool.make<double>(m);
+    scal = pool.make<double>(4);
+    HBGS_HIP(hipHostMalloc((void**)&host, 8 * sizeof(double), hipHostMallocDefault));
+    HBGS_HIP(hipHostGetDevicePointer((void**)&host_dev, host, 0));
+  }
+};
+
+// Nested form: one child of the outermost group of the field tree.  Its
+// fields are contiguous in the permuted ordering.
+struct Group {
+  int lo = 0, hi = 0;
+  std::vector<int> fields;    // leaves in visiting order
+  DCsr A, AT;                 // its diagonal block and transpose (columns relative to lo)
+  DCsr lower, upperT;         // couplings to earlier / later groups (global columns)
+  SweepPlan plan[2];          // the group's own sweep (forward, adjoint)
+  std::unique_ptr<Krylov> K;  // inner solver workspace
+  int n() const { return hi - lo; }
+};
+
 }  // namespace hbgs
 
 struct hbgs_ctx {
@@ -212,16 +278,13 @@ struct hbgs_ctx {
   hbgs::DCsr Ap, ApT;
   std::vector<int> leaf_order, f_lo, f_hi;
   std::vector<hbgs::Field> F;
-  // GMRES workspace (permuted ordering)
+  // outer GMRES workspace (permuted ordering)
   int m = 0;
-  size_t ld = 0;
-  double *V = nullptr, *Zd = nullptr;
-  float* Zf = nullptr;
-  double *bp = nullptr, *xp = nullptr, *r = nullptr, *part = nullptr, *h1 = nullptr, *h2 = nullptr,
-         *hn2 = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *scal = nullptr,
-         *tmp = nullptr;
-  double* host_scal = nullptr;      // pinned
-  double* host_scal_dev = nullptr;  // its device-side address
+  hbgs::Krylov K;
+  // nested form: the children of the outermost group
+  std::vector<std::vector<int>> group_fields;
+  std::vector<int> group_of;  // field -> index in group_fields
+  std::vector<hbgs::Group> G;
   hbgs::Profiler prof;
   hbgs_stats_t stats{};
   // concurrent sweep
@@ -246,7 +309,6 @@ struct hbgs_ctx {
     if (sm) (void)hipStreamDestroy(sm);
     if (join_in) (void)hipEventDestroy(join_in);
     if (join_out) (void)hipEventDestroy(join_out);
-    if (host_scal) (void)hipHostFree(host_scal);
     for (auto& st : fstream)
       if (st) (void)hipStreamDestroy(st);
     for (auto& e : fdone)
@@ -272,17 +334,27 @@ static void validate_options(const hbgs_options& o) {
   if (o.eig_iters < 0 || !(o.sa_damping > 0.0)) HBGS_FAIL(HBGS_EINVAL, "bad eigenvalue / damping options");
   if (o.coarse_max < 1 || o.coarse_max > 8000) HBGS_FAIL(HBGS_EINVAL, "coarse_max must be in [1, 8000]");
   if (o.max_levels < 1 || o.max_levels > HBGS_MAX_LEVELS) HBGS_FAIL(HBGS_EINVAL, "max_levels out of range");
+  if ((o.block_jacobi != 0 && o.block_jacobi != 1) || (o.nested != 0 && o.nested != 1) ||
+      (o.setup_concurrent != 0 && o.setup_concurrent != 1))
+    HBGS_FAIL(HBGS_EINVAL, "block_jacobi, nested and setup_concurrent must be 0 or 1");
+  if (o.inner_restart < 1 || o.inner_restart > 64) HBGS_FAIL(HBGS_EINVAL, "inner_restart must be in [1, 64]");
+  if (o.inner_max_iters < 0 || !(o.inner_rtol >= 0.0)) HBGS_FAIL(HBGS_EINVAL, "bad inner solver options");
+  for (int f = 0; f < HBGS_MAX_FIELDS; ++f)
+    if (o.field_cheb_degree[f] < 0 || o.field_cheb_degree[f] > 8)
+      HBGS_FAIL(HBGS_EINVAL, "field_cheb_degree must be in [0, 8]");
 }
 
 static void parse_tree(hbgs_ctx* c, const int32_t* tree, int len) {
   std::vector<char> seen(c->nf, 0);
   int depth = 0, closed_root = 0;
   c->leaf_order.clear();
+  c->group_fields.clear();
   for (int t = 0; t < len; ++t) {
     int code = tree[t];
     if (closed_root) HBGS_FAIL(HBGS_EINVAL, "group tree: entries after the outermost group");
     if (code == -1) {
       ++depth;
+      if (depth == 2) c->group_fields.push_back({});
     } else if (code == -2) {
       if (depth == 0) HBGS_FAIL(HBGS_EINVAL, "group tree: unbalanced close");
       if (--depth == 0) closed_root = 1;
@@ -290,6 +362,8 @@ static void parse_tree(hbgs_ctx* c, const int32_t* tree, int len) {
       if (depth == 0 || seen[code]) HBGS_FAIL(HBGS_EINVAL, "group tree: field outside a group or repeated");
       seen[code] = 1;
       c->leaf_order.push_back(code);
+      if (depth == 1) c->group_fields.push_back({});  // a leaf directly under the root: its own group
+      c->group_fields.back().push_back(code);
     } else {
       HBGS_FAIL(HBGS_EINVAL, "group tree: invalid code");
     }
@@ -460,7 +534,9 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
     L.dinvf = pool.make<float>(n);
     setup::reciprocal(n, d.p, L.dinv, L.dinvf, s);
     L.lam_cheb = setup::power_estimate(L.A, d.p, o.eig_iters, splitmix64_host(salt_base + 0x9000 + l), s);
-    L.cc = cheb_coef(o, L.lam_cheb);
+    hbgs_options of = o;
+    if (o.field_cheb_degree[F.id] > 0) of.cheb_degree = o.field_cheb_degree[F.id];
+    L.cc = cheb_coef(of, L.lam_cheb);
   }
   // solve-phase data: transposes, FP32 copies, work vectors
   if (!structurally_symmetric_dev(F.lv[0].A, s))
@@ -543,15 +619,14 @@ static void compute_stats(hbgs_ctx* c) {
 // Stream slots for the sweep: a field continues the stream of the latest
 // field (in visiting order) it depends on; a field without dependencies
 // starts the next free slot.
-static void plan_sweep(hbgs_ctx* c, int tr) {
-  SweepPlan& p = c->plan[tr];
-  const int nl = (int)c->leaf_order.size();
+static void plan_sweep(hbgs_ctx* c, const std::vector<int>& leaves, int tr, SweepPlan& p) {
+  const int nl = (int)leaves.size();
   p.order.clear();
   p.stream.clear();
   p.nstreams = 0;
   std::vector<int> slot_of(c->nf, -1);
   for (int q = 0; q < nl; ++q) {
-    int f = c->leaf_order[tr ? nl - 1 - q : q];
+    int f = leaves[tr ? nl - 1 - q : q];
     int slot = -1;
     for (int k = q - 1; k >= 0 && slot < 0; --k)
       if (c->F[f].deps[tr] >> p.order[k] & 1u) slot = slot_of[p.order[k]];
@@ -578,8 +653,18 @@ static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
   F.lv.clear();
   F.lv.emplace_back();
   F.lv[0].A = extract(c->hier, c->Ap, F.lo, F.hi, F.lo, F.hi, F.lo, F.n(), s);
-  F.lower = extract(c->hier, c->Ap, F.lo, F.hi, 0, F.lo, 0, c->n, s);
-  F.upperT = extract(c->hier, c->ApT, F.lo, F.hi, F.hi, c->n, 0, c->n, s);
+  // couplings read by this field's sweep step: every earlier (later, for the
+  // adjoint) field; in the nested form only those of its own group, with
+  // columns relative to the group; none in block Jacobi
+  int glo = 0, ghi = c->n;
+  if (c->o.nested) {
+    const std::vector<int>& gf = c->group_fields[c->group_of[F.id]];
+    glo = c->f_lo[gf.front()];
+    ghi = c->f_hi[gf.back()];
+  }
+  const bool bj = c->o.block_jacobi != 0;
+  F.lower = extract(c->hier, c->Ap, F.lo, F.hi, glo, bj ? glo : F.lo, glo, ghi - glo, s);
+  F.upperT = extract(c->hier, c->ApT, F.lo, F.hi, bj ? ghi : F.hi, ghi, glo, ghi - glo, s);
   add_f32(c->hier, F.lower, s);
   add_f32(c->hier, F.upperT, s);
   setup::row_stats(F.lower, s);
@@ -598,6 +683,9 @@ static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
 static void build_values(hbgs_ctx* c, hipStream_t s) {
   c->clear_graphs();
   c->hier.clear();
+  c->group_of.assign(c->nf, 0);
+  for (size_t q = 0; q < c->group_fields.size(); ++q)
+    for (int f : c->group_fields[q]) c->group_of[f] = (int)q;
   c->F.assign(c->nf, Field{});
   for (int f = 0; f < c->nf; ++f) {
     Field& F = c->F[f];
@@ -646,13 +734,35 @@ static void build_values(hbgs_ctx* c, hipStream_t s) {
         throw Error{(hbgs_status)code[f]};
       }
   }
-  // which fields each coupling reads
+  // nested form: each child of the outermost group, its diagonal block and
+  // its couplings to the other children
+  c->G.resize(c->o.nested ? c->group_fields.size() : 0);
+  for (size_t q = 0; q < c->G.size(); ++q) {
+    Group& g = c->G[q];
+    g.fields = c->group_fields[q];
+    g.lo = c->f_lo[g.fields.front()];
+    g.hi = c->f_hi[g.fields.back()];
+    g.A = extract(c->hier, c->Ap, g.lo, g.hi, g.lo, g.hi, g.lo, g.n(), s);
+    g.AT = extract(c->hier, c->ApT, g.lo, g.hi, g.lo, g.hi, g.lo, g.n(), s);
+    const bool bj = c->o.block_jacobi != 0;
+    g.lower = extract(c->hier, c->Ap, g.lo, g.hi, 0, bj ? 0 : g.lo, 0, c->n, s);
+    g.upperT = extract(c->hier, c->ApT, g.lo, g.hi, bj ? c->n : g.hi, c->n, 0, c->n, s);
+    for (DCsr* a : {&g.A, &g.AT, &g.lower, &g.upperT}) setup::row_stats(*a, s);
+  }
+  // which fields each coupling reads (column ranges relative to the
+  // coupling's own column origin)
   {
     Tmp<int> masks(2 * c->nf);
     HBGS_HIP(hipMemsetAsync(masks.p, 0, sizeof(int) * 2 * c->nf, s));
+    std::vector<int> lo(c->nf), hi(c->nf);
     for (int f = 0; f < c->nf; ++f) {
-      solve::column_fields(c->F[f].lower, c->nf, c->f_lo.data(), c->f_hi.data(), masks.p + 2 * f, s);
-      solve::column_fields(c->F[f].upperT, c->nf, c->f_lo.data(), c->f_hi.data(), masks.p + 2 * f + 1, s);
+      const int origin = c->o.nested ? c->f_lo[c->group_fields[c->group_of[f]].front()] : 0;
+      for (int g = 0; g < c->nf; ++g) {
+        lo[g] = c->f_lo[g] - origin;
+        hi[g] = c->f_hi[g] - origin;
+      }
+      solve::column_fields(c->F[f].lower, c->nf, lo.data(), hi.data(), masks.p + 2 * f, s);
+      solve::column_fields(c->F[f].upperT, c->nf, lo.data(), hi.data(), masks.p + 2 * f + 1, s);
     }
     std::vector<int> hm(2 * c->nf);
     HBGS_HIP(hipMemcpyAsync(hm.data(), masks.p, sizeof(int) * 2 * c->nf, hipMemcpyDeviceToHost, s));
@@ -662,7 +772,10 @@ static void build_values(hbgs_ctx* c, hipStream_t s) {
       c->F[f].deps[1] = (uint32_t)hm[2 * f + 1];
     }
   }
-  for (int tr = 0; tr < 2; ++tr) plan_sweep(c, tr);
+  for (int tr = 0; tr < 2; ++tr) {
+    plan_sweep(c, c->leaf_order, tr, c->plan[tr]);
+    for (Group& g : c->G) plan_sweep(c, g.fields, tr, g.plan[tr]);
+  }
   HBGS_HIP(hipStreamSynchronize(s));
   compute_stats(c);
 }
@@ -771,10 +884,11 @@ static void vcycle(hbgs_ctx* c, Field& F, int l, int tr, const T* b, T* x, hipSt
   }
 }
 
-// z = M^-1 v (tr = 0) or M^-T v (tr = 1), permuted ordering; z has type T
+// z = M^-1 v (tr = 0) or M^-T v (tr = 1) over the fields of `plan`, in the
+// permuted ordering shifted by `base` (field f's rows are v[F.lo - base ..]);
+// z has type T
 template <class T>
-static void sweep(hbgs_ctx* c, int tr, const double* v, T* z, hipStream_t s0) {
-  const SweepPlan& plan = c->plan[tr];
+static void sweep(hbgs_ctx* c, const SweepPlan& plan, int tr, const double* v, T* z, int base, hipStream_t s0) {
   const int nl = (int)plan.order.size();
   const int TS = (int)sizeof(T);
   HBGS_HIP(hipEventRecord(c->fork, s0));
@@ -790,6 +904,7 @@ static void sweep(hbgs_ctx* c, int tr, const double* v, T* z, hipStream_t s0) {
     }
     slot_of[F.id] = slot;
     const DCsr& cpl = tr ? F.upperT : F.lower;
+    const int off = F.lo - base;
     Level& L0 = F.lv[0];
     // the finest level's first Chebyshev direction is formed with its rhs
     const bool d0 = F.lv.size() > 1 && L0.cc.degree == 2;
@@ -799,20 +914,20 @@ static void sweep(hbgs_ctx* c, int tr, const double* v, T* z, hipStream_t s0) {
     if (cpl.nnz > 0) {
       Prof p(c->prof, s, solve::K_COUPLE,
              spmv_bytes(cpl, TS, 0, TS, d0 ? 2 : 0) + 8.0 * F.n() + (double)std::min<int64_t>(cpl.nnz, c->n) * TS);
-      VcOps<T>::couple(cpl, v + F.lo, z, Buf<T>::t(F), dinv0, L0.cc.c0, d00, s);
+      VcOps<T>::couple(cpl, v + off, z, Buf<T>::t(F), dinv0, L0.cc.c0, d00, s);
       t = Buf<T>::t(F);
     } else if (sizeof(T) == sizeof(double)) {
-      t = reinterpret_cast<const T*>(v + F.lo);
+      t = reinterpret_cast<const T*>(v + off);
       if (d0) {
         Prof p(c->prof, s, solve::K_COUPLE, 3.0 * F.n() * TS);
         VcOps<T>::make_d0(F.n(), t, dinv0, L0.cc.c0, d00, s);
       }
     } else {
       Prof p(c->prof, s, solve::K_COUPLE, (8.0 + TS * (d0 ? 3 : 1)) * F.n());
-      VcOps<T>::cast_in(F.n(), v + F.lo, Buf<T>::t(F), dinv0, L0.cc.c0, d00, s);
+      VcOps<T>::cast_in(F.n(), v + off, Buf<T>::t(F), dinv0, L0.cc.c0, d00, s);
       t = Buf<T>::t(F);
     }
-    vcycle<T>(c, F, 0, tr, t, z + F.lo, s);
+    vcycle<T>(c, F, 0, tr, t, z + off, s);
     HBGS_HIP(hipEventRecord(c->fdone[F.id], s));
   }
   for (int q = 0; q < nl; ++q) HBGS_HIP(hipStreamWaitEvent(s0, c->fdone[plan.order[q]], 0));
@@ -820,124 +935,94 @@ static void sweep(hbgs_ctx* c, int tr, const double* v, T* z, hipStream_t s0) {
 
 // ------------------------------------------------------------------ GMRES
 static void ensure_workspace(hbgs_ctx* c) {
-  if (c->V) {
-    if (c->precision == 1 && !c->Zf) c->Zf = c->pool.make<float>((size_t)c->m * c->ld);
-    if (c->precision == 0 && !c->Zd) c->Zd = c->pool.make<double>((size_t)c->m * c->ld);
-    return;
-  }
-  const int n = c->n, m = c->m;
-  c->ld = ((size_t)n + 63) / 64 * 64;
-  c->V = c->pool.make<double>((size_t)(m + 1) * c->ld);
-  if (c->precision == 1)
-    c->Zf = c->pool.make<float>((size_t)m * c->ld);
-  else
-    c->Zd = c->pool.make<double>((size_t)m * c->ld);
-  c->bp = c->pool.make<double>(n);
-  c->xp = c->pool.make<double>(n);
-  c->r = c->pool.make<double>(n);
-  c->tmp = c->pool.make<double>(n);
-  int nb = solve::dot_blocks(n);
-  c->part = c->pool.make<double>((size_t)(m + 2) * nb);
-  c->h1 = c->pool.make<double>(m + 2);
-  c->h2 = c->pool.make<double>(m + 2);
-  c->hn2 = c->pool.make<double>(2);
-  c->H = c->pool.make<double>((size_t)(m + 1) * m);
-  c->cs = c->pool.make<double>(m);
-  c->sn = c->pool.make<double>(m);
-  c->g = c->pool.make<double>(m + 1);
-  c->y = c->pool.make<double>(m);
-  c->scal = c->pool.make<double>(4);
-  if (!c->host_scal) {
-    HBGS_HIP(hipHostMalloc((void**)&c->host_scal, 8 * sizeof(double), hipHostMallocDefault));
-    HBGS_HIP(hipHostGetDevicePointer((void**)&c->host_scal_dev, c->host_scal, 0));
+  c->K.ensure(c->pool, c->n, c->m, c->precision);
+  for (Group& g : c->G) {
+    if (!g.K) g.K.reset(new Krylov());
+    g.K->ensure(c->pool, g.n(), c->o.inner_restart, c->precision);
   }
 }
 
-static double norm2(hbgs_ctx* c, const double* x, hipStream_t s) {
-  int nb = solve::dot_blocks(c->n);
+static double norm2(hbgs_ctx* c, Krylov& K, const double* x, hipStream_t s) {
+  int nb = solve::dot_blocks(K.n);
   {
-    Prof p(c->prof, s, solve::K_REDUCE, 8.0 * c->n);
-    solve::norm2_partial(c->n, x, c->part, s);
-    solve::mdot_reduce(1, nb, c->part, c->hn2, s);
+    Prof p(c->prof, s, solve::K_REDUCE, 8.0 * K.n);
+    solve::norm2_partial(K.n, x, K.part, s);
+    solve::mdot_reduce(1, nb, K.part, K.hn2, s);
   }
-  HBGS_HIP(hipMemcpyAsync(c->host_scal, c->hn2, sizeof(double), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipMemcpyAsync(K.host, K.hn2, sizeof(double), hipMemcpyDeviceToHost, s));
   HBGS_HIP(hipStreamSynchronize(s));
-  return c->host_scal[0];
+  return K.host[0];
 }
 
-static void apply_perm(hbgs_ctx* c, int tr, const double* v, int j, hipStream_t s) {
-  if (c->precision == 1)
-    sweep<float>(c, tr, v, c->Zf + (size_t)j * c->ld, s);
-  else
-    sweep<double>(c, tr, v, c->Zd + (size_t)j * c->ld, s);
-}
-
-// One Arnoldi step j: z_j = M^-1 v_j, w = A z_j (into column j+1 of V),
-// two classical Gram-Schmidt passes, Givens update, v_{j+1} = w / h_{j+1,j}.
-static void iteration_body(hbgs_ctx* c, int tr, int j, hipStream_t s) {
-  const int n = c->n, m = c->m;
-  const DCsr& A = tr ? c->ApT : c->Ap;
-  const size_t ld = c->ld;
+// One Arnoldi step j of the flexible GMRES on A with workspace K:
+// z_j = M(v_j) (written by prec into column j of K's Z), w = A z_j (into
+// column j+1 of V), two classical Gram-Schmidt passes, Givens update,
+// v_{j+1} = w / h_{j+1,j}.
+template <class Prec>
+static void iteration_body(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, int j, hipStream_t s) {
+  const int n = K.n, m = K.m;
+  const size_t ld = K.ld;
   const int nb = solve::dot_blocks(n);
-  double* vj = c->V + (size_t)j * ld;
-  double* w = c->V + (size_t)(j + 1) * ld;
-  apply_perm(c, tr, vj, j, s);
+  double* vj = K.V + (size_t)j * ld;
+  double* w = K.V + (size_t)(j + 1) * ld;
+  prec(j, (const double*)vj, s);
   {
     Prof p(c->prof, s, solve::K_SPMV_OUTER, spmv_bytes(A, 8, c->precision ? 4 : 8, 8, 0));
     if (c->precision == 1)
-      solve::spmv_outer_mixed(A, c->Zf + (size_t)j * ld, w, s);
+      solve::spmv_outer_mixed(A, K.Zf + (size_t)j * ld, w, s);
     else
-      solve::spmv_outer_f64(A, c->Zd + (size_t)j * ld, w, s);
+      solve::spmv_outer_f64(A, K.Zd + (size_t)j * ld, w, s);
   }
   {
     Prof p(c->prof, s, solve::K_DOT1, 8.0 * n * (j + 2));
-    solve::cgs_dots(n, j, c->V, ld, w, c->part, s);
+    solve::cgs_dots(n, j, K.V, ld, w, K.part, s);
   }
   {
     Prof p(c->prof, s, solve::K_REDUCE, 8.0 * nb * (j + 2));
-    solve::mdot_reduce(j + 2, nb, c->part, c->h1, s);
+    solve::mdot_reduce(j + 2, nb, K.part, K.h1, s);
   }
   {
     Prof p(c->prof, s, solve::K_UPD_DOT2, 8.0 * n * (j + 3));
-    solve::cgs_update_dots(n, j, c->V, ld, w, c->h1, c->part, s);
+    solve::cgs_update_dots(n, j, K.V, ld, w, K.h1, K.part, s);
   }
   {
     solve::GivensArgs ga;
     ga.j = j;
     ga.m = m;
-    ga.h1 = c->h1;
-    ga.H = c->H;
-    ga.cs = c->cs;
-    ga.sn = c->sn;
-    ga.g = c->g;
-    ga.scal = c->scal;
-    ga.host_scal = c->host_scal_dev;
+    ga.h1 = K.h1;
+    ga.H = K.H;
+    ga.cs = K.cs;
+    ga.sn = K.sn;
+    ga.g = K.g;
+    ga.scal = K.scal;
+    ga.host_scal = K.host_dev;
     Prof p(c->prof, s, solve::K_GIVENS, 8.0 * nb * (j + 2));
-    solve::reduce_givens(n, j, c->part, c->h2, ga, s);
+    solve::reduce_givens(n, j, K.part, K.h2, ga, s);
   }
   {
     Prof p(c->prof, s, solve::K_UPD_SCALE, 8.0 * n * (j + 3));
-    solve::upd_scale(n, j, c->V, ld, w, c->h2, c->scal, s);
+    solve::upd_scale(n, j, K.V, ld, w, K.h2, K.scal, s);
   }
 }
 
 // Runs step j eagerly, or replays its captured graph (capturing it on first
 // use; graphs are dropped when the hierarchy changes).  Kernel timing needs
 // events around individual launches, which graph replays do not provide, so
-// steps run eagerly while the profiler is on.
-static void run_iteration(hbgs_ctx* c, int tr, int j, hipStream_t s) {
-  if (!c->o.use_graphs || c->prof.on) {
-    iteration_body(c, tr, j, s);
+// steps run eagerly while the profiler is on.  graph_key < 0: always eager.
+template <class Prec>
+static void run_iteration(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, int j, int graph_key, hipStream_t s) {
+  if (graph_key < 0 || !c->o.use_graphs || c->prof.on) {
+    iteration_body(c, K, A, prec, j, s);
     return;
   }
-  const int key = (c->precision * 2 + tr) * 128 + j;
+  const int key = graph_key * 128 + j;
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     IterGraph ig;
     hipGraph_t g = nullptr;
     HBGS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     try {
-      iteration_body(c, tr, j, s);
+      iteration_body(c, K, A, prec, j, s);
     } catch (...) {
       (void)hipStreamEndCapture(s, &g);
       if (g) (void)hipGraphDestroy(g);
@@ -952,66 +1037,130 @@ static void run_iteration(hbgs_ctx* c, int tr, int j, hipStream_t s) {
   HBGS_HIP(hipGraphLaunch(it->second.exec, s));
 }
 
-static hbgs_status gmres(hbgs_ctx* c, int tr, int use_x0, int32_t* iters, double* hist, int cap, int32_t* hlen,
-                         hipStream_t s) {
-  const int n = c->n, m = c->m;
-  const DCsr& A = tr ? c->ApT : c->Ap;
-  const size_t ld = c->ld;
-  const int nb = solve::dot_blocks(n);
+// Flexible GMRES(K.m) for A x = b with b in K.bp and x in K.xp (zero start
+// unless use_x0); the relative residual target is rtol, at most max_iters
+// Arnoldi steps.  hist (optional) receives the residual estimates, the true
+// residual replacing the estimate at the end of every cycle.
+template <class Prec>
+static hbgs_status fgmres(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, double rtol, int max_iters, int use_x0,
+                          int32_t* iters, double* hist, int cap, int32_t* hlen, int graph_key, hipStream_t s) {
+  const int n = K.n, m = K.m;
+  const size_t ld = K.ld;
   *iters = 0;
   *hlen = 0;
   auto push = [&](double v) {
     if (hist && *hlen < cap) hist[*hlen] = v;
     (*hlen)++;
   };
-  double bnorm = std::sqrt(norm2(c, c->bp, s));
+  double bnorm = std::sqrt(norm2(c, K, K.bp, s));
   if (bnorm == 0.0) {
-    HBGS_HIP(hipMemsetAsync(c->xp, 0, sizeof(double) * n, s));
+    HBGS_HIP(hipMemsetAsync(K.xp, 0, sizeof(double) * n, s));
     push(0.0);
     return HBGS_OK;
   }
-  if (!use_x0) HBGS_HIP(hipMemsetAsync(c->xp, 0, sizeof(double) * n, s));
+  if (!use_x0) HBGS_HIP(hipMemsetAsync(K.xp, 0, sizeof(double) * n, s));
   auto true_resid = [&]() {
     {
       Prof p(c->prof, s, solve::K_SPMV_RESID, spmv_bytes(A, 8, 8, 8, 1));
-      solve::spmv_resid_f64(A, c->xp, c->bp, c->r, s);
+      solve::spmv_resid_f64(A, K.xp, K.bp, K.r, s);
     }
-    return std::sqrt(norm2(c, c->r, s));
+    return std::sqrt(norm2(c, K, K.r, s));
   };
   double beta = true_resid();
   push(beta / bnorm);
   for (;;) {
-    if (beta / bnorm <= c->o.rtol) return HBGS_OK;
-    if (*iters >= c->o.max_iters) return HBGS_NOT_CONVERGED;
+    if (beta / bnorm <= rtol) return HBGS_OK;
+    if (*iters >= max_iters) return HBGS_NOT_CONVERGED;
     {
       Prof p(c->prof, s, solve::K_SCALE, 16.0 * n);
-      solve::scale_copy(n, c->r, c->hn2, c->V, s);  // hn2 holds ||r||^2 from true_resid
+      solve::scale_copy(n, K.r, K.hn2, K.V, s);  // hn2 holds ||r||^2 from true_resid
     }
     std::vector<double> g0(m + 1, 0.0);
     g0[0] = beta;
-    HBGS_HIP(hipMemcpyAsync(c->g, g0.data(), sizeof(double) * (m + 1), hipMemcpyHostToDevice, s));
+    HBGS_HIP(hipMemcpyAsync(K.g, g0.data(), sizeof(double) * (m + 1), hipMemcpyHostToDevice, s));
     int jend = 0;
     for (int j = 0; j < m; ++j) {
-      run_iteration(c, tr, j, s);  // its Givens step writes the estimate to host_scal
+      run_iteration(c, K, A, prec, j, graph_key, s);  // its Givens step writes the estimate to K.host
       HBGS_HIP(hipStreamSynchronize(s));
       (*iters)++;
-      double est = c->host_scal[0] / bnorm, hn = c->host_scal[1], w0 = c->host_scal[2];
+      double est = K.host[0] / bnorm, hn = K.host[1], w0 = K.host[2];
       push(est);
       jend = j + 1;
       if (!(est == est)) HBGS_FAIL(HBGS_EHIP, "non-finite residual estimate");
-      if (est <= c->o.rtol || hn <= 1e-14 * w0 || *iters >= c->o.max_iters) break;
+      if (est <= rtol || hn <= 1e-14 * w0 || *iters >= max_iters) break;
     }
-    solve::backsolve(jend, m, c->H, c->g, c->y, s);
+    solve::backsolve(jend, m, K.H, K.g, K.y, s);
     {
       Prof p(c->prof, s, solve::K_XUPDATE, (double)n * (16 + jend * (c->precision ? 4 : 8)));
       if (c->precision == 1)
-        solve::xupdate<float>(n, jend, c->Zf, ld, c->y, c->xp, s);
+        solve::xupdate<float>(n, jend, K.Zf, ld, K.y, K.xp, s);
       else
-        solve::xupdate<double>(n, jend, c->Zd, ld, c->y, c->xp, s);
+        solve::xupdate<double>(n, jend, K.Zd, ld, K.y, K.xp, s);
     }
     beta = true_resid();
     if (hist && *hlen - 1 < cap) hist[*hlen - 1] = beta / bnorm;
   }
+}
+
+static void nested_apply(hbgs_ctx* c, int tr, const double* v, int j, hipStream_t s);
+
+// z_j = M^-1 v (tr = 0) or M^-T v, permuted ordering, into column j of the
+// outer Z
+static void apply_perm(hbgs_ctx* c, int tr, const double* v, int j, hipStream_t s) {
+  Krylov& K = c->K;
+  if (c->o.nested)
+    nested_apply(c, tr, v, j, s);
+  else if (c->precision == 1)
+    sweep<float>(c, c->plan[tr], tr, v, K.Zf + (size_t)j * K.ld, 0, s);
+  else
+    sweep<double>(c, c->plan[tr], tr, v, K.Zd + (size_t)j * K.ld, 0, s);
+}
+
+// Nested form (Sec. 3.2): the children of the outermost group are visited
+// in order (reversed for the adjoint); child g receives v_g minus the
+// couplings to the children already solved and is solved by an inner
+// flexible GMRES from a zero start, preconditioned by its own sweep, to the
+// inner tolerance.  Its result becomes block g of z_j (rounded to FP32 in the
+// mixed mode, where Z is FP32).
+static void nested_apply(hbgs_ctx* c, int tr, const double* v, int j, hipStream_t s) {
+  Krylov& K = c->K;
+  const int ng = (int)c->G.size();
+  for (int q = 0; q < ng; ++q) {
+    Group& g = c->G[tr ? ng - 1 - q : q];
+    Krylov& KG = *g.K;
+    const DCsr& cpl = tr ? g.upperT : g.lower;
+    if (cpl.nnz > 0) {
+      Prof p(c->prof, s, solve::K_COUPLE, spmv_bytes(cpl, 8, c->precision ? 4 : 8, 8, 1));
+      if (c->precision == 1)
+        solve::couple_f64<float>(cpl, v + g.lo, K.Zf + (size_t)j * K.ld, KG.bp, s);
+      else
+        solve::couple_f64<double>(cpl, v + g.lo, K.Zd + (size_t)j * K.ld, KG.bp, s);
+    } else {
+      HBGS_HIP(hipMemcpyAsync(KG.bp, v + g.lo, sizeof(double) * g.n(), hipMemcpyDeviceToDevice, s));
+    }
+    auto prec = [&](int jj, const double* vv, hipStream_t st) {
+      if (c->precision == 1)
+        sweep<float>(c, g.plan[tr], tr, vv, KG.Zf + (size_t)jj * KG.ld, g.lo, st);
+      else
+        sweep<double>(c, g.plan[tr], tr, vv, KG.Zd + (size_t)jj * KG.ld, g.lo, st);
+    };
+    int32_t it = 0, hl = 0;
+    (void)fgmres(c, KG, tr ? g.AT : g.A, prec, c->o.inner_rtol, c->o.inner_max_iters, 0, &it, nullptr, 0, &hl, -1,
+                 s);
+    if (c->precision == 1)
+      VcOps<float>::cast_in(g.n(), KG.xp, K.Zf + (size_t)j * K.ld + g.lo, nullptr, 0.0, nullptr, s);
+    else
+      HBGS_HIP(hipMemcpyAsync(K.Zd + (size_t)j * K.ld + g.lo, KG.xp, sizeof(double) * g.n(),
+                              hipMemcpyDeviceToDevice, s));
+  }
+}
+
+static hbgs_status gmres(hbgs_ctx* c, int tr, int use_x0, int32_t* iters, double* hist, int cap, int32_t* hlen,
+                         hipStream_t s) {
+  auto prec = [&](int j, const double* v, hipStream_t st) { apply_perm(c, tr, v, j, st); };
+  const int graph_key = c->o.nested ? -1 : c->precision * 2 + tr;
+  return fgmres(c, c->K, tr ? c->ApT : c->Ap, prec, c->o.rtol, c->o.max_iters, use_x0, iters, hist, cap, hlen,
+                graph_key, s);
 }
 
 }  // namespace hbgs
@@ -1049,6 +1198,11 @@ void hbgs_default_options(hbgs_options* o) {
   o->theta[0] = 0.04;
   o->use_graphs = 0;
   o->setup_concurrent = 1;
+  o->block_jacobi = 0;
+  o->nested = 0;
+  o->inner_restart = 30;
+  o->inner_max_iters = 300;
+  o->inner_rtol = 1e-6;
 }
 
 const char* hbgs_last_error(void) { return g_last_error.c_str(); }
@@ -1208,15 +1362,16 @@ hbgs_status hbgs_apply(hbgs_ctx* c, const double* r, double* z, int32_t transpos
   HBGS_API_BEGIN
   hipStream_t s = (hipStream_t)stream;
   ensure_workspace(c);
-  solve::permute_in(c->n, c->perm, r, c->bp, s);
-  apply_perm(c, transpose ? 1 : 0, c->bp, 0, s);
-  const double* zp = c->Zd;
+  Krylov& K = c->K;
+  solve::permute_in(c->n, c->perm, r, K.bp, s);
+  apply_perm(c, transpose ? 1 : 0, K.bp, 0, s);
+  const double* zp = K.Zd;
   if (c->precision == 1) {  // widen the FP32 result: tmp = 0 + 1 * Z_0
-    c->host_scal[4] = 1.0;
-    HBGS_HIP(hipMemcpyAsync(c->y, c->host_scal + 4, sizeof(double), hipMemcpyHostToDevice, s));
-    HBGS_HIP(hipMemsetAsync(c->tmp, 0, sizeof(double) * c->n, s));
-    solve::xupdate<float>(c->n, 1, c->Zf, c->ld, c->y, c->tmp, s);
-    zp = c->tmp;
+    K.host[4] = 1.0;
+    HBGS_HIP(hipMemcpyAsync(K.y, K.host + 4, sizeof(double), hipMemcpyHostToDevice, s));
+    HBGS_HIP(hipMemsetAsync(K.tmp, 0, sizeof(double) * c->n, s));
+    solve::xupdate<float>(c->n, 1, K.Zf, K.ld, K.y, K.tmp, s);
+    zp = K.tmp;
   }
   solve::permute_out(c->n, c->perm, zp, z, s);
   HBGS_HIP(hipStreamSynchronize(s));
@@ -1238,10 +1393,10 @@ hbgs_status hbgs_solve(hbgs_ctx* c, const double* b, double* x, int32_t use_x0, 
   hipStream_t s = c->sm;
   HBGS_HIP(hipEventRecord(c->join_in, us));
   HBGS_HIP(hipStreamWaitEvent(s, c->join_in, 0));
-  solve::permute_in(c->n, c->perm, b, c->bp, s);
-  if (use_x0) solve::permute_in(c->n, c->perm, x, c->xp, s);
+  solve::permute_in(c->n, c->perm, b, c->K.bp, s);
+  if (use_x0) solve::permute_in(c->n, c->perm, x, c->K.xp, s);
   hbgs_status st = gmres(c, transpose ? 1 : 0, use_x0, &it, hist, hist_cap, &hl, s);
-  solve::permute_out(c->n, c->perm, c->xp, x, s);
+  solve::permute_out(c->n, c->perm, c->K.xp, x, s);
   HBGS_HIP(hipEventRecord(c->join_out, s));
   HBGS_HIP(hipStreamWaitEvent(us, c->join_out, 0));
   HBGS_HIP(hipStreamSynchronize(us));

@@ -252,6 +252,9 @@ struct ChebCoef {
 // outer SpMV, y = A x with x double or float; resid: y = b - A x
 void spmv_outer_f64(const DCsr& a, const double* x, double* y, hipStream_t s);
 void spmv_outer_mixed(const DCsr& a, const float* x, double* y, hipStream_t s);
+// t = v - a z (FP64 values and result; z FP32 or FP64)
+template <class TZ>
+void couple_f64(const DCsr& a, const double* v, const TZ* z, double* t, hipStream_t s);
 void spmv_resid_f64(const DCsr& a, const double* x, const double* b, double* r, hipStream_t s);
 
 template <class T>

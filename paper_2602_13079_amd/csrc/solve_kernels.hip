@@ -274,6 +274,17 @@ struct EpiCouple {
   }
 };
 
+// group right-hand side of the nested form: t = v - sum a z (FP64 out)
+struct EpiSubFrom {
+  const double* __restrict__ v;
+  double* __restrict__ t;
+  struct Pre {
+    double v;
+  };
+  __device__ Pre load(int i) const { return {v[i]}; }
+  __device__ void store(int i, double acc, Pre p) const { t[i] = p.v - acc; }
+};
+
 // ---------------------------------------------------------- outer SpMV
 void spmv_outer_f64(const DCsr& a, const double* x, double* y, hipStream_t s) {
   launch_csr<double, double>(a, a.v, LoadArr<double>{x}, EpiStore<double, double>{y}, s);
@@ -281,6 +292,12 @@ void spmv_outer_f64(const DCsr& a, const double* x, double* y, hipStream_t s) {
 void spmv_outer_mixed(const DCsr& a, const float* x, double* y, hipStream_t s) {
   launch_csr<double, double>(a, a.v, LoadArr<float>{x}, EpiStore<double, double>{y}, s);
 }
+template <class TZ>
+void couple_f64(const DCsr& a, const double* v, const TZ* z, double* t, hipStream_t s) {
+  launch_csr<double, double>(a, a.v, LoadArr<TZ>{z}, EpiSubFrom{v, t}, s);
+}
+template void couple_f64<float>(const DCsr&, const double*, const float*, double*, hipStream_t);
+template void couple_f64<double>(const DCsr&, const double*, const double*, double*, hipStream_t);
 void spmv_resid_f64(const DCsr& a, const double* x, const double* b, double* r, hipStream_t s) {
   launch_csr<double, double>(a, a.v, LoadArr<double>{x}, EpiResid<double>{b, r}, s);
 }
