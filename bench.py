@@ -37,6 +37,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2, help="layered-battery configuration (default: 4.2M DOF)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the preconditioner variants and sweeps")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -211,9 +212,60 @@ def main():
             "traffic_source": traffic_src,
         },
     }
+    if not args.no_variants:
+        out["variants"] = variants(H, torch, s, rp, ci, val, fl, b)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(out), flush=True)
+
+
+def variants(H, torch, s, rp, ci, val, fl, b, reps=3):
+    """Other configurations of the method on the same system (each a fresh
+    setup, then the mean of `reps` mixed-precision solves to 1e-8):
+      * nested: the paper's nested form -- outer flexible GMRES(5); the
+        voltage block (phi_s, phi_e) and the non-voltage block (p, c...) each
+        solved by an inner GMRES(30) to 1e-6 preconditioned by its own sweep,
+        degree-4 Chebyshev on the voltage leaves;
+      * block_jacobi: couplings dropped, all field V-cycles concurrent;
+      * theta_phi_s: strength threshold of the phi_s hierarchy;
+      * cheb_degree_4: degree-4 Chebyshev on every level of every field."""
+    nsp = s.nf - 3
+    tree2 = [-1, -1, 0, 1, -2, -1] + list(range(2, 3 + nsp)) + [-2, -2]
+    cases = {
+        "nested": dict(tree=tree2, nested=1, restart=5, field_cheb_degree=[4, 4]),
+        "block_jacobi": dict(block_jacobi=1),
+        "cheb_degree_4": dict(cheb_degree=4),
+    }
+    for th in (0.0, 0.01, 0.04, 0.16, 0.64):
+        cases[f"theta_phi_s={th}"] = dict(theta=[th])
+    out = {}
+    for name, opt in cases.items():
+        opt = dict(opt)
+        tree = opt.pop("tree", s.tree)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            g = H.Solver(rp, ci, val, fl, s.nf, tree, precision=1, **opt)
+        except H.HBGSError as e:  # e.g. coarsening stalls above the dense coarse-solve limit
+            out[name] = dict(error=str(e))
+            log(f"variant {name}: {e}")
+            continue
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        times, its = [], []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            x, st, it, hist = g.solve(b)
+            times.append(time.perf_counter() - t0)
+            its.append(it)
+        xa, sta, ita, _ = g.solve(b, transpose=True)
+        out[name] = dict(setup_s=round(setup_s, 4), solve_s=round(min(times), 6), iters=its[-1], status=st,
+                         true_res=float(hist[-1]), levels=g.stats()["levels"], adjoint_iters=ita,
+                         adjoint_status=sta)
+        log(f"variant {name}: setup {setup_s:.3f}s, solve {min(times) * 1e3:.2f} ms, {its[-1]} iterations, "
+            f"levels {out[name]['levels']}, adjoint {ita} iterations")
+        del g
+    return out
 
 
 def copy_probe(torch, dev, mib=512, reps=5):
