@@ -275,6 +275,7 @@ struct hbgs_ctx {
   hbgs::Pool hier;  // value-dependent hierarchy (rebuilt by set_values)
   int *rp0 = nullptr, *ci0 = nullptr;  // caller's pattern
   int *perm = nullptr, *iperm = nullptr, *src = nullptr;
+  int* srcT = nullptr;  // caller's value index of each A_p^T entry
   hbgs::DCsr Ap, ApT;
   std::vector<int> leaf_order, f_lo, f_hi;
   std::vector<hbgs::Field> F;
@@ -1163,6 +1164,20 @@ static hbgs_status gmres(hbgs_ctx* c, int tr, int use_x0, int32_t* iters, double
                 graph_key, s);
 }
 
+__global__ void k_gather_vals(int64_t nnz, const double* v, const int* src, double* vp) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) vp[k] = v[src[k]];
+}
+__global__ void k_iota_f64(int64_t nnz, double* p) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) p[k] = (double)k;
+}
+// srcT[k] = src[position of A_p^T entry k in A_p]
+__global__ void k_compose(int64_t nnz, const double* pos, const int* src, int* srcT) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) srcT[k] = src[(int64_t)pos[k]];
+}
+
 }  // namespace hbgs
 
 // ===================================================================== C ABI
@@ -1289,7 +1304,21 @@ hbgs_status hbgs_setup(hbgs_ctx** out, int32_t n, int64_t nnz, const int32_t* ro
     c->src = c->pool.make<int>(nnz);
     setup::permute_fill(n, c->rp0, c->ci0, val, c->perm, c->iperm, c->Ap.rp, c->Ap.ci, c->Ap.v, c->src, s);
   }
-  c->ApT = transpose_new(c->pool, c->Ap, s);
+  // A_p^T, and for each of its entries the caller's value index (so that a
+  // value update is two gathers)
+  {
+    Tmp<double> pos(nnz);
+    k_iota_f64<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, pos.p);
+    HBGS_HIP(hipGetLastError());
+    DCsr idx = c->Ap;
+    idx.v = pos.p;
+    c->ApT = transpose_new(c->pool, idx, s);
+    c->srcT = c->pool.make<int>(nnz);
+    k_compose<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, c->ApT.v, c->src, c->srcT);
+    HBGS_HIP(hipGetLastError());
+    k_gather_vals<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, val, c->srcT, c->ApT.v);
+    HBGS_HIP(hipGetLastError());
+  }
   setup::row_stats(c->Ap, s);
   setup::row_stats(c->ApT, s);
   build_values(c, s);
@@ -1308,10 +1337,6 @@ hbgs_status hbgs_setup(hbgs_ctx** out, int32_t n, int64_t nnz, const int32_t* ro
   }
 }
 
-__global__ void k_gather_vals(int64_t nnz, const double* v, const int* src, double* vp) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < nnz) vp[k] = v[src[k]];
-}
 
 hbgs_status hbgs_set_values(hbgs_ctx* c, const double* val, int32_t rebuild_hierarchy, void* stream) {
   if (!c || !val) {
@@ -1322,9 +1347,8 @@ hbgs_status hbgs_set_values(hbgs_ctx* c, const double* val, int32_t rebuild_hier
   hipStream_t s = (hipStream_t)stream;
   auto t0 = std::chrono::steady_clock::now();
   k_gather_vals<<<grid_for(c->nnz, 256), 256, 0, s>>>(c->nnz, val, c->src, c->Ap.v);
+  k_gather_vals<<<grid_for(c->nnz, 256), 256, 0, s>>>(c->nnz, val, c->srcT, c->ApT.v);
   HBGS_HIP(hipGetLastError());
-  // A^T values: transpose again (same pattern)
-  setup::transpose(c->Ap, c->ApT, s);
   if (rebuild_hierarchy) {
     build_values(c, s);
     c->stats.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -861,8 +861,12 @@ __device__ __forceinline__ int wave_table(int64_t need) {  // power of two >= 2 
   while (t < 2 * need) t <<= 1;
   return t;
 }
-__device__ __forceinline__ bool sym_fits(int64_t ub) { return 2 * ub <= SPG_SYM_SLOTS; }
+constexpr int SPG_BLK_SLOTS = 4096;  // numeric, one block per row: keys and values (48 KB)
+// distinct columns of a product row are at most min(ub, columns of B)
+__device__ __forceinline__ int64_t sym_need(int64_t ub, int m) { return ub < m ? ub : (int64_t)m; }
+__device__ __forceinline__ bool sym_fits(int64_t need) { return 2 * need <= SPG_SYM_SLOTS; }
 __device__ __forceinline__ bool num_fits(int64_t cnt) { return 2 * cnt <= SPG_NUM_SLOTS; }
+__device__ __forceinline__ bool num_fits_block(int64_t cnt) { return 2 * cnt <= SPG_BLK_SLOTS; }
 
 // slot holding key c (claimed if absent); -1 if the table is full, which
 // the table sizes rule out (the caller reports it instead of looping)
@@ -880,14 +884,16 @@ __device__ __forceinline__ int lds_claim(int* keys, uint32_t mask, int c, bool* 
   return -1;
 }
 
-__global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_sym_wave(int n, const int* arp, const int* aci,
+__global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_sym_wave(int n, int bm, const int* arp, const int* aci,
                                                                    const int* brp, const int* bci,
                                                                    const int64_t* ub, int* cnt, int* overflow) {
   __shared__ int tab[SPG_WAVES][SPG_SYM_SLOTS];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = blockIdx.x * SPG_WAVES + wave;
-  if (i >= n || !sym_fits(ub[i])) return;
-  const int T = wave_table(ub[i]);
+  if (i >= n) return;
+  const int64_t need = sym_need(ub[i], bm);
+  if (!sym_fits(need)) return;
+  const int T = wave_table(need);
   int* keys = tab[wave];
   for (int q = lane; q < T; q += 64) keys[q] = -1;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1034,11 +1040,70 @@ __global__ void k_spgemm_numeric(int r0, int r1, const int* arp, const int* aci,
   }
 }
 // global table sizes of the rows the wave kernels leave over
-__global__ void k_spgemm_tsize_sym(int n, const int64_t* ub, int64_t* ts) {
-  GRID_STRIDE(i, n) ts[i] = sym_fits(ub[i]) ? 0 : table_size(ub[i]);
+__global__ void k_spgemm_tsize_sym(int n, int bm, const int64_t* ub, int64_t* ts) {
+  GRID_STRIDE(i, n) {
+    const int64_t need = sym_need(ub[i], bm);
+    ts[i] = sym_fits(need) ? 0 : table_size(need);
+  }
 }
-__global__ void k_spgemm_tsize_num(int n, const int64_t* ub, const int* crp, int64_t* ts) {
-  GRID_STRIDE(i, n) ts[i] = num_fits(crp[i + 1] - crp[i]) ? 0 : table_size(ub[i]);
+// rows for the one-block-per-row kernel are listed; rows beyond it get a
+// global table
+__global__ void k_spgemm_tsize_num(int n, const int* crp, int64_t* ts, int* nmid, int* mid) {
+  GRID_STRIDE(i, n) {
+    const int64_t cnt = crp[i + 1] - crp[i];
+    ts[i] = 0;
+    if (num_fits(cnt)) continue;
+    if (num_fits_block(cnt))
+      mid[atomicAdd(nmid, 1)] = (int)i;
+    else
+      ts[i] = table_size(cnt);
+  }
+}
+
+// numeric product of one listed row per block (rows of up to
+// SPG_BLK_SLOTS / 2 entries): the threads take the entries of one B row at a
+// time and the block synchronises between rows of B, so every slot sums its
+// products in ascending k
+__global__ __launch_bounds__(BLK) void k_spgemm_num_block(const int* rows, const int* arp, const int* aci,
+                                                          const double* av, const int* brp, const int* bci,
+                                                          const double* bv, const int* crp, int* cci, double* cv,
+                                                          int* overflow) {
+  __shared__ int keys[SPG_BLK_SLOTS];
+  __shared__ double vals[SPG_BLK_SLOTS];
+  const int i = rows[blockIdx.x];
+  const int o = crp[i], cnt = crp[i + 1] - o;
+  int T = 64;
+  while (T < 2 * cnt) T <<= 1;
+  for (int q = threadIdx.x; q < T; q += BLK) {
+    keys[q] = -1;
+    vals[q] = 0.0;
+  }
+  __syncthreads();
+  const uint32_t mask = (uint32_t)(T - 1);
+  for (int k = arp[i]; k < arp[i + 1]; ++k) {
+    const int kk = aci[k];
+    const double a = av[k];
+    for (int q = brp[kk] + threadIdx.x; q < brp[kk + 1]; q += BLK) {
+      bool fresh;
+      const int h = lds_claim(keys, mask, bci[q], &fresh);
+      if (h >= 0)
+        vals[h] += a * bv[q];
+      else
+        atomicOr(overflow, 1);
+    }
+    __syncthreads();
+  }
+  for (int q = threadIdx.x; q < T; q += BLK) {
+    const int c = keys[q];
+    if (c < 0) continue;
+    int rank = 0;
+    for (int p = 0; p < T; ++p) {
+      const int d = keys[p];
+      rank += (d >= 0) & (d < c);
+    }
+    cci[o + rank] = c;
+    cv[o + rank] = vals[q];
+  }
 }
 
 // row batches whose global tables fit the scratch budget; returns the largest batch
@@ -1068,8 +1133,8 @@ void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
   HBGS_HIP(hipGetLastError());
   const unsigned wgrid = (unsigned)(((int64_t)n + SPG_WAVES - 1) / SPG_WAVES);
   // symbolic: distinct columns per row
-  k_spgemm_sym_wave<<<wgrid, 64 * SPG_WAVES, 0, s>>>(n, a.rp, a.ci, b.rp, b.ci, ub.p, cnt.p, overflow.p);
-  k_spgemm_tsize_sym<<<grid_for(n, BLK), BLK, 0, s>>>(n, ub.p, ts.p);
+  k_spgemm_sym_wave<<<wgrid, 64 * SPG_WAVES, 0, s>>>(n, b.m, a.rp, a.ci, b.rp, b.ci, ub.p, cnt.p, overflow.p);
+  k_spgemm_tsize_sym<<<grid_for(n, BLK), BLK, 0, s>>>(n, b.m, ub.p, ts.p);
   HBGS_HIP(hipGetLastError());
   std::vector<int64_t> h_off(n + 1);
   std::vector<int> cuts;
@@ -1092,8 +1157,17 @@ void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
   // numeric
   k_spgemm_num_wave<<<wgrid, 64 * SPG_WAVES, 0, s>>>(n, a.rp, a.ci, a.v, b.rp, b.ci, b.v, c.rp, c.ci, c.v,
                                                      overflow.p);
-  k_spgemm_tsize_num<<<grid_for(n, BLK), BLK, 0, s>>>(n, ub.p, c.rp, ts.p);
+  Tmp<int> nmid(1), mid(n);
+  HBGS_HIP(hipMemsetAsync(nmid.p, 0, sizeof(int), s));
+  k_spgemm_tsize_num<<<grid_for(n, BLK), BLK, 0, s>>>(n, c.rp, ts.p, nmid.p, mid.p);
   HBGS_HIP(hipGetLastError());
+  int h_nmid = 0;
+  HBGS_HIP(hipMemcpyAsync(&h_nmid, nmid.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  if (h_nmid > 0) {
+    k_spgemm_num_block<<<h_nmid, BLK, 0, s>>>(mid.p, a.rp, a.ci, a.v, b.rp, b.ci, b.v, c.rp, c.ci, c.v, overflow.p);
+    HBGS_HIP(hipGetLastError());
+  }
   if (scan_i64(ts.p, toff.p, n, s) > 0) {
     HBGS_HIP(hipMemcpyAsync(h_off.data(), toff.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
     HBGS_HIP(hipStreamSynchronize(s));
