@@ -186,6 +186,9 @@ def main():
         "true_res_fp64": float(rs[-1]["res_fp64"]),
         "err_mixed_vs_fp64": float(rs[-1]["err_mixed_vs_fp64"]),
         "setup_s": round(mean("setup_s"), 4),
+        "setup_stage_s": dict(zip(("extract", "aggregation", "prolongator", "transpose_P", "galerkin", "coarse_lu",
+                                   "smoother_data", "solve_data"), (round(x, 4) for x in st["setup_stage_seconds"]))),
+        "setup_field_s": [round(x, 4) for x in st["setup_field_seconds"]],
         "adjoint_mixed_s": round(mean("adjoint_s"), 6),
         "adjoint_fp64_s": round(mean("adjoint64_s"), 6),
         "iters_adjoint": int(rs[-1]["it_adjoint"]),

@@ -103,6 +103,15 @@ typedef struct {
   double setup_seconds;     /* wall time of the last setup */
   double setup_field_seconds[HBGS_MAX_FIELDS]; /* wall time of each field's block
                                extraction and hierarchy build in the last setup */
+  double setup_stage_seconds[8]; /* last setup, summed over fields (host wall time of
+                               each stage, which includes its waits): [0] block and
+                               coupling extraction, [1] strength and MIS-2
+                               aggregation, [2] filtering, eigenvalue estimate and
+                               prolongator smoothing, [3] R = P^T, [4] Galerkin
+                               products, [5] coarsest factorisation and inverse,
+                               [6] smoother data (diagonal inverses, Chebyshev
+                               estimates), [7] transposes, FP32 copies, row
+                               statistics and work vectors */
 } hbgs_stats_t;
 
 /* Fill *opt with the defaults listed above. */
@@ -202,7 +211,8 @@ int32_t hbgs_kernel_times(hbgs_ctx *ctx, char (*names)[48], double *total_ms, in
  * threads (one per field) concurrently.  NULL for both restores hipMalloc /
  * hipFree.  Each allocation is freed with the hook that made it, so the hook
  * may change while contexts are alive; setup temporaries stay with HIP's
- * stream-ordered allocator.  Returns HBGS_EINVAL if exactly one of the two is
+ * stream-ordered allocator (whose default pool hbgs_setup lets keep freed
+ * memory, so that rebuilds recycle it).  Returns HBGS_EINVAL if exactly one of the two is
  * NULL.  Process-wide; not to be called concurrently with hbgs_setup. */
 hbgs_status hbgs_set_allocator(void *(*alloc)(size_t bytes, void *user), void (*free)(void *ptr, void *user),
                                void *user);

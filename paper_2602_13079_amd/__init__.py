@@ -50,6 +50,7 @@ class Stats(ctypes.Structure):
         ("nnz_p", (ctypes.c_int64 * MAX_LEVELS) * MAX_FIELDS),
         ("vcycle_bytes", ctypes.c_double * 2), ("spmv_bytes", ctypes.c_double * 2),
         ("setup_seconds", ctypes.c_double), ("setup_field_seconds", ctypes.c_double * MAX_FIELDS),
+        ("setup_stage_seconds", ctypes.c_double * 8),
     ]
 
 
@@ -253,7 +254,8 @@ class Solver:
             nnz_p=[[st.nnz_p[f][l] for l in range(st.levels[f])] for f in range(nf)],
             vcycle_bytes=list(st.vcycle_bytes), spmv_bytes=list(st.spmv_bytes),
             setup_seconds=st.setup_seconds,
-            setup_field_seconds=[st.setup_field_seconds[f] for f in range(nf)])
+            setup_field_seconds=[st.setup_field_seconds[f] for f in range(nf)],
+            setup_stage_seconds=list(st.setup_stage_seconds))
 
     def get_level(self, field, level, which="A"):
         """Host copy (rowptr, col, val, ncols) of A_l / P_l / R_l / A_l^T."""

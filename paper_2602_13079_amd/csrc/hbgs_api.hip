@@ -40,17 +40,9 @@ static void free_block(void* p, const Allocator& a) {
     (void)hipFree(p);
 }
 
-Pool::~Pool() { clear(); }
-void Pool::clear() {
-  std::lock_guard<std::mutex> lk(mu_);
-  for (auto& b : blocks_) free_block(b.p, b.a);
-  blocks_.clear();
-  total_ = 0;
-}
-void* Pool::get(size_t bytes) {
+void* Pool::raw(size_t bytes, Allocator& a) {
   void* p = nullptr;
-  if (bytes == 0) bytes = 8;
-  const Allocator a = current_allocator();
+  a = current_allocator();
   if (a.alloc) {
     p = a.alloc(bytes, a.user);
     if (!p) {
@@ -65,12 +57,50 @@ void* Pool::get(size_t bytes) {
       throw Error{HBGS_ENOMEM};
     }
   }
+  return p;
+}
+
+Pool::~Pool() {
+  clear();
+  for (auto& c : chunks_) free_block(c.base, c.a);
+  chunks_.clear();
+}
+void Pool::clear() {
+  std::lock_guard<std::mutex> lk(mu_);
+  for (auto& b : blocks_) free_block(b.p, b.a);
+  blocks_.clear();
+  for (auto& c : chunks_) c.used = 0;
+  total_ = 0;
+}
+void* Pool::get(size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (arena_) {
+    const size_t need = (bytes + 255) / 256 * 256;
+    std::lock_guard<std::mutex> lk(mu_);
+    for (auto& c : chunks_)
+      if (c.size - c.used >= need) {
+        void* p = c.base + c.used;
+        c.used += need;
+        total_ += need;
+        return p;
+      }
+    Chunk c{};
+    c.size = std::max<size_t>(need, size_t(256) << 20);
+    c.base = static_cast<char*>(raw(c.size, c.a));
+    c.used = need;
+    chunks_.push_back(c);
+    total_ += need;
+    return c.base;
+  }
+  Allocator a;
+  void* p = raw(bytes, a);
   std::lock_guard<std::mutex> lk(mu_);
   blocks_.push_back({p, bytes, a});
   total_ += bytes;
   return p;
 }
 void Pool::release(void* p) {
+  if (arena_) return;
   std::lock_guard<std::mutex> lk(mu_);
   for (size_t i = 0; i < blocks_.size(); ++i)
     if (blocks_[i].p == p) {
@@ -181,6 +211,7 @@ struct Field {
   float* tf = nullptr;
   uint32_t deps[2] = {0, 0};  // fields read by the coupling rows: [0] forward, [1] adjoint sweep
   double setup_seconds = 0.0;  // wall time of this field's part of the last setup
+  double stage_seconds[8] = {};  // per setup stage (see hbgs_stats_t)
   int n() const { return hi - lo; }
 };
 
@@ -272,7 +303,7 @@ struct hbgs_ctx {
   int n = 0, nf = 0;
   int64_t nnz = 0;
   hbgs::Pool pool;
-  hbgs::Pool hier;  // value-dependent hierarchy (rebuilt by set_values)
+  hbgs::Pool hier{true};  // value-dependent hierarchy (rebuilt by set_values; arena)
   int *rp0 = nullptr, *ci0 = nullptr;  // caller's pattern
   int *perm = nullptr, *iperm = nullptr, *src = nullptr;
   int* srcT = nullptr;  // caller's value index of each A_p^T entry
@@ -440,14 +471,31 @@ static bool structurally_symmetric_dev(const DCsr& a, hipStream_t s) {
   return d == 0;
 }
 
+// host wall time per setup stage: to(q) closes the running stage and starts q
+struct StageClock {
+  double* acc;
+  std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+  int cur = -1;
+  explicit StageClock(double* a) : acc(a) {}
+  void to(int q) {
+    auto now = std::chrono::steady_clock::now();
+    if (cur >= 0) acc[cur] += std::chrono::duration<double>(now - t).count();
+    t = now;
+    cur = q;
+  }
+  ~StageClock() { to(-1); }
+};
+
 // SA-AMG hierarchy of one field's diagonal block (level 0 already set)
 static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
   const hbgs_options& o = c->o;
+  StageClock clk(F.stage_seconds);
   Pool& pool = c->hier;
   const uint64_t salt_base = splitmix64_host(o.seed + 0x1000ull * (uint64_t)(F.id + 1));
   Tmp<int> flag1(1);
   for (int l = 0;; ++l) {
     const int n = F.lv[l].A.n;
+    clk.to(6);
     Tmp<double> d(n);
     HBGS_HIP(hipMemsetAsync(flag1.p, 0, sizeof(int), s));
     setup::diagonal(F.lv[l].A, d.p, flag1.p, s);
@@ -458,6 +506,7 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
     bool last = n <= o.coarse_max || l + 1 >= o.max_levels;
     if (!last) {
       DCsr& A = F.lv[l].A;
+      clk.to(1);
       Tmp<char> strong(A.nnz), excluded(n), state(n), r1(n);
       Tmp<uint64_t> m1(n);
       setup::strength(A, d.p, o.theta[F.id], strong.p, excluded.p, s);
@@ -486,6 +535,7 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
       } else {
         F.lv[l].agg = agg;
         // filtered matrix and absolute-row-sum weight
+        clk.to(2);
         DCsr af;
         af.n = af.m = n;
         Tmp<int> cnt(n), afrp(n + 1);
@@ -511,7 +561,9 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
         P.ci = pool.make<int>(P.nnz);
         P.v = pool.make<double>(P.nnz);
         setup::psmooth_fill(af, agg, dabs.p, omega, P.rp, P.ci, P.v, s);
+        clk.to(3);
         DCsr R = transpose_new(pool, P, s);
+        clk.to(4);
         DCsr AP, Ac;
         Pool tmp_pool;
         setup::spgemm(A, P, AP, tmp_pool, s);
@@ -524,6 +576,7 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
     }
     Level& L = F.lv[l];
     if (last) {
+      clk.to(5);
       if (n > 8000) HBGS_FAIL(HBGS_ESETUP, "coarsest level too large for the dense factorisation");
       F.inv = pool.make<double>((size_t)n * n);
       if (setup::dense_inverse(L.A, F.inv, s) != 0) HBGS_FAIL(HBGS_ESINGULAR, "singular coarsest-level matrix");
@@ -531,6 +584,7 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
       setup::dense_transpose(n, F.inv, F.invT, s);
       break;
     }
+    clk.to(6);
     L.dinv = pool.make<double>(n);
     L.dinvf = pool.make<float>(n);
     setup::reciprocal(n, d.p, L.dinv, L.dinvf, s);
@@ -540,6 +594,7 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
     L.cc = cheb_coef(of, L.lam_cheb);
   }
   // solve-phase data: transposes, FP32 copies, work vectors
+  clk.to(7);
   if (!structurally_symmetric_dev(F.lv[0].A, s))
     HBGS_FAIL(HBGS_EINVAL, "a diagonal field block is not structurally symmetric");
   for (size_t l = 0; l < F.lv.size(); ++l) {
@@ -605,8 +660,10 @@ static void compute_stats(hbgs_ctx* c) {
     st.vcycle_bytes[p] = b;
     st.spmv_bytes[p] = spmv_bytes(c->Ap, 8, T, 8, 0);
   }
+  for (int q = 0; q < 8; ++q) st.setup_stage_seconds[q] = 0.0;
   for (int f = 0; f < c->nf && f < HBGS_MAX_FIELDS; ++f) {
     const Field& F = c->F[f];
+    for (int q = 0; q < 8; ++q) st.setup_stage_seconds[q] += F.stage_seconds[q];
     st.levels[f] = (int)F.lv.size();
     st.setup_field_seconds[f] = F.setup_seconds;
     for (size_t l = 0; l < F.lv.size() && l < HBGS_MAX_LEVELS; ++l) {
@@ -651,6 +708,9 @@ static void plan_sweep(hbgs_ctx* c, const std::vector<int>& leaves, int tr, Swee
 // SA-AMG hierarchy
 static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
+  std::fill(std::begin(F.stage_seconds), std::end(F.stage_seconds), 0.0);
+  StageClock clk(F.stage_seconds);
+  clk.to(0);
   F.lv.clear();
   F.lv.emplace_back();
   F.lv[0].A = extract(c->hier, c->Ap, F.lo, F.hi, F.lo, F.hi, F.lo, F.n(), s);
@@ -672,6 +732,8 @@ static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
   setup::row_stats(F.upperT, s);
   F.td = c->hier.make<double>(F.n());
   F.tf = c->hier.make<float>(F.n());
+  HBGS_HIP(hipStreamSynchronize(s));
+  clk.to(-1);
   build_hierarchy(c, F, s);
   HBGS_HIP(hipStreamSynchronize(s));
   F.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1237,6 +1299,17 @@ hbgs_status hbgs_setup(hbgs_ctx** out, int32_t n, int64_t nnz, const int32_t* ro
   if (n <= 0 || nnz <= 0 || nnz > INT32_MAX) HBGS_FAIL(HBGS_EINVAL, "n and nnz must be positive (nnz < 2^31)");
   if (n_fields < 1 || n_fields > HBGS_MAX_FIELDS) HBGS_FAIL(HBGS_EINVAL, "n_fields out of range");
   if (!rowptr || !col || !val || !field_of_row || !group_tree) HBGS_FAIL(HBGS_EINVAL, "NULL argument");
+  {
+    // setup temporaries come from HIP's default stream-ordered pool: let it
+    // keep freed memory so that rebuilds recycle it instead of reallocating
+    int dev = 0;
+    hipMemPool_t mp = nullptr;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&mp, dev) == hipSuccess && mp) {
+      uint64_t keep = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(mp, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+  }
   c = new hbgs_ctx();
   if (opt)
     c->o = *opt;

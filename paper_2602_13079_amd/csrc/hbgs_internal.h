@@ -46,13 +46,16 @@ Allocator current_allocator();
 
 // All device memory of a context goes through a Pool: persistent buffers
 // live until the pool is destroyed, temporaries are released explicitly.
-// Safe to use from several host threads.
+// An arena pool (the value-dependent hierarchy) carves allocations out of
+// large chunks and keeps the chunks when cleared, so a rebuild of the same
+// pattern allocates nothing.  Safe to use from several host threads.
 class Pool {
  public:
+  explicit Pool(bool arena = false) : arena_(arena) {}
   ~Pool();
   void* get(size_t bytes);  // persistent
-  void release(void* p);    // free one persistent allocation early
-  void clear();             // free everything
+  void release(void* p);    // free one allocation early (arena: kept until clear)
+  void clear();             // release everything (arena: chunks are kept for reuse)
   template <class T>
   T* make(size_t count) {
     return static_cast<T*>(get(count * sizeof(T) + (count == 0 ? sizeof(T) : 0)));
@@ -65,8 +68,16 @@ class Pool {
     size_t bytes;
     Allocator a;
   };
+  struct Chunk {
+    char* base;
+    size_t size, used;
+    Allocator a;
+  };
+  void* raw(size_t bytes, Allocator& a);
   std::mutex mu_;
+  bool arena_;
   std::vector<Block> blocks_;
+  std::vector<Chunk> chunks_;
   size_t total_ = 0;
 };
 

@@ -1245,53 +1245,242 @@ __global__ void k_lu_update(int n, int k, double* m) {
     m[(int64_t)i * n + j] -= m[(int64_t)i * n + k] * m[(int64_t)k * n + j];
   }
 }
-// Columns c0..c0+NC-1 of A^-1 = U^-1 L^-1 P e_c, one wavefront per group of
-// NC columns: the columns live in LDS, each substitution row is a
-// cross-lane dot product over the factor row (coalesced loads).
-// pinv[c] = row of P e_c holding the 1.
-template <int NC>
-__global__ __launch_bounds__(64) void k_lu_inverse(int n, const double* __restrict__ lu, const int* __restrict__ pinv,
-                                                   double* __restrict__ inv) {
-  extern __shared__ double y[];  // NC * n
-  const int lane = threadIdx.x;
-  const int c0 = blockIdx.x * NC;
-  int r[NC];
-  for (int q = 0; q < NC; ++q) r[q] = c0 + q < n ? pinv[c0 + q] : -1;
-  for (int i = lane; i < NC * n; i += 64) y[i] = 0.0;
+// Blocked form of the same factorisation (partial pivoting, the first row
+// of maximal |a_ik| as pivot, interchanges recorded as in the unblocked
+// steps) for n <= LU_MAXN: panels of LU_NB columns are factored by one
+// block holding the panel rows in registers; then the panel's interchanges
+// are applied to the other columns together with U12 = L11^-1 A12, and the
+// trailing matrix is updated by A22 -= L21 U12.
+__global__ void k_iota_i32(int n, int* p) {
+  GRID_STRIDE(i, n) p[i] = (int)i;
+}
+constexpr int LU_NB = 16;
+constexpr int LU_PT = 1024;
+constexpr int LU_R = 2;
+constexpr int LU_MAXN = LU_PT * LU_R;
+
+__global__ __launch_bounds__(LU_PT) void k_lu_panel(int n, int k0, double* m, int* piv, int* singular) {
+  __shared__ double wv[LU_PT / 64];
+  __shared__ int wi[LU_PT / 64];
+  __shared__ double prow[LU_NB], xrow[LU_NB];
+  __shared__ int sp;
+  __shared__ double spv;
+  const int rows = n - k0, nb = min(LU_NB, n - k0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double a[LU_R][LU_NB];
+#pragma unroll
+  for (int q = 0; q < LU_R; ++q) {
+    const int r = tid + q * LU_PT;
+#pragma unroll
+    for (int t = 0; t < LU_NB; ++t) a[q][t] = (r < rows && t < nb) ? m[(int64_t)(k0 + r) * n + k0 + t] : 0.0;
+  }
+  bool failed = false;
+#pragma unroll
+  for (int j = 0; j < LU_NB; ++j) {
+    if (j >= nb || failed) continue;  // uniform across the block
+    // pivot: largest |a_rj| over r >= j, first index on ties
+    double best = -1.0;
+    int bi = INT32_MAX;
+#pragma unroll
+    for (int q = 0; q < LU_R; ++q) {
+      const int r = tid + q * LU_PT;
+      if (r >= j && r < rows) {
+        const double v = fabs(a[q][j]);
+        if (v > best) {
+          best = v;
+          bi = r;
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      wv[wave] = best;
+      wi[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double b = wv[0];
+      int ib = wi[0];
+      for (int w = 1; w < LU_PT / 64; ++w)
+        if (wv[w] > b || (wv[w] == b && wi[w] < ib)) {
+          b = wv[w];
+          ib = wi[w];
+        }
+      sp = ib;
+      spv = b;
+      if (b > 0.0)
+        piv[k0 + j] = k0 + ib;
+      else
+        *singular = 1;
+    }
+    __syncthreads();
+    const int p = sp;
+    if (!(spv > 0.0)) {  // uniform: the factorisation has failed
+      failed = true;
+      continue;
+    }
+    // interchange panel rows j and p; the pivot row goes to prow
+#pragma unroll
+    for (int q = 0; q < LU_R; ++q) {
+      const int r = tid + q * LU_PT;
+      if (r == p)
+#pragma unroll
+        for (int t = 0; t < LU_NB; ++t) prow[t] = a[q][t];
+      if (r == j)
+#pragma unroll
+        for (int t = 0; t < LU_NB; ++t) xrow[t] = a[q][t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < LU_R; ++q) {
+      const int r = tid + q * LU_PT;
+      if (r == j)
+#pragma unroll
+        for (int t = 0; t < LU_NB; ++t) a[q][t] = prow[t];
+      else if (r == p)
+#pragma unroll
+        for (int t = 0; t < LU_NB; ++t) a[q][t] = xrow[t];
+    }
+    // multipliers and the update of the panel's remaining columns
+    const double d = prow[j];
+#pragma unroll
+    for (int q = 0; q < LU_R; ++q) {
+      const int r = tid + q * LU_PT;
+      if (r > j && r < rows) {
+        const double l = a[q][j] / d;
+        a[q][j] = l;
+#pragma unroll
+        for (int t = 0; t < LU_NB; ++t)
+          if (t > j) a[q][t] -= l * prow[t];
+      }
+    }
+    __syncthreads();
+  }
+  if (failed) return;
+#pragma unroll
+  for (int q = 0; q < LU_R; ++q) {
+    const int r = tid + q * LU_PT;
+    if (r < rows)
+#pragma unroll
+      for (int t = 0; t < LU_NB; ++t)
+        if (t < nb) m[(int64_t)(k0 + r) * n + k0 + t] = a[q][t];
+  }
+}
+
+// every column outside the panel: the panel's interchanges; trailing
+// columns also get U12 = L11^-1 A12 (L11 unit lower)
+__global__ void k_lu_swap_trsm(int n, int k0, int nb, double* m, const int* piv) {
+  GRID_STRIDE(c, n - nb) {
+    const int j = c < k0 ? (int)c : (int)c + nb;
+    for (int t = 0; t < nb; ++t) {
+      const int p = piv[k0 + t];
+      if (p > k0 + t && p < n) {
+        const double x = m[(int64_t)(k0 + t) * n + j];
+        m[(int64_t)(k0 + t) * n + j] = m[(int64_t)p * n + j];
+        m[(int64_t)p * n + j] = x;
+      }
+    }
+    if (j >= k0 + nb)
+      for (int t = 1; t < nb; ++t) {
+        double s = m[(int64_t)(k0 + t) * n + j];
+        for (int u = 0; u < t; ++u) s -= m[(int64_t)(k0 + t) * n + k0 + u] * m[(int64_t)(k0 + u) * n + j];
+        m[(int64_t)(k0 + t) * n + j] = s;
+      }
+  }
+}
+
+// A22 -= L21 U12 in tiles of 32 rows x 64 columns
+__global__ __launch_bounds__(BLK) void k_lu_gemm(int n, int k0, int nb, double* m) {
+  __shared__ double sL[32][LU_NB];
+  __shared__ double sU[LU_NB][64];
+  const int r0 = k0 + nb + blockIdx.y * 32, c0 = k0 + nb + blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 32 * LU_NB; e += BLK) {
+    const int i = e / LU_NB, t = e % LU_NB;
+    sL[i][t] = (r0 + i < n && t < nb) ? m[(int64_t)(r0 + i) * n + k0 + t] : 0.0;
+  }
+  for (int e = threadIdx.x; e < LU_NB * 64; e += BLK) {
+    const int t = e / 64, jj = e % 64;
+    sU[t][jj] = (c0 + jj < n && t < nb) ? m[(int64_t)(k0 + t) * n + c0 + jj] : 0.0;
+  }
   __syncthreads();
-  // forward: L y = P e_c (L unit lower)
-  for (int i = 0; i < n; ++i) {
-    double acc[NC];
-    for (int q = 0; q < NC; ++q) acc[q] = 0.0;
-    const double* row = lu + (int64_t)i * n;
-    for (int k = lane; k < i; k += 64) {
-      double l = row[k];
-      for (int q = 0; q < NC; ++q) acc[q] += l * y[q * n + k];
-    }
-    for (int q = 0; q < NC; ++q)
-      for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
-    if (lane == 0)
-      for (int q = 0; q < NC; ++q) y[q * n + i] = (i == r[q] ? 1.0 : 0.0) - acc[q];
-    __syncthreads();
+  const int jj = threadIdx.x & 63, ib = (threadIdx.x >> 6) * 8;
+  if (c0 + jj >= n) return;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int i = r0 + ib + u;
+    if (i >= n) break;
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < LU_NB; ++t) acc += sL[ib + u][t] * sU[t][jj];
+    m[(int64_t)i * n + c0 + jj] -= acc;
   }
-  // backward: U x = y
-  for (int i = n - 1; i >= 0; --i) {
-    double acc[NC];
-    for (int q = 0; q < NC; ++q) acc[q] = 0.0;
-    const double* row = lu + (int64_t)i * n;
-    for (int k = i + 1 + lane; k < n; k += 64) {
-      double u = row[k];
-      for (int q = 0; q < NC; ++q) acc[q] += u * y[q * n + k];
-    }
-    for (int q = 0; q < NC; ++q)
-      for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
-    if (lane == 0)
-      for (int q = 0; q < NC; ++q) y[q * n + i] = (y[q * n + i] - acc[q]) / row[i];
-    __syncthreads();
+}
+
+// Explicit inverse from the factors, X = U^-1 (L^-1 P), by blocks of
+// INV_NB rows: each block row of X is finished by a small triangular solve
+// (one thread per column) and then removed from the other block rows by a
+// tiled update (forward: the rows below; backward: the rows above).
+constexpr int INV_NB = 32;
+// X = P: column c holds a 1 in row pinv[c]
+__global__ void k_inv_init(int n, const int* pinv, double* x) {
+  GRID_STRIDE(e, (int64_t)n * n) {
+    const int i = (int)(e / n), c = (int)(e % n);
+    x[e] = pinv[c] == i ? 1.0 : 0.0;
   }
-  for (int q = 0; q < NC; ++q)
-    if (c0 + q < n)
-      for (int i = lane; i < n; i += 64) inv[(int64_t)i * n + c0 + q] = y[q * n + i];
+}
+// rows kb..kb+nb of X: unit lower (forward) or upper (backward) block solve
+template <bool UPPER>
+__global__ void k_inv_trsm(int n, int kb, int nb, const double* f, double* x) {
+  GRID_STRIDE(c, n) {
+    if (!UPPER) {
+      for (int t = 1; t < nb; ++t) {
+        double s = x[(int64_t)(kb + t) * n + c];
+        for (int u = 0; u < t; ++u) s -= f[(int64_t)(kb + t) * n + kb + u] * x[(int64_t)(kb + u) * n + c];
+        x[(int64_t)(kb + t) * n + c] = s;
+      }
+    } else {
+      for (int t = nb - 1; t >= 0; --t) {
+        double s = x[(int64_t)(kb + t) * n + c];
+        for (int u = t + 1; u < nb; ++u) s -= f[(int64_t)(kb + t) * n + kb + u] * x[(int64_t)(kb + u) * n + c];
+        x[(int64_t)(kb + t) * n + c] = s / f[(int64_t)(kb + t) * n + kb + t];
+      }
+    }
+  }
+}
+// X[i, :] -= F[i, kb..kb+nb) X[kb..kb+nb, :] for rows i in [r_lo, r_hi), in
+// tiles of 32 rows x 64 columns
+__global__ __launch_bounds__(BLK) void k_inv_update(int n, int kb, int nb, int r_lo, int r_hi, const double* f,
+                                                    double* x) {
+  __shared__ double sF[32][INV_NB];
+  __shared__ double sX[INV_NB][64];
+  const int r0 = r_lo + blockIdx.y * 32, c0 = blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 32 * INV_NB; e += BLK) {
+    const int i = e / INV_NB, t = e % INV_NB;
+    sF[i][t] = (r0 + i < r_hi && t < nb) ? f[(int64_t)(r0 + i) * n + kb + t] : 0.0;
+  }
+  for (int e = threadIdx.x; e < INV_NB * 64; e += BLK) {
+    const int t = e / 64, jj = e % 64;
+    sX[t][jj] = (c0 + jj < n && t < nb) ? x[(int64_t)(kb + t) * n + c0 + jj] : 0.0;
+  }
+  __syncthreads();
+  const int jj = threadIdx.x & 63, ib = (threadIdx.x >> 6) * 8;
+  if (c0 + jj >= n) return;
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int i = r0 + ib + u;
+    if (i >= r_hi) break;
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < INV_NB; ++t) acc += sF[ib + u][t] * sX[t][jj];
+    x[(int64_t)i * n + c0 + jj] -= acc;
+  }
 }
 
 int dense_inverse(const DCsr& a, double* inv, hipStream_t s) {
@@ -1301,9 +1490,22 @@ int dense_inverse(const DCsr& a, double* inv, hipStream_t s) {
   HBGS_HIP(hipMemsetAsync(sing.p, 0, sizeof(int), s));
   k_dense_fill<<<grid_for(n, 64), 64, 0, s>>>(n, a.rp, a.ci, a.v, m.p);
   HBGS_HIP(hipGetLastError());
-  for (int k = 0; k < n; ++k) {
-    k_lu_pivot<<<1, BLK, 0, s>>>(n, k, m.p, piv.p, sing.p);
-    if (k + 1 < n) k_lu_update<<<grid_for((int64_t)(n - k - 1) * (n - k - 1), BLK, 8192), BLK, 0, s>>>(n, k, m.p);
+  if (n <= LU_MAXN) {
+    k_iota_i32<<<grid_for(n, BLK), BLK, 0, s>>>(n, piv.p);  // no interchange unless a pivot is found
+    HBGS_HIP(hipGetLastError());
+    for (int k0 = 0; k0 < n; k0 += LU_NB) {
+      const int nb = std::min(LU_NB, n - k0);
+      k_lu_panel<<<1, LU_PT, 0, s>>>(n, k0, m.p, piv.p, sing.p);
+      if (n - nb > 0) k_lu_swap_trsm<<<grid_for(n - nb, BLK), BLK, 0, s>>>(n, k0, nb, m.p, piv.p);
+      const int rest = n - k0 - nb;
+      if (rest > 0) k_lu_gemm<<<dim3((rest + 63) / 64, (rest + 31) / 32), BLK, 0, s>>>(n, k0, nb, m.p);
+    }
+  } else {
+    for (int k = 0; k < n; ++k) {
+      k_lu_pivot<<<1, BLK, 0, s>>>(n, k, m.p, piv.p, sing.p);
+      if (k + 1 < n)
+        k_lu_update<<<grid_for((int64_t)(n - k - 1) * (n - k - 1), BLK, 8192), BLK, 0, s>>>(n, k, m.p);
+    }
   }
   HBGS_HIP(hipGetLastError());
   int singular = 0;
@@ -1318,13 +1520,21 @@ int dense_inverse(const DCsr& a, double* inv, hipStream_t s) {
   for (int k = 0; k < n; ++k) std::swap(rowof[k], rowof[hp[k]]);
   for (int r = 0; r < n; ++r) where[rowof[r]] = r;
   HBGS_HIP(hipMemcpyAsync(pinv.p, where.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
-  // columns per wavefront so that NC * n doubles fit in 64 KiB of LDS
-  if (n <= 2000)
-    k_lu_inverse<4><<<(n + 3) / 4, 64, 4 * n * sizeof(double), s>>>(n, m.p, pinv.p, inv);
-  else if (n <= 4000)
-    k_lu_inverse<2><<<(n + 1) / 2, 64, 2 * n * sizeof(double), s>>>(n, m.p, pinv.p, inv);
-  else
-    k_lu_inverse<1><<<n, 64, n * sizeof(double), s>>>(n, m.p, pinv.p, inv);
+  k_inv_init<<<grid_for((int64_t)n * n, BLK), BLK, 0, s>>>(n, pinv.p, inv);
+  HBGS_HIP(hipGetLastError());
+  const unsigned cgrid = (unsigned)((n + 63) / 64);
+  for (int kb = 0; kb < n; kb += INV_NB) {  // L Y = P
+    const int nb = std::min(INV_NB, n - kb);
+    k_inv_trsm<false><<<grid_for(n, BLK), BLK, 0, s>>>(n, kb, nb, m.p, inv);
+    const int below = n - kb - nb;
+    if (below > 0)
+      k_inv_update<<<dim3(cgrid, (below + 31) / 32), BLK, 0, s>>>(n, kb, nb, kb + nb, n, m.p, inv);
+  }
+  for (int kb = (n - 1) / INV_NB * INV_NB; kb >= 0; kb -= INV_NB) {  // U X = Y
+    const int nb = std::min(INV_NB, n - kb);
+    k_inv_trsm<true><<<grid_for(n, BLK), BLK, 0, s>>>(n, kb, nb, m.p, inv);
+    if (kb > 0) k_inv_update<<<dim3(cgrid, (kb + 31) / 32), BLK, 0, s>>>(n, kb, nb, 0, kb, m.p, inv);
+  }
   HBGS_HIP(hipGetLastError());
   HBGS_HIP(hipStreamSynchronize(s));
   return 0;
