@@ -607,12 +607,17 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
     add_f32(pool, L.A, s);
     add_f32(pool, L.AT, s);
     setup::row_stats(L.A, s);
+    setup::pack_columns(pool, L.A, s);
     L.AT.maxlen = L.A.maxlen;
+    L.AT.cd = L.A.cd;  // same pattern
+    L.AT.cb = L.A.cb;
     if (l + 1 < F.lv.size()) {
       add_f32(pool, L.P, s);
       add_f32(pool, L.R, s);
       setup::row_stats(L.P, s);
       setup::row_stats(L.R, s);
+      setup::pack_columns(pool, L.P, s);
+      setup::pack_columns(pool, L.R, s);
     }
     const int n = L.A.n;
     L.bd = pool.make<double>(n);
@@ -730,6 +735,8 @@ static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
   add_f32(c->hier, F.upperT, s);
   setup::row_stats(F.lower, s);
   setup::row_stats(F.upperT, s);
+  setup::pack_columns(c->hier, F.lower, s);
+  setup::pack_columns(c->hier, F.upperT, s);
   F.td = c->hier.make<double>(F.n());
   F.tf = c->hier.make<float>(F.n());
   HBGS_HIP(hipStreamSynchronize(s));
@@ -810,7 +817,10 @@ static void build_values(hbgs_ctx* c, hipStream_t s) {
     const bool bj = c->o.block_jacobi != 0;
     g.lower = extract(c->hier, c->Ap, g.lo, g.hi, 0, bj ? 0 : g.lo, 0, c->n, s);
     g.upperT = extract(c->hier, c->ApT, g.lo, g.hi, bj ? c->n : g.hi, c->n, 0, c->n, s);
-    for (DCsr* a : {&g.A, &g.AT, &g.lower, &g.upperT}) setup::row_stats(*a, s);
+    for (DCsr* a : {&g.A, &g.AT, &g.lower, &g.upperT}) {
+      setup::row_stats(*a, s);
+      setup::pack_columns(c->hier, *a, s);
+    }
   }
   // which fields each coupling reads (column ranges relative to the
   // coupling's own column origin)
@@ -1394,6 +1404,8 @@ hbgs_status hbgs_setup(hbgs_ctx** out, int32_t n, int64_t nnz, const int32_t* ro
   }
   setup::row_stats(c->Ap, s);
   setup::row_stats(c->ApT, s);
+  setup::pack_columns(c->pool, c->Ap, s);
+  setup::pack_columns(c->pool, c->ApT, s);
   build_values(c, s);
   c->stats.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = c;

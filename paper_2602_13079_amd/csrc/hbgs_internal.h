@@ -133,6 +133,7 @@ struct Tmp {
 };
 
 // ------------------------------------------------------------- device CSR
+constexpr int COL_CHUNK = 256;  // entries sharing one base of packed column indices
 struct DCsr {
   int n = 0, m = 0;  // rows, columns
   int64_t nnz = 0;
@@ -141,6 +142,11 @@ struct DCsr {
   double* v = nullptr;
   float* vf = nullptr;  // FP32 copy of v (solve phase, mixed precision)
   int maxlen = 0;  // longest row (selects the solve-phase kernel shape)
+  // packed column indices for the solve phase (null when a chunk of
+  // COL_CHUNK consecutive entries spans 65536 columns or more):
+  // col(k) = cb[k / COL_CHUNK] + cd[k]
+  uint16_t* cd = nullptr;
+  int* cb = nullptr;
   float avg_row() const { return n ? (float)nnz / (float)n : 0.f; }
 };
 
@@ -213,6 +219,9 @@ void cast_f32(int64_t n, const double* in, float* out, hipStream_t s);
 void transpose_symmetric(const DCsr& a, double* vt, hipStream_t s);
 // longest row of a (a.maxlen)
 void row_stats(DCsr& a, hipStream_t s);
+// builds a.cd / a.cb when every chunk of COL_CHUNK entries fits a 16-bit
+// offset from its smallest column (leaves them null otherwise)
+void pack_columns(Pool& pool, DCsr& a, hipStream_t s);
 // dense transpose of an n x n row-major matrix
 void dense_transpose(int n, const double* in, double* out, hipStream_t s);
 void reciprocal(int n, const double* d, double* dinv, float* dinvf, hipStream_t s);

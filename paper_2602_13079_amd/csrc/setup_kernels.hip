@@ -1584,6 +1584,62 @@ void row_stats(DCsr& a, hipStream_t s) {
   HBGS_HIP(hipStreamSynchronize(s));
 }
 
+// per chunk of COL_CHUNK entries: smallest column, and whether the chunk's
+// columns span 65536 or more
+__global__ __launch_bounds__(COL_CHUNK) void k_col_base(int64_t nnz, const int* ci, int* cb, int* bad) {
+  __shared__ int smin[COL_CHUNK / 64], smax[COL_CHUNK / 64];
+  const int64_t nch = (nnz + COL_CHUNK - 1) / COL_CHUNK;
+  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    const int64_t k = ch * COL_CHUNK + threadIdx.x;
+    int lo = INT32_MAX, hi = INT32_MIN;
+    if (k < nnz) lo = hi = ci[k];
+    for (int off = 32; off > 0; off >>= 1) {
+      lo = min(lo, __shfl_xor(lo, off, 64));
+      hi = max(hi, __shfl_xor(hi, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+      smin[threadIdx.x >> 6] = lo;
+      smax[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < COL_CHUNK / 64; ++w) {
+        lo = min(lo, smin[w]);
+        hi = max(hi, smax[w]);
+      }
+      cb[ch] = lo;
+      if ((int64_t)hi - (int64_t)lo > 65535) atomicOr(bad, 1);
+    }
+    __syncthreads();
+  }
+}
+__global__ void k_col_pack(int64_t nnz, const int* ci, const int* cb, uint16_t* cd) {
+  GRID_STRIDE(k, nnz) cd[k] = (uint16_t)(ci[k] - cb[k / COL_CHUNK]);
+}
+void pack_columns(Pool& pool, DCsr& a, hipStream_t s) {
+  a.cd = nullptr;
+  a.cb = nullptr;
+  if (a.nnz == 0) return;
+  const int64_t nch = (a.nnz + COL_CHUNK - 1) / COL_CHUNK;
+  int* cb = pool.make<int>(nch);
+  Tmp<int> bad(1);
+  HBGS_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
+  k_col_base<<<grid_for(nch, 1, 65536), COL_CHUNK, 0, s>>>(a.nnz, a.ci, cb, bad.p);
+  HBGS_HIP(hipGetLastError());
+  int h_bad = 0;
+  HBGS_HIP(hipMemcpyAsync(&h_bad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  if (h_bad) {
+    pool.release(cb);
+    return;
+  }
+  uint16_t* cd = pool.make<uint16_t>(a.nnz);
+  k_col_pack<<<grid_for(a.nnz, BLK), BLK, 0, s>>>(a.nnz, a.ci, cb, cd);
+  HBGS_HIP(hipGetLastError());
+  a.cd = cd;
+  a.cb = cb;
+}
+
 __global__ void k_dense_transpose(int n, const double* __restrict__ in, double* __restrict__ out) {
   GRID_STRIDE(t, (int64_t)n * n) {
     int i = (int)(t / n), j = (int)(t % n);

@@ -31,16 +31,28 @@ __device__ __forceinline__ T lanes_sum(T v, int lpr) {
   return v;
 }
 
+// column index loaders: plain int32, or packed 16-bit offsets from a base
+// per chunk of COL_CHUNK entries (2 bytes per entry instead of 4)
+struct ColPlain {
+  const int* __restrict__ ci;
+  __device__ int operator()(int k) const { return ci[k]; }
+};
+struct ColPacked {
+  const uint16_t* __restrict__ cd;
+  const int* __restrict__ cb;
+  __device__ int operator()(int k) const { return cb[k / COL_CHUNK] + (int)cd[k]; }
+};
+
 // acc = sum_k v[k] * X(ci[k]) over row `row`, then epi(row, acc)
-template <int LPR, class TV, class TACC, class LoadX, class Epi>
-__global__ __launch_bounds__(BLK) void k_csr(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                             const TV* __restrict__ v, LoadX lx, Epi epi) {
+template <int LPR, class TV, class TACC, class Col, class LoadX, class Epi>
+__global__ __launch_bounds__(BLK) void k_csr(int n, const int* __restrict__ rp, Col ci, const TV* __restrict__ v,
+                                             LoadX lx, Epi epi) {
   const int lane = threadIdx.x & (LPR - 1);
   const int row = (int)(((int64_t)blockIdx.x * BLK + threadIdx.x) / LPR);
   if (row >= n) return;
   const int s = rp[row], e = rp[row + 1];
   TACC acc = 0;
-  for (int k = s + lane; k < e; k += LPR) acc += (TACC)v[k] * (TACC)lx(ci[k]);
+  for (int k = s + lane; k < e; k += LPR) acc += (TACC)v[k] * (TACC)lx(ci(k));
   if (LPR > 1) acc = lanes_sum<TACC>(acc, LPR);
   if (lane == 0) epi.store(row, acc, epi.load(row));
 }
@@ -60,8 +72,8 @@ __global__ void k_empty(int n, Epi epi) {
 constexpr int SBLK = 256;
 constexpr int ROWS_LDS_BYTES = 16384;
 
-template <int RB, class TV, class TACC, class LoadX, class Epi>
-__global__ __launch_bounds__(SBLK) void k_csr_rows(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+template <int RB, class TV, class TACC, class Col, class LoadX, class Epi>
+__global__ __launch_bounds__(SBLK) void k_csr_rows(int n, const int* __restrict__ rp, Col ci,
                                                    const TV* __restrict__ v, LoadX lx, Epi epi) {
   constexpr int LPR = RB >= SBLK ? 1 : SBLK / RB;  // lanes per row in the row sums
   constexpr int RPT = RB >= SBLK ? RB / SBLK : 1;  // rows per thread
@@ -80,13 +92,13 @@ __global__ __launch_bounds__(SBLK) void k_csr_rows(int n, const int* __restrict_
   // two independent entries per step keep more gathers in flight
   int k = s0 + threadIdx.x;
   for (; k + SBLK < s1; k += 2 * SBLK) {
-    const int c0 = ci[k], c1 = ci[k + SBLK];
+    const int c0 = ci(k), c1 = ci(k + SBLK);
     const TV w0 = v[k], w1 = v[k + SBLK];
     const TACC x0 = (TACC)lx(c0), x1 = (TACC)lx(c1);
     prod[k - s0] = (TACC)w0 * x0;
     prod[k + SBLK - s0] = (TACC)w1 * x1;
   }
-  if (k < s1) prod[k - s0] = (TACC)v[k] * (TACC)lx(ci[k]);
+  if (k < s1) prod[k - s0] = (TACC)v[k] * (TACC)lx(ci(k));
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
@@ -101,15 +113,14 @@ __global__ __launch_bounds__(SBLK) void k_csr_rows(int n, const int* __restrict_
   }
 }
 
-template <class TV, class TACC, class LoadX, class Epi>
-static void launch_csr(const DCsr& a, const TV* v, LoadX lx, Epi epi, hipStream_t s) {
-  if (a.n == 0) return;
+template <class TV, class TACC, class Col, class LoadX, class Epi>
+static void launch_csr_cols(const DCsr& a, Col col, const TV* v, LoadX lx, Epi epi, hipStream_t s) {
   constexpr int cap = ROWS_LDS_BYTES / (int)sizeof(TACC);
-#define HBGS_ROWS(RB)                                                                                    \
-  if (a.maxlen > 0 && a.maxlen <= cap / RB) {                                                            \
-    k_csr_rows<RB, TV, TACC, LoadX, Epi><<<(a.n + RB - 1) / RB, SBLK, 0, s>>>(a.n, a.rp, a.ci, v, lx, epi); \
-    HBGS_HIP(hipGetLastError());                                                                         \
-    return;                                                                                              \
+#define HBGS_ROWS(RB)                                                                                      \
+  if (a.maxlen > 0 && a.maxlen <= cap / RB) {                                                              \
+    k_csr_rows<RB, TV, TACC, Col, LoadX, Epi><<<(a.n + RB - 1) / RB, SBLK, 0, s>>>(a.n, a.rp, col, v, lx, epi); \
+    HBGS_HIP(hipGetLastError());                                                                           \
+    return;                                                                                                \
   }
   HBGS_ROWS(512)
   HBGS_ROWS(256)
@@ -117,17 +128,12 @@ static void launch_csr(const DCsr& a, const TV* v, LoadX lx, Epi epi, hipStream_
   HBGS_ROWS(64)
   HBGS_ROWS(32)
 #undef HBGS_ROWS
-  if (a.nnz == 0) {  // rows without entries: epilogue of an empty sum
-    k_empty<TACC, Epi><<<grid_for(a.n, 256), 256, 0, s>>>(a.n, epi);
-    HBGS_HIP(hipGetLastError());
-    return;
-  }
   float avg = a.avg_row();
   int lpr = avg <= 1.5f ? 1 : avg <= 3.f ? 2 : avg <= 6.f ? 4 : avg <= 16.f ? 8 : avg <= 64.f ? 16 : avg <= 128.f ? 32 : 64;
   unsigned grid = (unsigned)(((int64_t)a.n * lpr + BLK - 1) / BLK);
 #define HBGS_CASE(L) \
   case L:            \
-    k_csr<L, TV, TACC, LoadX, Epi><<<grid, BLK, 0, s>>>(a.n, a.rp, a.ci, v, lx, epi); break;
+    k_csr<L, TV, TACC, Col, LoadX, Epi><<<grid, BLK, 0, s>>>(a.n, a.rp, col, v, lx, epi); break;
   switch (lpr) {
     HBGS_CASE(1)
     HBGS_CASE(2)
@@ -139,6 +145,20 @@ static void launch_csr(const DCsr& a, const TV* v, LoadX lx, Epi epi, hipStream_
   }
 #undef HBGS_CASE
   HBGS_HIP(hipGetLastError());
+}
+
+template <class TV, class TACC, class LoadX, class Epi>
+static void launch_csr(const DCsr& a, const TV* v, LoadX lx, Epi epi, hipStream_t s) {
+  if (a.n == 0) return;
+  if (a.nnz == 0) {  // rows without entries: epilogue of an empty sum
+    k_empty<TACC, Epi><<<grid_for(a.n, 256), 256, 0, s>>>(a.n, epi);
+    HBGS_HIP(hipGetLastError());
+    return;
+  }
+  if (a.cd)
+    launch_csr_cols<TV, TACC>(a, ColPacked{a.cd, a.cb}, v, lx, epi, s);
+  else
+    launch_csr_cols<TV, TACC>(a, ColPlain{a.ci}, v, lx, epi, s);
 }
 
 // operand loaders
