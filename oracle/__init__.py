@@ -27,7 +27,8 @@ class Options(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("theta", ctypes.c_double * 16), ("exact_leaves", ctypes.c_int32),
         ("block_jacobi", ctypes.c_int32), ("nested", ctypes.c_int32), ("inner_restart", ctypes.c_int32),
         ("inner_max_iters", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-        ("field_cheb_degree", ctypes.c_int32 * 16),
+        ("field_cheb_degree", ctypes.c_int32 * 16), ("field_leaf", ctypes.c_int32 * 16),
+        ("ilu_block", ctypes.c_int32),
     ]
 
 
@@ -106,11 +107,12 @@ def options(**kw) -> Options:
                 o.theta[i] = 0.0
             for i, t in enumerate(v):
                 o.theta[i] = t
-        elif k == "field_cheb_degree":
+        elif k in ("field_cheb_degree", "field_leaf"):
+            arr = getattr(o, k)
             for i in range(16):
-                o.field_cheb_degree[i] = 0
+                arr[i] = 0
             for i, t in enumerate(v):
-                o.field_cheb_degree[i] = t
+                arr[i] = t
         else:
             setattr(o, k, v)
     return o

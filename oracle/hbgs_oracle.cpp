@@ -41,6 +41,7 @@
 #include <cstring>
 #include <limits>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 namespace {
@@ -122,6 +123,9 @@ typedef struct {
   int32_t inner_max_iters; // cap on inner Arnoldi steps per solve
   double inner_rtol;       // inner target ||t - A_GG y|| / ||t||
   int32_t field_cheb_degree[16]; // > 0: Chebyshev degree of that field's V-cycle
+  int32_t field_leaf[16]; // leaf solver per field: 0 SA-AMG V-cycle, 1 diagonal
+                          // (one Jacobi sweep), 2 DD(0)-ILU(0)
+  int32_t ilu_block;      // rows per ILU(0) subdomain (contiguous row blocks)
 } or_options;
 }
 
@@ -648,6 +652,92 @@ void vcycle(const Amg& h, const or_options& o, int l, int transpose, const T* b,
   chebyshev<T>(L, o, transpose, b, x, false);
 }
 
+// ------------------------------------------------------------- other leaves
+// DD(0)-ILU(0) (the species-block preconditioner of Sec. 3.2, with the
+// domain decomposition of Sec. 3.1 without overlap): the block's rows are
+// cut into contiguous subdomains of `ilu_block` rows; entries coupling two
+// subdomains are dropped, and each subdomain block gets the incomplete LU
+// factorisation with zero fill: L unit lower and U upper on the block's own
+// pattern, computed row by row (IKJ order): for row i and each k < i in its
+// pattern (ascending), l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for every
+// j > k present in both rows i and k.
+struct Ilu {
+  int sub = 0;          // rows per subdomain
+  CsrD F, FT;           // factors (L strictly below, U on and above the diagonal) and their transpose
+  Csr<float> Ff, FTf;
+  std::vector<int> dpos, dposT;  // position of each row's diagonal in F / FT
+};
+
+bool ilu0_setup(const CsrD& a, int sub, Ilu& f) {
+  f.sub = sub;
+  CsrD& F = f.F;
+  F.n = F.m = a.n;
+  F.rp.assign(a.n + 1, 0);
+  for (int i = 0; i < a.n; ++i) {
+    for (int k = a.rp[i]; k < a.rp[i + 1]; ++k)
+      if (a.ci[k] / sub == i / sub) {
+        F.ci.push_back(a.ci[k]);
+        F.v.push_back(a.v[k]);
+      }
+    F.rp[i + 1] = (int)F.ci.size();
+  }
+  f.dpos.assign(a.n, -1);
+  for (int i = 0; i < a.n; ++i)
+    for (int k = F.rp[i]; k < F.rp[i + 1]; ++k)
+      if (F.ci[k] == i) f.dpos[i] = k;
+  for (int i = 0; i < a.n; ++i) {
+    if (f.dpos[i] < 0) return false;
+    for (int p = F.rp[i]; p < F.rp[i + 1] && F.ci[p] < i; ++p) {
+      const int k = F.ci[p];
+      const double l = F.v[p] / F.v[f.dpos[k]];
+      F.v[p] = l;
+      // a_ij -= l * u_kj for j > k in both rows (both sorted by column)
+      int q = f.dpos[k] + 1;
+      for (int r = p + 1; r < F.rp[i + 1]; ++r) {
+        while (q < F.rp[k + 1] && F.ci[q] < F.ci[r]) ++q;
+        if (q < F.rp[k + 1] && F.ci[q] == F.ci[r]) F.v[r] = F.v[r] - l * F.v[q];
+      }
+    }
+    if (F.v[f.dpos[i]] == 0.0) return false;
+  }
+  f.FT = transpose(F);
+  f.dposT.assign(a.n, -1);
+  for (int i = 0; i < a.n; ++i)
+    for (int k = f.FT.rp[i]; k < f.FT.rp[i + 1]; ++k)
+      if (f.FT.ci[k] == i) f.dposT[i] = k;
+  f.Ff = cast_csr<float>(F);
+  f.FTf = cast_csr<float>(f.FT);
+  return true;
+}
+
+template <class T>
+const Csr<T>& ilu_mat(const Ilu& f, int transpose);
+template <>
+const Csr<double>& ilu_mat<double>(const Ilu& f, int transpose) { return transpose ? f.FT : f.F; }
+template <>
+const Csr<float>& ilu_mat<float>(const Ilu& f, int transpose) { return transpose ? f.FTf : f.Ff; }
+
+// z = U^-1 L^-1 t (transpose: z = L^-T U^-T t, i.e. the same two sweeps on
+// the transposed factors: a lower sweep with U^T, dividing by the diagonal,
+// then an upper sweep with L^T, unit diagonal); each sum in ascending column
+template <class T>
+void ilu0_solve(const Ilu& f, int transpose, const T* t, T* z) {
+  const Csr<T>& M = ilu_mat<T>(f, transpose);
+  const std::vector<int>& dp = transpose ? f.dposT : f.dpos;
+  const int n = M.n;
+  std::vector<T> y(n);
+  for (int i = 0; i < n; ++i) {  // lower sweep
+    T s = t[i];
+    for (int k = M.rp[i]; k < dp[i]; ++k) s = s - M.v[k] * y[M.ci[k]];
+    y[i] = transpose ? s / M.v[dp[i]] : s;
+  }
+  for (int i = n - 1; i >= 0; --i) {  // upper sweep
+    T s = y[i];
+    for (int k = dp[i] + 1; k < M.rp[i + 1]; ++k) s = s - M.v[k] * z[M.ci[k]];
+    z[i] = transpose ? s : s / M.v[dp[i]];
+  }
+}
+
 // ----------------------------------------------------------- system context
 struct Node {  // field-group tree node
   int lo = 0, hi = 0;   // row range in the permuted ordering
@@ -668,6 +758,9 @@ struct Ctx {
   std::vector<Node> nodes;     // nodes[0] = root
   std::vector<int> leaf_order;
   std::vector<or_options> fo;  // per-field options (Chebyshev degree)
+  std::vector<std::vector<double>> dinv;  // diagonal leaves: 1 / a_ii (double and single)
+  std::vector<std::vector<float>> dinvf;
+  std::vector<Ilu> ilu;                   // ILU(0) leaves
   std::vector<CsrD> gA, gAT;   // nested form: diagonal block of each child of the root (and transpose)
 };
 
@@ -743,6 +836,15 @@ void leaf_solve(const Ctx& c, int f, int transpose, const T* t, T* z) {
     std::vector<double> td(t, t + n), zd(n);
     lu_solve(c.exact[f], td.data(), zd.data(), transpose);
     for (int i = 0; i < n; ++i) z[i] = (T)zd[i];
+    return;
+  }
+  const int leaf = c.o.field_leaf[f];
+  if (leaf == 1) {  // one Jacobi sweep from zero: exact for a diagonal block
+    for (int i = 0; i < n; ++i) z[i] = std::is_same<T, float>::value ? t[i] * (T)c.dinvf[f][i] : t[i] * (T)c.dinv[f][i];
+    return;
+  }
+  if (leaf == 2) {
+    ilu0_solve<T>(c.ilu[f], transpose, t, z);
     return;
   }
   vcycle<T>(c.amg[f], c.fo[f], 0, transpose, t, z);
@@ -986,6 +1088,8 @@ void or_default_options(or_options* o) {
   o->inner_max_iters = 300;
   o->inner_rtol = 1e-6;
   for (int f = 0; f < 16; ++f) o->field_cheb_degree[f] = 0;
+  for (int f = 0; f < 16; ++f) o->field_leaf[f] = 0;
+  o->ilu_block = 4096;
 }
 
 const char* or_last_error(void) { return g_err.msg.c_str(); }
@@ -1178,11 +1282,41 @@ or_ctx* or_setup(int n, const int* rp, const int* ci, const double* v, int nf, c
     }
   c->amg.resize(nf);
   c->exact.resize(nf);
+  c->ilu.resize(nf);
+  c->dinv.resize(nf);
+  c->dinvf.resize(nf);
   for (int f = 0; f < nf; ++f) {
+    if (o->field_leaf[f] < 0 || o->field_leaf[f] > 2 || o->ilu_block < 1) {
+      g_err = {-1, "invalid leaf solver options"};
+      delete c;
+      return nullptr;
+    }
     CsrD blk = block(ap, c->f_lo[f], c->f_hi[f]);
+    c->dinv[f].assign(blk.n, 0.0);
+    c->dinvf[f].assign(blk.n, 0.0f);
     if (o->exact_leaves) {
       if (!lu_factor(blk, c->exact[f])) {
         g_err = {-4, "singular diagonal block"};
+        delete c;
+        return nullptr;
+      }
+    } else if (o->field_leaf[f] == 1) {
+      std::vector<double> d(blk.n, 0.0);
+      for (int i = 0; i < blk.n; ++i)
+        for (int k = blk.rp[i]; k < blk.rp[i + 1]; ++k)
+          if (blk.ci[k] == i) d[i] = blk.v[k];
+      for (int i = 0; i < blk.n; ++i) {
+        if (d[i] == 0.0) {
+          g_err = {-1, "zero diagonal entry"};
+          delete c;
+          return nullptr;
+        }
+        c->dinv[f][i] = 1.0 / d[i];
+        c->dinvf[f][i] = (float)c->dinv[f][i];
+      }
+    } else if (o->field_leaf[f] == 2) {
+      if (!ilu0_setup(blk, o->ilu_block, c->ilu[f])) {
+        g_err = {-4, "zero pivot in the incomplete factorisation"};
         delete c;
         return nullptr;
       }
