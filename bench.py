@@ -231,13 +231,17 @@ def variants(H, torch, s, rp, ci, val, fl, b, reps=3):
         degree-4 Chebyshev on the voltage leaves;
       * block_jacobi: couplings dropped, all field V-cycles concurrent;
       * theta_phi_s: strength threshold of the phi_s hierarchy;
-      * cheb_degree_4: degree-4 Chebyshev on every level of every field."""
+      * cheb_degree_4: degree-4 Chebyshev on every level of every field;
+      * species_ilu0 / species_jacobi: the species leaves solved by DD(0)-ILU(0)
+        (4096-row subdomains) or one Jacobi sweep instead of SA-AMG."""
     nsp = s.nf - 3
     tree2 = [-1, -1, 0, 1, -2, -1] + list(range(2, 3 + nsp)) + [-2, -2]
     cases = {
         "nested": dict(tree=tree2, nested=1, restart=5, field_cheb_degree=[4, 4]),
         "block_jacobi": dict(block_jacobi=1),
         "cheb_degree_4": dict(cheb_degree=4),
+        "species_ilu0": dict(field_leaf=[0, 0, 0] + [2] * nsp, ilu_block=4096),
+        "species_jacobi": dict(field_leaf=[0, 0, 0] + [1] * nsp),
     }
     for th in (0.0, 0.01, 0.04, 0.16, 0.64):
         cases[f"theta_phi_s={th}"] = dict(theta=[th])

@@ -88,6 +88,13 @@ typedef struct {
   double inner_rtol;       /* inner stopping test ||t - A_GG y|| / ||t|| (default 1e-6) */
   int32_t field_cheb_degree[HBGS_MAX_FIELDS]; /* > 0: Chebyshev degree of that field's
                             V-cycle (e.g. 4 on the voltage leaves, Sec. 4); 0: cheb_degree */
+  int32_t field_leaf[HBGS_MAX_FIELDS]; /* leaf solver of each field's diagonal block:
+                            0 (default) one SA-AMG V-cycle; 1 one Jacobi sweep z = D^-1 t
+                            (exact for a diagonal block, e.g. the solid-species ODEs of
+                            Sec. 3.2); 2 DD(0)-ILU(0): contiguous subdomains of ilu_block
+                            rows without overlap, incomplete LU with zero fill in each
+                            (the species-block choice of Sec. 3.2) */
+  int32_t ilu_block;     /* rows per ILU(0) subdomain (default 4096) */
 } hbgs_options;
 
 typedef struct {

@@ -37,7 +37,8 @@ class Options(ctypes.Structure):
         ("theta", ctypes.c_double * MAX_FIELDS), ("use_graphs", ctypes.c_int32),
         ("setup_concurrent", ctypes.c_int32), ("block_jacobi", ctypes.c_int32), ("nested", ctypes.c_int32),
         ("inner_restart", ctypes.c_int32), ("inner_max_iters", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
-        ("field_cheb_degree", ctypes.c_int32 * MAX_FIELDS),
+        ("field_cheb_degree", ctypes.c_int32 * MAX_FIELDS), ("field_leaf", ctypes.c_int32 * MAX_FIELDS),
+        ("ilu_block", ctypes.c_int32),
     ]
 
 
@@ -104,7 +105,7 @@ def default_options(**kw) -> Options:
     o = Options()
     load().hbgs_default_options(ctypes.byref(o))
     for k, v in kw.items():
-        if k in ("theta", "field_cheb_degree"):
+        if k in ("theta", "field_cheb_degree", "field_leaf"):
             arr = getattr(o, k)
             for i in range(MAX_FIELDS):
                 arr[i] = 0

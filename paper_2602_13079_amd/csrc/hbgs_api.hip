@@ -212,6 +212,8 @@ struct Field {
   uint32_t deps[2] = {0, 0};  // fields read by the coupling rows: [0] forward, [1] adjoint sweep
   double setup_seconds = 0.0;  // wall time of this field's part of the last setup
   double stage_seconds[8] = {};  // per setup stage (see hbgs_stats_t)
+  int leaf = 0;                  // 0 SA-AMG V-cycle, 1 Jacobi sweep, 2 DD(0)-ILU(0)
+  IluLeaf ilu;
   int n() const { return hi - lo; }
 };
 
@@ -371,9 +373,12 @@ static void validate_options(const hbgs_options& o) {
     HBGS_FAIL(HBGS_EINVAL, "block_jacobi, nested and setup_concurrent must be 0 or 1");
   if (o.inner_restart < 1 || o.inner_restart > 64) HBGS_FAIL(HBGS_EINVAL, "inner_restart must be in [1, 64]");
   if (o.inner_max_iters < 0 || !(o.inner_rtol >= 0.0)) HBGS_FAIL(HBGS_EINVAL, "bad inner solver options");
-  for (int f = 0; f < HBGS_MAX_FIELDS; ++f)
+  for (int f = 0; f < HBGS_MAX_FIELDS; ++f) {
     if (o.field_cheb_degree[f] < 0 || o.field_cheb_degree[f] > 8)
       HBGS_FAIL(HBGS_EINVAL, "field_cheb_degree must be in [0, 8]");
+    if (o.field_leaf[f] < 0 || o.field_leaf[f] > 2) HBGS_FAIL(HBGS_EINVAL, "field_leaf must be 0, 1 or 2");
+  }
+  if (o.ilu_block < 1) HBGS_FAIL(HBGS_EINVAL, "ilu_block must be >= 1");
 }
 
 static void parse_tree(hbgs_ctx* c, const int32_t* tree, int len) {
@@ -503,6 +508,22 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
     HBGS_HIP(hipMemcpyAsync(&missing, flag1.p, sizeof(int), hipMemcpyDeviceToHost, s));
     HBGS_HIP(hipStreamSynchronize(s));
     if (missing) HBGS_FAIL(HBGS_EINVAL, "zero or missing diagonal entry in a field block");
+    if (F.leaf != 0) {  // one-level leaf: diagonal inverse, or the incomplete factors
+      Level& L = F.lv[0];
+      if (!structurally_symmetric_dev(L.A, s))
+        HBGS_FAIL(HBGS_EINVAL, "a diagonal field block is not structurally symmetric");
+      clk.to(6);
+      L.dinv = pool.make<double>(n);
+      L.dinvf = pool.make<float>(n);
+      setup::reciprocal(n, d.p, L.dinv, L.dinvf, s);
+      if (F.leaf == 2) {
+        clk.to(5);
+        if (setup::ilu_setup(pool, L.A, o.ilu_block, F.ilu, s) != 0)
+          HBGS_FAIL(HBGS_ESINGULAR, "zero pivot in the incomplete factorisation");
+      }
+      HBGS_HIP(hipStreamSynchronize(s));
+      return;
+    }
     bool last = n <= o.coarse_max || l + 1 >= o.max_levels;
     if (!last) {
       DCsr& A = F.lv[l].A;
@@ -649,6 +670,14 @@ static void compute_stats(hbgs_ctx* c) {
     for (int f : c->leaf_order) {
       const Field& F = c->F[f];
       if (F.lower.nnz) b += spmv_bytes(F.lower, T, T, T, 0) + 8.0 * F.n();
+      if (F.leaf == 1) {
+        b += 3.0 * T * F.n();
+        continue;
+      }
+      if (F.leaf == 2) {
+        b += 2.0 * spmv_bytes(F.ilu.F, T, T, T, 1);
+        continue;
+      }
       for (size_t l = 0; l + 1 < F.lv.size(); ++l) {
         const Level& L = F.lv[l];
         const DCsr& A = L.A;
@@ -714,6 +743,7 @@ static void plan_sweep(hbgs_ctx* c, const std::vector<int>& leaves, int tr, Swee
 static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
   std::fill(std::begin(F.stage_seconds), std::end(F.stage_seconds), 0.0);
+  F.leaf = c->o.field_leaf[F.id];
   StageClock clk(F.stage_seconds);
   clk.to(0);
   F.lv.clear();
@@ -983,6 +1013,19 @@ static void sweep(hbgs_ctx* c, const SweepPlan& plan, int tr, const double* v, T
     const bool d0 = F.lv.size() > 1 && L0.cc.degree == 2;
     const T* dinv0 = d0 ? Buf<T>::dinv(L0) : nullptr;
     T* d00 = d0 ? Buf<T>::d(L0) : nullptr;
+    if (F.leaf == 1) {  // z = D^-1 t straight from the coupling / cast epilogue
+      const T* dinv = Buf<T>::dinv(L0);
+      T* zf = z + off;
+      Prof p(c->prof, s, solve::K_COUPLE, (cpl.nnz ? spmv_bytes(cpl, TS, 0, TS, 2) : 0.0) + (8.0 + 2 * TS) * F.n());
+      if (cpl.nnz > 0)
+        VcOps<T>::couple(cpl, v + off, z, Buf<T>::t(F), dinv, 1.0, zf, s);
+      else if (sizeof(T) == sizeof(double))
+        VcOps<T>::make_d0(F.n(), reinterpret_cast<const T*>(v + off), dinv, 1.0, zf, s);
+      else
+        VcOps<T>::cast_in(F.n(), v + off, Buf<T>::t(F), dinv, 1.0, zf, s);
+      HBGS_HIP(hipEventRecord(c->fdone[F.id], s));
+      continue;
+    }
     const T* t;
     if (cpl.nnz > 0) {
       Prof p(c->prof, s, solve::K_COUPLE,
@@ -1000,7 +1043,12 @@ static void sweep(hbgs_ctx* c, const SweepPlan& plan, int tr, const double* v, T
       VcOps<T>::cast_in(F.n(), v + off, Buf<T>::t(F), dinv0, L0.cc.c0, d00, s);
       t = Buf<T>::t(F);
     }
-    vcycle<T>(c, F, 0, tr, t, z + off, s);
+    if (F.leaf == 2) {
+      Prof p(c->prof, s, solve::K_COARSE, 2.0 * spmv_bytes(F.ilu.F, TS, TS, TS, 1));
+      VcOps<T>::ilu(F.ilu, tr, t, z + off, s);
+    } else {
+      vcycle<T>(c, F, 0, tr, t, z + off, s);
+    }
     HBGS_HIP(hipEventRecord(c->fdone[F.id], s));
   }
   for (int q = 0; q < nl; ++q) HBGS_HIP(hipStreamWaitEvent(s0, c->fdone[plan.order[q]], 0));
@@ -1290,6 +1338,7 @@ void hbgs_default_options(hbgs_options* o) {
   o->inner_restart = 30;
   o->inner_max_iters = 300;
   o->inner_rtol = 1e-6;
+  o->ilu_block = 4096;
 }
 
 const char* hbgs_last_error(void) { return g_last_error.c_str(); }
@@ -1548,6 +1597,7 @@ hbgs_status hbgs_get_level(hbgs_ctx* c, int32_t field, int32_t level, int32_t wh
   bool coarsest = level + 1 == (int)c->F[field].lv.size();
   if ((which == 1 || which == 2) && coarsest) HBGS_FAIL(HBGS_EINVAL, "the coarsest level has no transfer operators");
   const DCsr& a = which == 0 ? L.A : which == 1 ? L.P : which == 2 ? L.R : L.AT;
+  if (!a.rp || !a.v) HBGS_FAIL(HBGS_EINVAL, "this operator is not built for the field's leaf solver");
   if (n_rows) *n_rows = a.n;
   if (n_cols) *n_cols = a.m;
   if (nnz) *nnz = a.nnz;

@@ -151,6 +151,25 @@ struct DCsr {
 };
 
 
+// DD(0)-ILU(0) leaf of one field: factors on the subdomain-block pattern of
+// the field's diagonal block (L strictly below the diagonal, unit diagonal
+// implied; U on and above), the transposed factors' values on the same
+// pattern (the block is structurally symmetric), and level schedules: within
+// subdomain b the rows of level l are order[lev[sub[b] + l] ..
+// lev[sub[b] + l + 1]) and depend only on rows of earlier levels (fwd: the
+// lower sweep and the factorisation; bwd: the upper sweep).
+struct IluLeaf {
+  DCsr F;                 // F.v: factors; F.vf: FP32 copy
+  double* vT = nullptr;   // transposed factors (same pattern)
+  float* vTf = nullptr;
+  int* dpos = nullptr;    // position of each row's diagonal entry
+  int nsub = 0;
+  int *ford = nullptr, *flev = nullptr, *fsub = nullptr;
+  int *bord = nullptr, *blev = nullptr, *bsub = nullptr;
+  double* yd = nullptr;   // intermediate vector of the two sweeps
+  float* yf = nullptr;
+};
+
 // ------------------------------------------------------ launch helpers
 inline unsigned grid_for(int64_t work, int block, int64_t cap = 1 << 20) {
   int64_t g = (work + block - 1) / block;
@@ -219,6 +238,9 @@ void cast_f32(int64_t n, const double* in, float* out, hipStream_t s);
 void transpose_symmetric(const DCsr& a, double* vt, hipStream_t s);
 // longest row of a (a.maxlen)
 void row_stats(DCsr& a, hipStream_t s);
+// DD(0)-ILU(0) of the n x n block a with subdomains of `sub` rows (factors,
+// transposed factors, schedules, FP32 copies); returns -4 on a zero pivot
+int ilu_setup(Pool& pool, const DCsr& a, int sub, IluLeaf& out, hipStream_t s);
 // builds a.cd / a.cb when every chunk of COL_CHUNK entries fits a 16-bit
 // offset from its smallest column (leaves them null otherwise)
 void pack_columns(Pool& pool, DCsr& a, hipStream_t s);
@@ -303,6 +325,7 @@ struct VcOps {
   static void coarse(int n, const double* inv, int transpose, const T* b, T* x, hipStream_t s);
   // t = (T)v - sum over coupling columns of a * z, rows of one field; with
   // d0 given also d0 = (D^-1 t) * c0 for the field's finest level
+  static void ilu(const IluLeaf& f, int transpose, const T* t, T* z, hipStream_t s);
   static void couple(const DCsr& c, const double* v, const T* z, T* t, const T* dinv, double c0, T* d0,
                      hipStream_t s);
   static void cast_in(int n, const double* v, T* t, const T* dinv, double c0, T* d0, hipStream_t s);

@@ -1584,6 +1584,157 @@ void row_stats(DCsr& a, hipStream_t s) {
   HBGS_HIP(hipStreamSynchronize(s));
 }
 
+// ------------------------------------------------------- DD(0)-ILU(0) leaf
+__global__ void k_sub_count(int n, const int* rp, const int* ci, int sub, int* cnt) {
+  GRID_STRIDE(i, n) {
+    const int b = (int)(i / sub);
+    int c = 0;
+    for (int k = rp[i]; k < rp[i + 1]; ++k) c += ci[k] / sub == b;
+    cnt[i] = c;
+  }
+}
+__global__ void k_sub_fill(int n, const int* rp, const int* ci, const double* v, int sub, const int* orp, int* oci,
+                           double* ov, int* dpos, int* missing) {
+  GRID_STRIDE(i, n) {
+    const int b = (int)(i / sub);
+    int o = orp[i], d = -1;
+    for (int k = rp[i]; k < rp[i + 1]; ++k)
+      if (ci[k] / sub == b) {
+        if (ci[k] == (int)i) d = o;
+        oci[o] = ci[k];
+        ov[o] = v[k];
+        ++o;
+      }
+    dpos[i] = d;
+    if (d < 0) atomicOr(missing, 1);
+  }
+}
+// one block per subdomain, level by level, one thread per row: the IKJ
+// row update (each l_ik, then a_ij -= l_ik u_kj in ascending j), the rows it
+// reads being final
+__global__ __launch_bounds__(BLK) void k_ilu_factor(const int* ford, const int* flev, const int* fsub, const int* rp,
+                                                    const int* ci, double* v, const int* dpos, int* zero_pivot) {
+  const int b = blockIdx.x;
+  for (int l = fsub[b]; l + 1 < fsub[b + 1]; ++l) {
+    for (int t = flev[l] + threadIdx.x; t < flev[l + 1]; t += BLK) {
+      const int i = ford[t];
+      for (int p = rp[i]; p < dpos[i]; ++p) {
+        const int k = ci[p];
+        const double lik = v[p] / v[dpos[k]];
+        v[p] = lik;
+        int q = dpos[k] + 1;
+        for (int r = p + 1; r < rp[i + 1]; ++r) {
+          while (q < rp[k + 1] && ci[q] < ci[r]) ++q;
+          if (q < rp[k + 1] && ci[q] == ci[r]) v[r] = v[r] - lik * v[q];
+        }
+      }
+      if (v[dpos[i]] == 0.0) atomicOr(zero_pivot, 1);
+    }
+    __syncthreads();
+  }
+}
+
+// level schedule of one direction on the host: level(i) = 1 + max level of
+// the rows it reads (lower part for fwd, upper part for bwd), per subdomain
+static void ilu_schedule(int n, int sub, const std::vector<int>& rp, const std::vector<int>& ci,
+                         const std::vector<int>& dpos, bool fwd, std::vector<int>& order, std::vector<int>& lev,
+                         std::vector<int>& subp) {
+  std::vector<int> level(n, 0);
+  if (fwd) {
+    for (int i = 0; i < n; ++i)
+      for (int k = rp[i]; k < dpos[i]; ++k) level[i] = std::max(level[i], level[ci[k]] + 1);
+  } else {
+    for (int i = n - 1; i >= 0; --i)
+      for (int k = dpos[i] + 1; k < rp[i + 1]; ++k) level[i] = std::max(level[i], level[ci[k]] + 1);
+  }
+  const int nsub = (n + sub - 1) / sub;
+  order.resize(n);
+  lev.clear();
+  subp.assign(nsub + 1, 0);
+  for (int b = 0; b < nsub; ++b) {
+    const int r0 = b * sub, r1 = std::min(n, r0 + sub);
+    int nl = 0;
+    for (int i = r0; i < r1; ++i) nl = std::max(nl, level[i] + 1);
+    std::vector<int> cnt(nl + 1, 0);
+    for (int i = r0; i < r1; ++i) cnt[level[i] + 1]++;
+    for (int q = 0; q < nl; ++q) cnt[q + 1] += cnt[q];
+    subp[b] = (int)lev.size();
+    for (int q = 0; q <= nl; ++q) lev.push_back(r0 + cnt[q]);
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    for (int i = r0; i < r1; ++i) order[r0 + fill[level[i]]++] = i;
+  }
+  subp[nsub] = (int)lev.size();
+}
+
+int ilu_setup(Pool& pool, const DCsr& a, int sub, IluLeaf& out, hipStream_t s) {
+  const int n = a.n;
+  DCsr& F = out.F;
+  F.n = F.m = n;
+  {
+    Tmp<int> cnt(n), missing(1);
+    F.rp = pool.make<int>(n + 1);
+    k_sub_count<<<grid_for(n, BLK), BLK, 0, s>>>(n, a.rp, a.ci, sub, cnt.p);
+    HBGS_HIP(hipGetLastError());
+    F.nnz = counts_to_rowptr(cnt.p, F.rp, n, s);
+    F.ci = pool.make<int>(F.nnz);
+    F.v = pool.make<double>(F.nnz);
+    out.dpos = pool.make<int>(n);
+    HBGS_HIP(hipMemsetAsync(missing.p, 0, sizeof(int), s));
+    k_sub_fill<<<grid_for(n, BLK), BLK, 0, s>>>(n, a.rp, a.ci, a.v, sub, F.rp, F.ci, F.v, out.dpos, missing.p);
+    HBGS_HIP(hipGetLastError());
+    int h_missing = 0;
+    HBGS_HIP(hipMemcpyAsync(&h_missing, missing.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    HBGS_HIP(hipStreamSynchronize(s));
+    if (h_missing) return -4;
+  }
+  // schedules (host)
+  std::vector<int> rp(n + 1), ci(F.nnz), dp(n);
+  HBGS_HIP(hipMemcpyAsync(rp.data(), F.rp, sizeof(int) * (n + 1), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipMemcpyAsync(ci.data(), F.ci, sizeof(int) * F.nnz, hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipMemcpyAsync(dp.data(), out.dpos, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  out.nsub = (n + sub - 1) / sub;
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<int> order, lev, subp;
+    ilu_schedule(n, sub, rp, ci, dp, pass == 0, order, lev, subp);
+    int* o = pool.make<int>(n);
+    int* l = pool.make<int>(lev.size());
+    int* sp = pool.make<int>(subp.size());
+    HBGS_HIP(hipMemcpyAsync(o, order.data(), sizeof(int) * n, hipMemcpyHostToDevice, s));
+    HBGS_HIP(hipMemcpyAsync(l, lev.data(), sizeof(int) * lev.size(), hipMemcpyHostToDevice, s));
+    HBGS_HIP(hipMemcpyAsync(sp, subp.data(), sizeof(int) * subp.size(), hipMemcpyHostToDevice, s));
+    HBGS_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+    if (pass == 0) {
+      out.ford = o;
+      out.flev = l;
+      out.fsub = sp;
+    } else {
+      out.bord = o;
+      out.blev = l;
+      out.bsub = sp;
+    }
+  }
+  // factorisation, transposed factors, FP32 copies, work vector
+  Tmp<int> zp(1);
+  HBGS_HIP(hipMemsetAsync(zp.p, 0, sizeof(int), s));
+  k_ilu_factor<<<out.nsub, BLK, 0, s>>>(out.ford, out.flev, out.fsub, F.rp, F.ci, F.v, out.dpos, zp.p);
+  HBGS_HIP(hipGetLastError());
+  int h_zero = 0;
+  HBGS_HIP(hipMemcpyAsync(&h_zero, zp.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  if (h_zero) return -4;
+  out.vT = pool.make<double>(F.nnz);
+  transpose_symmetric(F, out.vT, s);
+  F.vf = pool.make<float>(F.nnz);
+  out.vTf = pool.make<float>(F.nnz);
+  cast_f32(F.nnz, F.v, F.vf, s);
+  cast_f32(F.nnz, out.vT, out.vTf, s);
+  out.yd = pool.make<double>(n);
+  out.yf = pool.make<float>(n);
+  HBGS_HIP(hipStreamSynchronize(s));
+  return 0;
+}
+
 // per chunk of COL_CHUNK entries: smallest column, and whether the chunk's
 // columns span 65536 or more
 __global__ __launch_bounds__(COL_CHUNK) void k_col_base(int64_t nnz, const int* ci, int* cb, int* bad) {

@@ -463,6 +463,67 @@ void VcOps<T>::coarse(int n, const double* inv, int transpose, const T* b, T* x,
   HBGS_HIP(hipGetLastError());
 }
 
+// DD(0)-ILU(0) sweeps: one block per subdomain, level by level, one thread
+// per row (each sum in ascending column)
+template <class T, bool DIAG>
+__global__ __launch_bounds__(BLK) void k_ilu_lower(const int* __restrict__ ord, const int* __restrict__ lev,
+                                                   const int* __restrict__ sub, const int* __restrict__ rp,
+                                                   const int* __restrict__ ci, const T* __restrict__ v,
+                                                   const int* __restrict__ dpos, const T* __restrict__ t, T* y) {
+  const int b = blockIdx.x;
+  for (int l = sub[b]; l + 1 < sub[b + 1]; ++l) {
+    for (int q = lev[l] + threadIdx.x; q < lev[l + 1]; q += BLK) {
+      const int i = ord[q];
+      T s = t[i];
+      for (int k = rp[i]; k < dpos[i]; ++k) s -= v[k] * y[ci[k]];
+      y[i] = DIAG ? s / v[dpos[i]] : s;
+    }
+    __syncthreads();
+  }
+}
+template <class T, bool DIAG>
+__global__ __launch_bounds__(BLK) void k_ilu_upper(const int* __restrict__ ord, const int* __restrict__ lev,
+                                                   const int* __restrict__ sub, const int* __restrict__ rp,
+                                                   const int* __restrict__ ci, const T* __restrict__ v,
+                                                   const int* __restrict__ dpos, const T* __restrict__ y, T* z) {
+  const int b = blockIdx.x;
+  for (int l = sub[b]; l + 1 < sub[b + 1]; ++l) {
+    for (int q = lev[l] + threadIdx.x; q < lev[l + 1]; q += BLK) {
+      const int i = ord[q];
+      T s = y[i];
+      for (int k = dpos[i] + 1; k < rp[i + 1]; ++k) s -= v[k] * z[ci[k]];
+      z[i] = DIAG ? s / v[dpos[i]] : s;
+    }
+    __syncthreads();
+  }
+}
+template <class T>
+static const T* ilu_vals(const IluLeaf& f, int transpose);
+template <>
+const double* ilu_vals<double>(const IluLeaf& f, int transpose) {
+  return transpose ? f.vT : f.F.v;
+}
+template <>
+const float* ilu_vals<float>(const IluLeaf& f, int transpose) {
+  return transpose ? f.vTf : f.F.vf;
+}
+// z = U^-1 L^-1 t, or z = L^-T U^-T t (lower sweep on the transposed
+// factors dividing by the diagonal, then the unit upper sweep)
+template <class T>
+void VcOps<T>::ilu(const IluLeaf& f, int transpose, const T* t, T* z, hipStream_t s) {
+  const T* v = ilu_vals<T>(f, transpose);
+  T* y = sizeof(T) == sizeof(double) ? reinterpret_cast<T*>(f.yd) : reinterpret_cast<T*>(f.yf);
+  const DCsr& F = f.F;
+  if (!transpose) {
+    k_ilu_lower<T, false><<<f.nsub, BLK, 0, s>>>(f.ford, f.flev, f.fsub, F.rp, F.ci, v, f.dpos, t, y);
+    k_ilu_upper<T, true><<<f.nsub, BLK, 0, s>>>(f.bord, f.blev, f.bsub, F.rp, F.ci, v, f.dpos, y, z);
+  } else {
+    k_ilu_lower<T, true><<<f.nsub, BLK, 0, s>>>(f.ford, f.flev, f.fsub, F.rp, F.ci, v, f.dpos, t, y);
+    k_ilu_upper<T, false><<<f.nsub, BLK, 0, s>>>(f.bord, f.blev, f.bsub, F.rp, F.ci, v, f.dpos, y, z);
+  }
+  HBGS_HIP(hipGetLastError());
+}
+
 template struct VcOps<float>;
 template struct VcOps<double>;
 

@@ -1,9 +1,10 @@
 """GPU parity of the preconditioner variants against the CPU oracle, through
-the C ABI: block Jacobi (couplings dropped), per-field Chebyshev degree, and
-the nested form of Sec. 3.2 (an inner flexible GMRES per child of the
-outermost group, preconditioned by that child's sweep).
+the C ABI: block Jacobi (couplings dropped), per-field Chebyshev degree,
+the other leaf solvers (diagonal / DD(0)-ILU(0)), and the nested form of
+Sec. 3.2 (an inner flexible GMRES per child of the outermost group,
+preconditioned by that child's sweep).
 
-Bars: block Jacobi and per-field degree as the single sweep (FP64 apply
+Bars: block Jacobi, per-field degree and the leaves as the single sweep (FP64 apply
 <= 1e-13, FP32 V-cycle <= 1e-5, same iteration counts within 2).  The
 nested preconditioner is not a fixed linear operator once the inner solve
 stops on a tolerance, so its parity is taken with the inner and outer step
@@ -134,3 +135,25 @@ def test_nested_paper_settings(torch_dev, case, precision):
         assert abs(it - ro["iters"]) <= 1, (it, ro["iters"])
         assert it <= 6
         assert _res(s, x.cpu().numpy(), b, tr) <= 1e-8
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("leaf", [1, 2])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_leaf_solvers(torch_dev, case, leaf, precision):
+    """Diagonal (Jacobi) and DD(0)-ILU(0) leaves on the species block(s),
+    SA-AMG elsewhere: apply parity in both directions, and the solve."""
+    torch, dev = torch_dev
+    s = _system(case)
+    leaves = [0, 0, 0] + [leaf] * (s.nf - 3)
+    s, g, o = _pair(torch_dev, case, field_leaf=leaves, ilu_block=48, precision=precision)
+    r = np.random.default_rng(9).standard_normal(s.n)
+    tol = 1e-13 if precision == 0 else 1e-5
+    for tr in (False, True):
+        z = g.apply(torch.from_numpy(r).to(dev), transpose=tr).cpu().numpy()
+        zo = o.apply(r, transpose=tr)
+        assert np.linalg.norm(z - zo) <= tol * np.linalg.norm(zo), (tr, np.linalg.norm(z - zo) / np.linalg.norm(zo))
+    x, st, it, _ = g.solve(torch.from_numpy(s.b).to(dev))
+    ro = o.solve(s.b)
+    assert st == 0 and ro["status"] == 0 and abs(it - ro["iters"]) <= 2
+    assert _res(s, x.cpu().numpy(), s.b) <= 1e-8
