@@ -1284,19 +1284,19 @@ static hbgs_status gmres(hbgs_ctx* c, int tr, int use_x0, int32_t* iters, double
                 graph_key, s);
 }
 
+#define HBGS_FOR_ALL(k, n) \
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < (n); k += (int64_t)gridDim.x * blockDim.x)
 __global__ void k_gather_vals(int64_t nnz, const double* v, const int* src, double* vp) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < nnz) vp[k] = v[src[k]];
+  HBGS_FOR_ALL(k, nnz) vp[k] = v[src[k]];
 }
 __global__ void k_iota_f64(int64_t nnz, double* p) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < nnz) p[k] = (double)k;
+  HBGS_FOR_ALL(k, nnz) p[k] = (double)k;
 }
 // srcT[k] = src[position of A_p^T entry k in A_p]
 __global__ void k_compose(int64_t nnz, const double* pos, const int* src, int* srcT) {
-  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < nnz) srcT[k] = src[(int64_t)pos[k]];
+  HBGS_FOR_ALL(k, nnz) srcT[k] = src[(int64_t)pos[k]];
 }
+#undef HBGS_FOR_ALL
 
 }  // namespace hbgs
 

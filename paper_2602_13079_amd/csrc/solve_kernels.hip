@@ -59,8 +59,7 @@ __global__ __launch_bounds__(BLK) void k_csr(int n, const int* __restrict__ rp, 
 
 template <class TACC, class Epi>
 __global__ void k_empty(int n, Epi epi) {
-  int i = blockIdx.x * 256 + threadIdx.x;
-  if (i < n) epi.store(i, TACC(0), epi.load(i));
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) epi.store((int)i, TACC(0), epi.load((int)i));
 }
 // Row-block streaming form for short and medium rows (longest row <=
 // ROWS_LDS / RB).  Block b owns rows [RB b, RB (b+1)) and their entries: the
@@ -337,12 +336,12 @@ const float* vals_of<float>(const DCsr& a) {
 template <class T>
 __global__ void k_cheb_init0(int n, const T* __restrict__ dinv, const T* __restrict__ b, T c0, T* __restrict__ r,
                              T* __restrict__ d, T* __restrict__ x) {
-  int i = blockIdx.x * BLK + threadIdx.x;
-  if (i >= n) return;
-  T di = dinv[i] * b[i] * c0;
-  r[i] = b[i];
-  d[i] = di;
-  x[i] = di;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
+    T di = dinv[i] * b[i] * c0;
+    r[i] = b[i];
+    d[i] = di;
+    x[i] = di;
+  }
 }
 
 template <class T>
@@ -352,8 +351,7 @@ void VcOps<T>::pre2(const DCsr& a, const T* dinv, const ChebCoef& c, const T* b,
 
 template <class T>
 __global__ void k_make_d0(int n, const T* __restrict__ b, const T* __restrict__ dinv, T c0, T* __restrict__ d0) {
-  int i = blockIdx.x * BLK + threadIdx.x;
-  if (i < n) d0[i] = dinv[i] * b[i] * c0;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) d0[i] = dinv[i] * b[i] * c0;
 }
 template <class T>
 void VcOps<T>::make_d0(int n, const T* b, const T* dinv, double c0, T* d0, hipStream_t s) {
@@ -375,8 +373,7 @@ void VcOps<T>::post_start(const DCsr& a, const T* dinv, const ChebCoef& c, const
 
 template <class T>
 __global__ void k_add(int n, const T* __restrict__ d, T* __restrict__ x) {
-  int i = blockIdx.x * BLK + threadIdx.x;
-  if (i < n) x[i] = x[i] + d[i];
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) x[i] = x[i] + d[i];
 }
 
 template <class T>
@@ -422,11 +419,11 @@ void VcOps<T>::couple(const DCsr& c, const double* v, const T* z, T* t, const T*
 template <class T>
 __global__ void k_cast_in(int n, const double* __restrict__ v, T* __restrict__ t, const T* __restrict__ dinv, T c0,
                           T* __restrict__ d0) {
-  int i = blockIdx.x * BLK + threadIdx.x;
-  if (i >= n) return;
-  T ti = (T)v[i];
-  t[i] = ti;
-  if (d0) d0[i] = dinv[i] * ti * c0;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
+    T ti = (T)v[i];
+    t[i] = ti;
+    if (d0) d0[i] = dinv[i] * ti * c0;
+  }
 }
 template <class T>
 void VcOps<T>::cast_in(int n, const double* v, T* t, const T* dinv, double c0, T* d0, hipStream_t s) {
@@ -530,13 +527,11 @@ template struct VcOps<double>;
 // --------------------------------------------------------------- GMRES
 __global__ void k_permute_in(int n, const int* __restrict__ perm, const double* __restrict__ x,
                              double* __restrict__ xp) {
-  int i = blockIdx.x * BLK + threadIdx.x;
-  if (i < n) xp[perm[i]] = x[i];
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) xp[perm[i]] = x[i];
 }
 __global__ void k_permute_out(int n, const int* __restrict__ perm, const double* __restrict__ xp,
                               double* __restrict__ x) {
-  int i = blockIdx.x * BLK + threadIdx.x;
-  if (i < n) x[i] = xp[perm[i]];
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) x[i] = xp[perm[i]];
 }
 void permute_in(int n, const int* perm, const double* x, double* xp, hipStream_t s) {
   k_permute_in<<<grid_for(n, BLK), BLK, 0, s>>>(n, perm, x, xp);
@@ -750,11 +745,11 @@ void backsolve(int jend, int m, const double* H, const double* g, double* y, hip
 template <class TZ>
 __global__ void k_xupdate(int n, int jend, const TZ* __restrict__ Z, size_t ldz, const double* __restrict__ y,
                           double* __restrict__ x) {
-  int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-  if (i >= n) return;
-  double xi = x[i];
-  for (int k = 0; k < jend; ++k) xi += y[k] * (double)Z[(size_t)k * ldz + i];
-  x[i] = xi;
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
+    double xi = x[i];
+    for (int k = 0; k < jend; ++k) xi += y[k] * (double)Z[(size_t)k * ldz + i];
+    x[i] = xi;
+  }
 }
 template <class TZ>
 void xupdate(int n, int jend, const TZ* Z, size_t ldz, const double* y, double* x, hipStream_t s) {
@@ -779,9 +774,8 @@ void norm2_partial(int n, const double* x, double* part, hipStream_t s) {
 
 __global__ void k_scale_copy(int n, const double* __restrict__ r, const double* __restrict__ ss,
                              double* __restrict__ v) {
-  int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x;
-  double nr = sqrt(*ss);
-  if (i < n) v[i] = r[i] / nr;
+  const double nr = sqrt(*ss);
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) v[i] = r[i] / nr;
 }
 void scale_copy(int n, const double* r, const double* part_sum, double* v, hipStream_t s) {
   k_scale_copy<<<grid_for(n, BLK), BLK, 0, s>>>(n, r, part_sum, v);
@@ -790,10 +784,10 @@ void scale_copy(int n, const double* r, const double* part_sum, double* v, hipSt
 
 __global__ void k_grad(int n, const int* __restrict__ rp, const int* __restrict__ ci, const double* __restrict__ lam,
                        const double* __restrict__ x, double* __restrict__ g) {
-  int i = blockIdx.x * BLK + threadIdx.x;
-  if (i >= n) return;
-  double li = lam[i];
-  for (int k = rp[i]; k < rp[i + 1]; ++k) g[k] = -li * x[ci[k]];
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
+    double li = lam[i];
+    for (int k = rp[i]; k < rp[i + 1]; ++k) g[k] = -li * x[ci[k]];
+  }
 }
 void grad_values(int n, const int* rp, const int* ci, const double* lam, const double* x, double* g,
                  hipStream_t s) {
