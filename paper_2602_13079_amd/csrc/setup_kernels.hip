@@ -856,11 +856,6 @@ __device__ __forceinline__ uint32_t hslot(int c, uint32_t mask) { return ((uint3
 constexpr int SPG_WAVES = 4;          // rows (waves) per block
 constexpr int SPG_SYM_SLOTS = 4096;   // symbolic: keys per wave (16 KB)
 constexpr int SPG_NUM_SLOTS = 1024;   // numeric: keys and values per wave (12 KB)
-__device__ __forceinline__ int wave_table(int64_t need) {  // power of two >= 2 need, at least 64
-  int t = 64;
-  while (t < 2 * need) t <<= 1;
-  return t;
-}
 constexpr int SPG_BLK_SLOTS = 4096;  // numeric, one block per row: keys and values (48 KB)
 // distinct columns of a product row are at most min(ub, columns of B)
 __device__ __forceinline__ int64_t sym_need(int64_t ub, int m) { return ub < m ? ub : (int64_t)m; }
@@ -884,51 +879,66 @@ __device__ __forceinline__ int lds_claim(int* keys, uint32_t mask, int c, bool* 
   return -1;
 }
 
-__global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_sym_wave(int n, int bm, const int* arp, const int* aci,
-                                                                   const int* brp, const int* bci,
-                                                                   const int64_t* ub, int* cnt, int* overflow) {
+// Groups of LPR lanes (64 / LPR rows per wavefront): a group walks its row
+// of A in order and its lanes take the entries of one row of B at a time.
+// Each row owns SLOTS / (64 / LPR) table slots; the kernel takes the rows
+// whose size measure lies in (lo, hi] and leaves the others to the wider
+// kernels (lanes of one wavefront stay in lockstep, so the per-slot order
+// argument above holds group by group).
+__device__ __forceinline__ int group_table(int64_t need) {  // power of two >= 2 need, at least 16
+  int t = 16;
+  while (t < 2 * need) t <<= 1;
+  return t;
+}
+template <int LPR>
+__global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_sym_grp(int n, int bm, const int* arp, const int* aci,
+                                                                  const int* brp, const int* bci, const int64_t* ub,
+                                                                  int64_t lo, int64_t hi, int* cnt, int* overflow) {
+  constexpr int G = 64 / LPR, SLOTS = SPG_SYM_SLOTS / G;
   __shared__ int tab[SPG_WAVES][SPG_SYM_SLOTS];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * SPG_WAVES + wave;
-  if (i >= n) return;
-  const int64_t need = sym_need(ub[i], bm);
-  if (!sym_fits(need)) return;
-  const int T = wave_table(need);
-  int* keys = tab[wave];
-  for (int q = lane; q < T; q += 64) keys[q] = -1;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  const uint32_t mask = (uint32_t)(T - 1);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane / LPR, gl = lane % LPR;
+  const int64_t i = ((int64_t)blockIdx.x * SPG_WAVES + wave) * G + grp;
+  const int64_t need = i < n ? sym_need(ub[i], bm) : 0;
+  const bool active = i < n && need > lo && need <= hi && 2 * need <= SLOTS;
   int u = 0;
-  for (int k = arp[i]; k < arp[i + 1]; ++k) {
-    const int kk = aci[k];
-    for (int q = brp[kk] + lane; q < brp[kk + 1]; q += 64) {
-      bool fresh;
-      if (lds_claim(keys, mask, bci[q], &fresh) < 0) atomicOr(overflow, 1);
-      u += fresh;
+  if (active) {
+    const int T = group_table(need);
+    int* keys = tab[wave] + grp * SLOTS;
+    for (int q = gl; q < T; q += LPR) keys[q] = -1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t mask = (uint32_t)(T - 1);
+    for (int k = arp[i]; k < arp[i + 1]; ++k) {
+      const int kk = aci[k];
+      for (int q = brp[kk] + gl; q < brp[kk + 1]; q += LPR) {
+        bool fresh;
+        if (lds_claim(keys, mask, bci[q], &fresh) < 0) atomicOr(overflow, 1);
+        u += fresh;
+      }
     }
   }
-  for (int off = 32; off > 0; off >>= 1) u += __shfl_xor(u, off, 64);
-  if (lane == 0) cnt[i] = u;
+  for (int off = LPR >> 1; off > 0; off >>= 1) u += __shfl_xor(u, off, LPR);
+  if (active && gl == 0) cnt[i] = u;
 }
 
-__global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_num_wave(int n, const int* arp, const int* aci,
-                                                                   const double* av, const int* brp,
-                                                                   const int* bci, const double* bv,
-                                                                   const int* crp, int* cci, double* cv,
-                                                                   int* overflow) {
+template <int LPR>
+__global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_num_grp(int n, const int* arp, const int* aci,
+                                                                  const double* av, const int* brp, const int* bci,
+                                                                  const double* bv, const int* crp, int64_t lo,
+                                                                  int64_t hi, int* cci, double* cv, int* overflow) {
+  constexpr int G = 64 / LPR, SLOTS = SPG_NUM_SLOTS / G;
   __shared__ int tk[SPG_WAVES][SPG_NUM_SLOTS];
   __shared__ double tv[SPG_WAVES][SPG_NUM_SLOTS];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int i = blockIdx.x * SPG_WAVES + wave;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane / LPR, gl = lane % LPR;
+  const int64_t i = ((int64_t)blockIdx.x * SPG_WAVES + wave) * G + grp;
   if (i >= n) return;
   const int o = crp[i], cnt = crp[i + 1] - o;
-  if (!num_fits(cnt)) return;
-  const int T = wave_table(cnt);
-  int* keys = tk[wave];
-  double* vals = tv[wave];
-  for (int q = lane; q < T; q += 64) {
+  if (!(cnt > lo && cnt <= hi && 2 * cnt <= SLOTS)) return;
+  const int T = group_table(cnt);
+  int* keys = tk[wave] + grp * SLOTS;
+  double* vals = tv[wave] + grp * SLOTS;
+  for (int q = gl; q < T; q += LPR) {
     keys[q] = -1;
     vals[q] = 0.0;
   }
@@ -939,7 +949,7 @@ __global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_num_wave(int n, const
   for (int k = arp[i]; k < arp[i + 1]; ++k) {
     const int kk = aci[k];
     const double a = av[k];
-    for (int q = brp[kk] + lane; q < brp[kk + 1]; q += 64) {
+    for (int q = brp[kk] + gl; q < brp[kk + 1]; q += LPR) {
       bool fresh;
       const int h = lds_claim(keys, mask, bci[q], &fresh);
       if (h >= 0)
@@ -952,7 +962,7 @@ __global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_num_wave(int n, const
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   // each occupied slot goes to its rank among the row's columns
-  for (int q = lane; q < T; q += 64) {
+  for (int q = gl; q < T; q += LPR) {
     const int c = keys[q];
     if (c < 0) continue;
     int rank = 0;
@@ -1131,9 +1141,24 @@ void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
   HBGS_HIP(hipMemsetAsync(overflow.p, 0, sizeof(int), s));
   k_spgemm_ub<<<grid_for(n, BLK), BLK, 0, s>>>(n, a.rp, a.ci, b.rp, ub.p);
   HBGS_HIP(hipGetLastError());
-  const unsigned wgrid = (unsigned)(((int64_t)n + SPG_WAVES - 1) / SPG_WAVES);
+  // lanes per row from the mean length of B's rows; rows too long for the
+  // group tables go to the one-row-per-wavefront kernels
+  const double bavg = b.n ? (double)b.nnz / b.n : 0.0;
+  const int lpr = bavg <= 8.0 ? 8 : bavg <= 16.0 ? 16 : bavg <= 32.0 ? 32 : 64;
+  const int64_t sym_g = SPG_SYM_SLOTS / (64 / lpr) / 2, num_g = SPG_NUM_SLOTS / (64 / lpr) / 2;
+  auto groups = [&](int l) { return (unsigned)(((int64_t)n + (int64_t)SPG_WAVES * (64 / l) - 1) / (SPG_WAVES * (64 / l))); };
   // symbolic: distinct columns per row
-  k_spgemm_sym_wave<<<wgrid, 64 * SPG_WAVES, 0, s>>>(n, b.m, a.rp, a.ci, b.rp, b.ci, ub.p, cnt.p, overflow.p);
+#define HBGS_SYM(L, LO, HI)                                                                                      \
+  k_spgemm_sym_grp<L><<<groups(L), 64 * SPG_WAVES, 0, s>>>(n, b.m, a.rp, a.ci, b.rp, b.ci, ub.p, LO, HI, cnt.p, \
+                                                           overflow.p)
+  switch (lpr) {
+    case 8: HBGS_SYM(8, -1, sym_g); break;
+    case 16: HBGS_SYM(16, -1, sym_g); break;
+    case 32: HBGS_SYM(32, -1, sym_g); break;
+    default: break;
+  }
+  HBGS_SYM(64, lpr < 64 ? sym_g : -1, SPG_SYM_SLOTS / 2);
+#undef HBGS_SYM
   k_spgemm_tsize_sym<<<grid_for(n, BLK), BLK, 0, s>>>(n, b.m, ub.p, ts.p);
   HBGS_HIP(hipGetLastError());
   std::vector<int64_t> h_off(n + 1);
@@ -1155,8 +1180,17 @@ void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
   c.ci = pool.make<int>(c.nnz);
   c.v = pool.make<double>(c.nnz);
   // numeric
-  k_spgemm_num_wave<<<wgrid, 64 * SPG_WAVES, 0, s>>>(n, a.rp, a.ci, a.v, b.rp, b.ci, b.v, c.rp, c.ci, c.v,
-                                                     overflow.p);
+#define HBGS_NUM(L, LO, HI)                                                                                  \
+  k_spgemm_num_grp<L><<<groups(L), 64 * SPG_WAVES, 0, s>>>(n, a.rp, a.ci, a.v, b.rp, b.ci, b.v, c.rp, LO, HI, c.ci, \
+                                                           c.v, overflow.p)
+  switch (lpr) {
+    case 8: HBGS_NUM(8, -1, num_g); break;
+    case 16: HBGS_NUM(16, -1, num_g); break;
+    case 32: HBGS_NUM(32, -1, num_g); break;
+    default: break;
+  }
+  HBGS_NUM(64, lpr < 64 ? num_g : -1, SPG_NUM_SLOTS / 2);
+#undef HBGS_NUM
   Tmp<int> nmid(1), mid(n);
   HBGS_HIP(hipMemsetAsync(nmid.p, 0, sizeof(int), s));
   k_spgemm_tsize_num<<<grid_for(n, BLK), BLK, 0, s>>>(n, c.rp, ts.p, nmid.p, mid.p);
