@@ -69,9 +69,11 @@ typedef struct {
   uint64_t seed;         /* salt of the aggregation priorities and start vectors */
   double theta[HBGS_MAX_FIELDS]; /* strength threshold per field (default 0.04 for
                                     field 0, 0 otherwise) */
-  int32_t use_graphs;    /* 1: replay each GMRES iteration as a captured HIP graph;
-                            0: launch kernels one by one (default; measured faster
-                            than graph replay on ROCm 7.2 for this kernel mix) */
+  int32_t use_graphs;    /* 1: replay each GMRES iteration as a HIP graph captured on
+                            its first use (per precision, direction and step; bitwise
+                            the eager result; not used by the nested form or while
+                            kernel timing is on).  A value update drops the graphs.
+                            0 (default): launch kernels one by one */
   int32_t setup_concurrent; /* 1 (default): the fields' blocks and hierarchies are
                                built concurrently, one host thread and HIP stream per
                                field (the results do not depend on it); 0: one after
