@@ -670,27 +670,70 @@ __global__ void k_pw_init(int n, uint64_t salt, double* w) {
     w[i] = 2.0 * ((double)(h >> 11) * 0x1.0p-53) - 1.0;
   }
 }
-// y = D^-1 B w, row sums in ascending column order; track max |y|
-__global__ void k_pw_apply(int n, const int* rp, const int* ci, const double* v, const double* d, const double* w,
-                           double* y, unsigned long long* amax) {
-  __shared__ unsigned long long sh[BLK];
+// y = D^-1 B w with every row summed in ascending column order; tracks max |y|.
+// w is win, or (amax_in set) win scaled by 2^-e with max|win| = f * 2^e,
+// f in [0.5, 1), as the power method normalises its iterate (zero if
+// max|win| = 0); the scaling is exact, so folding it into the gather gives
+// bitwise the products of the scaled vector.  A block takes PW_RB rows: its
+// threads stage the products of PW_CH consecutive entries at a time in LDS
+// with coalesced loads, then each row's thread adds its products in order.
+constexpr int PW_RB = 256;
+constexpr int PW_CH = 2048;
+__global__ __launch_bounds__(PW_RB) void k_pw_apply(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                    const double* __restrict__ v, const double* __restrict__ d,
+                                                    const double* __restrict__ win,
+                                                    const unsigned long long* amax_in, double* __restrict__ y,
+                                                    unsigned long long* amax) {
+  __shared__ double prod[PW_CH];
+  __shared__ unsigned long long sh[PW_RB / 64];
+  bool scaled = amax_in != nullptr, zero = false;
+  int e = 0;
+  if (scaled) {
+    const double mx = __longlong_as_double((long long)*amax_in);
+    if (mx > 0.0)
+      frexp(mx, &e);
+    else
+      zero = true;
+  }
   unsigned long long m = 0;
-  GRID_STRIDE(i, n) {
+  const int64_t nblk = ((int64_t)n + PW_RB - 1) / PW_RB;
+  for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
+    const int r0 = (int)(b * PW_RB), r1 = min(r0 + PW_RB, n);
+    const int i = r0 + (int)threadIdx.x;
+    const bool own = i < r1;
+    const int e0 = rp[r0], e1 = rp[r1];
+    const int my0 = own ? rp[i] : 0, my1 = own ? rp[i + 1] : 0;
     double s = 0.0;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) s += v[k] * w[ci[k]];
-    double yi = s / d[i];
-    y[i] = yi;
-    unsigned long long b = (unsigned long long)__double_as_longlong(fabs(yi));
-    m = b > m ? b : m;
+    for (int c0 = e0; c0 < e1; c0 += PW_CH) {
+      const int c1 = min(c0 + PW_CH, e1);
+      for (int k = c0 + (int)threadIdx.x; k < c1; k += PW_RB) {
+        double w = win[ci[k]];
+        if (scaled) w = zero ? 0.0 : ldexp(w, -e);
+        prod[k - c0] = v[k] * w;
+      }
+      __syncthreads();
+      const int a = max(my0, c0), z = min(my1, c1);
+      for (int k = a; k < z; ++k) s += prod[k - c0];
+      __syncthreads();
+    }
+    if (own) {
+      const double yi = s / d[i];
+      y[i] = yi;
+      const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(yi));
+      m = bits > m ? bits : m;
+    }
   }
-  sh[threadIdx.x] = m;
+  if (!amax) return;
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long o = __shfl_xor(m, off, 64);
+    m = o > m ? o : m;
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
   __syncthreads();
-  for (int st = BLK / 2; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) sh[threadIdx.x] = sh[threadIdx.x] > sh[threadIdx.x + st] ? sh[threadIdx.x]
-                                                                                          : sh[threadIdx.x + st];
-    __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < PW_RB / 64; ++q) m = sh[q] > m ? sh[q] : m;
+    atomicMax(amax, m);
   }
-  if (threadIdx.x == 0 && amax) atomicMax(amax, sh[0]);
 }
 // w = y * 2^-e with max|y| = f * 2^e, f in [0.5, 1)
 __global__ void k_pw_scale(int n, const double* y, const unsigned long long* amax, double* w) {
@@ -741,25 +784,39 @@ static double tree_dot(int64_t n, const double* x, const double* y, double* buf_
 double power_estimate(const DCsr& b, const double* d, int iters, uint64_t salt, hipStream_t s) {
   const int n = b.n;
   Tmp<double> w(n), y(n), pa((n + 255) / 256 + 1), pb((n + 255) / 256 + 1);
-  Tmp<unsigned long long> amax(1);
-  unsigned g = grid_for(n, BLK);
+  Tmp<unsigned long long> amax(iters > 0 ? iters : 1);
+  const unsigned g = grid_for(n, BLK);
+  const unsigned ga = grid_for(n, PW_RB);
   k_pw_init<<<g, BLK, 0, s>>>(n, salt, w.p);
   HBGS_HIP(hipGetLastError());
+  if (iters > 0) HBGS_HIP(hipMemsetAsync(amax.p, 0, sizeof(unsigned long long) * iters, s));
+  // iterate it reads the previous one scaled on the fly: w -> y -> w -> ...
+  double* buf[2] = {y.p, w.p};
   for (int it = 0; it < iters; ++it) {
-    HBGS_HIP(hipMemsetAsync(amax.p, 0, sizeof(unsigned long long), s));
-    k_pw_apply<<<g, BLK, 0, s>>>(n, b.rp, b.ci, b.v, d, w.p, y.p, amax.p);
-    k_pw_scale<<<g, BLK, 0, s>>>(n, y.p, amax.p, w.p);
+    k_pw_apply<<<ga, PW_RB, 0, s>>>(n, b.rp, b.ci, b.v, d, buf[(it + 1) & 1], it ? amax.p + it - 1 : nullptr,
+                                    buf[it & 1], amax.p + it);
     HBGS_HIP(hipGetLastError());
   }
-  unsigned long long mx = 0;
-  HBGS_HIP(hipMemcpyAsync(&mx, amax.p, sizeof(mx), hipMemcpyDeviceToHost, s));
-  HBGS_HIP(hipStreamSynchronize(s));
+  const double* wl = w.p;  // the normalised last iterate
   if (iters > 0) {
+    unsigned long long mx = 0;
+    HBGS_HIP(hipMemcpyAsync(&mx, amax.p + iters - 1, sizeof(mx), hipMemcpyDeviceToHost, s));
+    HBGS_HIP(hipStreamSynchronize(s));
     double m = 0.0;
     std::memcpy(&m, &mx, sizeof(m));
     if (m == 0.0) return 0.0;
+    double* last = buf[(iters - 1) & 1];
+    double* other = buf[iters & 1];
+    k_pw_scale<<<g, BLK, 0, s>>>(n, last, amax.p + iters - 1, other);
+    HBGS_HIP(hipGetLastError());
+    wl = other;
+    k_pw_apply<<<ga, PW_RB, 0, s>>>(n, b.rp, b.ci, b.v, d, other, nullptr, last, nullptr);
+    HBGS_HIP(hipGetLastError());
+    double wy = tree_dot(n, wl, last, pa.p, pb.p, s);
+    double ww = tree_dot(n, wl, wl, pa.p, pb.p, s);
+    return wy / ww;
   }
-  k_pw_apply<<<g, BLK, 0, s>>>(n, b.rp, b.ci, b.v, d, w.p, y.p, nullptr);
+  k_pw_apply<<<ga, PW_RB, 0, s>>>(n, b.rp, b.ci, b.v, d, w.p, nullptr, y.p, nullptr);
   HBGS_HIP(hipGetLastError());
   double wy = tree_dot(n, w.p, y.p, pa.p, pb.p, s);
   double ww = tree_dot(n, w.p, w.p, pa.p, pb.p, s);
@@ -859,12 +916,25 @@ constexpr int SPG_NUM_SLOTS = 1024;   // numeric: keys and values per wave (12 K
 constexpr int SPG_BLK_SLOTS = 4096;  // numeric, one block per row: keys and values (48 KB)
 // distinct columns of a product row are at most min(ub, columns of B)
 __device__ __forceinline__ int64_t sym_need(int64_t ub, int m) { return ub < m ? ub : (int64_t)m; }
-__device__ __forceinline__ bool sym_fits(int64_t need) { return 2 * need <= SPG_SYM_SLOTS; }
 __device__ __forceinline__ bool num_fits(int64_t cnt) { return 2 * cnt <= SPG_NUM_SLOTS; }
 __device__ __forceinline__ bool num_fits_block(int64_t cnt) { return 2 * cnt <= SPG_BLK_SLOTS; }
 
 // slot holding key c (claimed if absent); -1 if the table is full, which
-// the table sizes rule out (the caller reports it instead of looping)
+// the table sizes rule out (the caller reports it instead of looping);
+// lds_claim_bounded gives up after max_probes slots
+__device__ __forceinline__ int lds_claim_bounded(int* keys, uint32_t mask, int c, uint32_t max_probes, bool* fresh) {
+  uint32_t h = hslot(c, mask);
+  for (uint32_t probe = 0; probe < max_probes && probe <= mask; ++probe) {
+    int prev = atomicCAS(&keys[h], -1, c);
+    if (prev == -1 || prev == c) {
+      *fresh = prev == -1;
+      return (int)h;
+    }
+    h = (h + 1) & mask;
+  }
+  *fresh = false;
+  return -1;
+}
 __device__ __forceinline__ int lds_claim(int* keys, uint32_t mask, int c, bool* fresh) {
   uint32_t h = hslot(c, mask);
   for (uint32_t probe = 0; probe <= mask; ++probe) {
@@ -890,19 +960,26 @@ __device__ __forceinline__ int group_table(int64_t need) {  // power of two >= 2
   while (t < 2 * need) t <<= 1;
   return t;
 }
+// Rows too large for a table of 2 * need slots (big, taken only when
+// allow_big) get the group's whole table with probing bounded by
+// SPG_BIG_PROBES: the distinct count is usually far below the bound need,
+// and a row whose claims fail is marked (cnt = -1) for the global-table pass.
+constexpr uint32_t SPG_BIG_PROBES = 64;
 template <int LPR>
 __global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_sym_grp(int n, int bm, const int* arp, const int* aci,
                                                                   const int* brp, const int* bci, const int64_t* ub,
-                                                                  int64_t lo, int64_t hi, int* cnt, int* overflow) {
+                                                                  int64_t lo, int64_t hi, int allow_big, int* cnt,
+                                                                  int* overflow) {
   constexpr int G = 64 / LPR, SLOTS = SPG_SYM_SLOTS / G;
   __shared__ int tab[SPG_WAVES][SPG_SYM_SLOTS];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane / LPR, gl = lane % LPR;
   const int64_t i = ((int64_t)blockIdx.x * SPG_WAVES + wave) * G + grp;
   const int64_t need = i < n ? sym_need(ub[i], bm) : 0;
-  const bool active = i < n && need > lo && need <= hi && 2 * need <= SLOTS;
-  int u = 0;
+  const bool big = 2 * need > SLOTS;
+  const bool active = i < n && need > lo && need <= hi && (!big || allow_big);
+  int u = 0, failed = 0;
   if (active) {
-    const int T = group_table(need);
+    const int T = big ? SLOTS : group_table(need);
     int* keys = tab[wave] + grp * SLOTS;
     for (int q = gl; q < T; q += LPR) keys[q] = -1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -913,13 +990,20 @@ __global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_sym_grp(int n, int bm
       const int kk = aci[k];
       for (int q = brp[kk] + gl; q < brp[kk + 1]; q += LPR) {
         bool fresh;
-        if (lds_claim(keys, mask, bci[q], &fresh) < 0) atomicOr(overflow, 1);
+        if (big) {
+          if (lds_claim_bounded(keys, mask, bci[q], SPG_BIG_PROBES, &fresh) < 0) failed = 1;
+        } else if (lds_claim(keys, mask, bci[q], &fresh) < 0) {
+          atomicOr(overflow, 1);
+        }
         u += fresh;
       }
     }
   }
-  for (int off = LPR >> 1; off > 0; off >>= 1) u += __shfl_xor(u, off, LPR);
-  if (active && gl == 0) cnt[i] = u;
+  for (int off = LPR >> 1; off > 0; off >>= 1) {
+    u += __shfl_xor(u, off, LPR);
+    failed |= __shfl_xor(failed, off, LPR);
+  }
+  if (active && gl == 0) cnt[i] = failed ? -1 : u;
 }
 
 template <int LPR>
@@ -1049,12 +1133,9 @@ __global__ void k_spgemm_numeric(int r0, int r1, const int* arp, const int* aci,
     }
   }
 }
-// global table sizes of the rows the wave kernels leave over
-__global__ void k_spgemm_tsize_sym(int n, int bm, const int64_t* ub, int64_t* ts) {
-  GRID_STRIDE(i, n) {
-    const int64_t need = sym_need(ub[i], bm);
-    ts[i] = sym_fits(need) ? 0 : table_size(need);
-  }
+// global table sizes of the rows the group kernels marked (cnt < 0)
+__global__ void k_spgemm_tsize_sym(int n, int bm, const int64_t* ub, const int* cnt, int64_t* ts) {
+  GRID_STRIDE(i, n) ts[i] = cnt[i] < 0 ? table_size(sym_need(ub[i], bm)) : 0;
 }
 // rows for the one-block-per-row kernel are listed; rows beyond it get a
 // global table
@@ -1148,18 +1229,18 @@ void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
   const int64_t sym_g = SPG_SYM_SLOTS / (64 / lpr) / 2, num_g = SPG_NUM_SLOTS / (64 / lpr) / 2;
   auto groups = [&](int l) { return (unsigned)(((int64_t)n + (int64_t)SPG_WAVES * (64 / l) - 1) / (SPG_WAVES * (64 / l))); };
   // symbolic: distinct columns per row
-#define HBGS_SYM(L, LO, HI)                                                                                      \
-  k_spgemm_sym_grp<L><<<groups(L), 64 * SPG_WAVES, 0, s>>>(n, b.m, a.rp, a.ci, b.rp, b.ci, ub.p, LO, HI, cnt.p, \
-                                                           overflow.p)
+#define HBGS_SYM(L, LO, HI, BIG)                                                                               \
+  k_spgemm_sym_grp<L><<<groups(L), 64 * SPG_WAVES, 0, s>>>(n, b.m, a.rp, a.ci, b.rp, b.ci, ub.p, LO, HI, BIG, \
+                                                           cnt.p, overflow.p)
   switch (lpr) {
-    case 8: HBGS_SYM(8, -1, sym_g); break;
-    case 16: HBGS_SYM(16, -1, sym_g); break;
-    case 32: HBGS_SYM(32, -1, sym_g); break;
+    case 8: HBGS_SYM(8, -1, sym_g, 0); break;
+    case 16: HBGS_SYM(16, -1, sym_g, 0); break;
+    case 32: HBGS_SYM(32, -1, sym_g, 0); break;
     default: break;
   }
-  HBGS_SYM(64, lpr < 64 ? sym_g : -1, SPG_SYM_SLOTS / 2);
+  HBGS_SYM(64, lpr < 64 ? sym_g : -1, INT64_MAX, 1);
 #undef HBGS_SYM
-  k_spgemm_tsize_sym<<<grid_for(n, BLK), BLK, 0, s>>>(n, b.m, ub.p, ts.p);
+  k_spgemm_tsize_sym<<<grid_for(n, BLK), BLK, 0, s>>>(n, b.m, ub.p, cnt.p, ts.p);
   HBGS_HIP(hipGetLastError());
   std::vector<int64_t> h_off(n + 1);
   std::vector<int> cuts;
@@ -1769,47 +1850,61 @@ int ilu_setup(Pool& pool, const DCsr& a, int sub, IluLeaf& out, hipStream_t s) {
   return 0;
 }
 
-// per chunk of COL_CHUNK entries: smallest column, and whether the chunk's
-// columns span 65536 or more
-__global__ __launch_bounds__(COL_CHUNK) void k_col_base(int64_t nnz, const int* ci, int* cb, int* bad) {
-  __shared__ int smin[COL_CHUNK / 64], smax[COL_CHUNK / 64];
+// One wavefront per chunk of COL_CHUNK entries.  k_col_base: the chunk's
+// smallest column goes to cb; a chunk whose columns span 65536 or more sets
+// bad.  k_col_pack: every entry's offset from its chunk's base.
+static_assert(COL_CHUNK % 64 == 0, "chunks are whole wavefronts");
+constexpr int COL_PER_LANE = COL_CHUNK / 64;
+__global__ __launch_bounds__(256) void k_col_base(int64_t nnz, const int* __restrict__ ci, int* __restrict__ cb,
+                                                  int* bad) {
+  const int lane = threadIdx.x & 63;
   const int64_t nch = (nnz + COL_CHUNK - 1) / COL_CHUNK;
-  for (int64_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
-    const int64_t k = ch * COL_CHUNK + threadIdx.x;
+  for (int64_t ch = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); ch < nch; ch += (int64_t)gridDim.x * 4) {
+    const int64_t k0 = ch * COL_CHUNK + lane;
     int lo = INT32_MAX, hi = INT32_MIN;
-    if (k < nnz) lo = hi = ci[k];
+#pragma unroll
+    for (int q = 0; q < COL_PER_LANE; ++q) {
+      const int64_t k = k0 + q * 64;
+      if (k < nnz) {
+        const int c = ci[k];
+        lo = min(lo, c);
+        hi = max(hi, c);
+      }
+    }
     for (int off = 32; off > 0; off >>= 1) {
       lo = min(lo, __shfl_xor(lo, off, 64));
       hi = max(hi, __shfl_xor(hi, off, 64));
     }
-    if ((threadIdx.x & 63) == 0) {
-      smin[threadIdx.x >> 6] = lo;
-      smax[threadIdx.x >> 6] = hi;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int w = 1; w < COL_CHUNK / 64; ++w) {
-        lo = min(lo, smin[w]);
-        hi = max(hi, smax[w]);
-      }
+    if (lane == 0) {
       cb[ch] = lo;
       if ((int64_t)hi - (int64_t)lo > 65535) atomicOr(bad, 1);
     }
-    __syncthreads();
   }
 }
-__global__ void k_col_pack(int64_t nnz, const int* ci, const int* cb, uint16_t* cd) {
-  GRID_STRIDE(k, nnz) cd[k] = (uint16_t)(ci[k] - cb[k / COL_CHUNK]);
+__global__ __launch_bounds__(256) void k_col_pack(int64_t nnz, const int* __restrict__ ci,
+                                                  const int* __restrict__ cb, uint16_t* __restrict__ cd) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nch = (nnz + COL_CHUNK - 1) / COL_CHUNK;
+  for (int64_t ch = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); ch < nch; ch += (int64_t)gridDim.x * 4) {
+    const int base = cb[ch];
+    const int64_t k0 = ch * COL_CHUNK + lane;
+#pragma unroll
+    for (int q = 0; q < COL_PER_LANE; ++q) {
+      const int64_t k = k0 + q * 64;
+      if (k < nnz) cd[k] = (uint16_t)(ci[k] - base);
+    }
+  }
 }
 void pack_columns(Pool& pool, DCsr& a, hipStream_t s) {
   a.cd = nullptr;
   a.cb = nullptr;
   if (a.nnz == 0) return;
   const int64_t nch = (a.nnz + COL_CHUNK - 1) / COL_CHUNK;
+  const unsigned g = grid_for((nch + 3) / 4, 1);
   int* cb = pool.make<int>(nch);
   Tmp<int> bad(1);
   HBGS_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
-  k_col_base<<<grid_for(nch, 1, 65536), COL_CHUNK, 0, s>>>(a.nnz, a.ci, cb, bad.p);
+  k_col_base<<<g, 256, 0, s>>>(a.nnz, a.ci, cb, bad.p);
   HBGS_HIP(hipGetLastError());
   int h_bad = 0;
   HBGS_HIP(hipMemcpyAsync(&h_bad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1819,7 +1914,7 @@ void pack_columns(Pool& pool, DCsr& a, hipStream_t s) {
     return;
   }
   uint16_t* cd = pool.make<uint16_t>(a.nnz);
-  k_col_pack<<<grid_for(a.nnz, BLK), BLK, 0, s>>>(a.nnz, a.ci, cb, cd);
+  k_col_pack<<<g, 256, 0, s>>>(a.nnz, a.ci, cb, cd);
   HBGS_HIP(hipGetLastError());
   a.cd = cd;
   a.cb = cb;
