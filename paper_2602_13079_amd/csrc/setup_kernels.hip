@@ -4,8 +4,10 @@
 // by the sequential, rounded-product-then-add evaluation that the method's
 // definitions state (ascending column order within a row), so aggregates,
 // sparsity patterns and hierarchy values are reproducible bit for bit.
-// Parallelism comes from rows (one thread per row); only integer decisions
-// and order-independent max reductions use atomics.
+// Parallelism comes from rows: a row has one thread, or a group of lanes
+// that read its entries with coalesced loads and combine them with
+// cross-lane shuffles, adding order-dependent sums in entry order.  Only
+// integer decisions and order-independent max reductions use atomics.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,6 +40,78 @@ __device__ __forceinline__ uint64_t agg_key(int i, uint64_t salt) {
 
 #define GRID_STRIDE(i, n) \
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+// ------------------------------------------------------------- row groups
+// Rows of n handled by groups of L lanes (grid-stride over row groups); gl
+// is the lane's index in its group.  Every lane of a group runs the same
+// iterations, so the group's shuffles below always see their whole group.
+#define ROW_GROUPS(L, i, gl, n)                                                       \
+  const int gl = (int)(threadIdx.x % (L));                                             \
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / (L); i < (n); \
+       i += (int64_t)gridDim.x * blockDim.x / (L))
+
+template <int L, class T>
+__device__ __forceinline__ T grp_max(T x) {
+  for (int off = L >> 1; off > 0; off >>= 1) {
+    const T o = __shfl_xor(x, off, L);
+    x = o > x ? o : x;
+  }
+  return x;
+}
+template <int L, class T>
+__device__ __forceinline__ T grp_min(T x) {
+  for (int off = L >> 1; off > 0; off >>= 1) {
+    const T o = __shfl_xor(x, off, L);
+    x = o < x ? o : x;
+  }
+  return x;
+}
+template <int L>
+__device__ __forceinline__ int grp_sum(int x) {
+  for (int off = L >> 1; off > 0; off >>= 1) x += __shfl_xor(x, off, L);
+  return x;
+}
+// s + (the x of the group's lanes with take set, added one by one in lane
+// order): the sequential sum over a row's entries, L entries at a time
+template <int L>
+__device__ __forceinline__ double grp_ordered_add(double s, double x, bool take) {
+  const uint64_t b = __ballot(take);
+  const int lane = (int)(threadIdx.x & 63), base = lane & ~(L - 1);
+  uint64_t g = L == 64 ? b : (b >> base) & ((1ull << (L & 63)) - 1);
+  while (g) {  // the group's takers, lowest lane first
+    const int j = __builtin_ctzll(g);
+    s += __shfl(x, j, L);
+    g &= g - 1;
+  }
+  return s;
+}
+// number of lanes below this one in the group with pred set; *total: in the group
+template <int L>
+__device__ __forceinline__ int grp_rank(bool pred, int* total) {
+  const uint64_t b = __ballot(pred);
+  const int lane = (int)(threadIdx.x & 63), base = lane & ~(L - 1);
+  const uint64_t g = L == 64 ? b : (b >> base) & ((1ull << (L & 63)) - 1);
+  *total = __popcll(g);
+  return __popcll(g & ((1ull << (lane - base)) - 1));
+}
+
+// lanes per row from the mean row length
+static int row_lanes(int64_t n, int64_t nnz) {
+  const double avg = n ? (double)nnz / (double)n : 0.0;
+  return avg <= 7.5 ? 8 : avg <= 15.0 ? 16 : 32;
+}
+#define LAUNCH_ROW_GROUPS(kern, L, nrows, s, ...) LAUNCH_ROW_GROUPS_CAP(kern, L, nrows, 1 << 20, s, __VA_ARGS__)
+// cap: most blocks (kernels that end in one atomic per block use a small cap)
+#define LAUNCH_ROW_GROUPS_CAP(kern, L, nrows, cap, s, ...)            \
+  do {                                                                 \
+    const unsigned g_ = grid_for((int64_t)(nrows) * (L), BLK, cap);    \
+    switch (L) {                                                       \
+      case 8: kern<8><<<g_, BLK, 0, s>>>(__VA_ARGS__); break;          \
+      case 16: kern<16><<<g_, BLK, 0, s>>>(__VA_ARGS__); break;        \
+      default: kern<32><<<g_, BLK, 0, s>>>(__VA_ARGS__); break;        \
+    }                                                                  \
+    HBGS_HIP(hipGetLastError());                                       \
+  } while (0)
 
 // ------------------------------------------------------------------ scans
 // Exclusive scan in tiles of 1024: tile sums, scan of the tile sums
@@ -263,11 +337,12 @@ void scatter_values(int64_t nnz, const double* v, const int* pos, double* v_p, h
 __global__ void k_col_count(int64_t nnz, const int* ci, int* cnt) {
   GRID_STRIDE(k, nnz) atomicAdd(&cnt[ci[k]], 1);
 }
+template <int L>
 __global__ void k_transpose_scatter(int n, const int* rp, const int* ci, const double* v, int* cursor,
                                     int* tci, double* tv) {
-  GRID_STRIDE(i, n) {
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
-      int q = atomicAdd(&cursor[ci[k]], 1);
+  ROW_GROUPS(L, i, gl, n) {
+    for (int k = rp[i] + gl; k < rp[i + 1]; k += L) {
+      const int q = atomicAdd(&cursor[ci[k]], 1);
       tci[q] = (int)i;
       if (v) tv[q] = v[k];
     }
@@ -380,86 +455,100 @@ void transpose(const DCsr& a, DCsr& t, hipStream_t s) {
   HBGS_HIP(hipGetLastError());
   counts_to_rowptr(cnt.p, t.rp, a.m, s);
   HBGS_HIP(hipMemcpyAsync(cnt.p, t.rp, sizeof(int) * a.m, hipMemcpyDeviceToDevice, s));
-  k_transpose_scatter<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v, cnt.p, t.ci, t.v);
-  HBGS_HIP(hipGetLastError());
+  const int L = row_lanes(a.n, a.nnz);
+  LAUNCH_ROW_GROUPS(k_transpose_scatter, L, a.n, s, a.n, a.rp, a.ci, a.v, cnt.p, t.ci, t.v);
   sort_rows(t, s);
   HBGS_HIP(hipStreamSynchronize(s));
 }
 
 // ----------------------------------------------------------- block extract
+template <int L>
 __global__ void k_block_count(int r0, int r1, const int* rp, const int* ci, int c0, int c1, int* cnt) {
-  GRID_STRIDE(t, r1 - r0) {
-    int i = r0 + (int)t, c = 0;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) c += (ci[k] >= c0 && ci[k] < c1) ? 1 : 0;
-    cnt[t] = c;
+  const int64_t m = r1 - r0;
+  ROW_GROUPS(L, t, gl, m) {
+    const int i = r0 + (int)t;
+    int c = 0;
+    for (int k = rp[i] + gl; k < rp[i + 1]; k += L) c += (ci[k] >= c0 && ci[k] < c1) ? 1 : 0;
+    c = grp_sum<L>(c);
+    if (gl == 0) cnt[t] = c;
   }
 }
+template <int L>
 __global__ void k_block_fill(int r0, int r1, const int* rp, const int* ci, const double* v, int c0, int c1,
                              int coff, const int* rpo, int* cio, double* vo) {
-  GRID_STRIDE(t, r1 - r0) {
-    int i = r0 + (int)t, q = rpo[t];
-    for (int k = rp[i]; k < rp[i + 1]; ++k)
-      if (ci[k] >= c0 && ci[k] < c1) {
-        cio[q] = ci[k] - coff;
-        vo[q] = v[k];
-        ++q;
+  const int64_t m = r1 - r0;
+  ROW_GROUPS(L, t, gl, m) {
+    const int i = r0 + (int)t, e = rp[i + 1];
+    int q = rpo[t];
+    for (int b = rp[i]; b < e; b += L) {
+      const int k = b + gl;
+      const int c = k < e ? ci[k] : -1;
+      const bool keep = k < e && c >= c0 && c < c1;
+      int tot;
+      const int r = grp_rank<L>(keep, &tot);
+      if (keep) {
+        cio[q + r] = c - coff;
+        vo[q + r] = v[k];
       }
+      q += tot;
+    }
   }
 }
 void block_count(const DCsr& a, int r0, int r1, int c0, int c1, int* cnt, hipStream_t s) {
-  k_block_count<<<grid_for(r1 - r0, BLK), BLK, 0, s>>>(r0, r1, a.rp, a.ci, c0, c1, cnt);
-  HBGS_HIP(hipGetLastError());
+  const int L = row_lanes(a.n, a.nnz);
+  LAUNCH_ROW_GROUPS(k_block_count, L, r1 - r0, s, r0, r1, a.rp, a.ci, c0, c1, cnt);
 }
 void block_fill(const DCsr& a, int r0, int r1, int c0, int c1, int coff, const int* rp_out, int* ci_out,
                 double* v_out, hipStream_t s) {
-  k_block_fill<<<grid_for(r1 - r0, BLK), BLK, 0, s>>>(r0, r1, a.rp, a.ci, a.v, c0, c1, coff, rp_out, ci_out,
-                                                         v_out);
-  HBGS_HIP(hipGetLastError());
+  const int L = row_lanes(a.n, a.nnz);
+  LAUNCH_ROW_GROUPS(k_block_fill, L, r1 - r0, s, r0, r1, a.rp, a.ci, a.v, c0, c1, coff, rp_out, ci_out, v_out);
 }
 
 // ---------------------------------------------------------------- strength
+template <int L>
 __global__ void k_diagonal(int n, const int* rp, const int* ci, const double* v, double* d, int* missing) {
-  GRID_STRIDE(i, n) {
-    double x = 0.0;
-    bool found = false;
-    for (int k = rp[i]; k < rp[i + 1]; ++k)
-      if (ci[k] == i) {
-        x = v[k];
-        found = true;
-      }
-    d[i] = x;
-    if (!found || x == 0.0) atomicOr(missing, 1);
+  ROW_GROUPS(L, i, gl, n) {
+    int pos = -1;
+    for (int k = rp[i] + gl; k < rp[i + 1]; k += L)
+      if (ci[k] == (int)i) pos = k;
+    pos = grp_max<L>(pos);
+    if (gl == 0) {
+      const double x = pos >= 0 ? v[pos] : 0.0;
+      d[i] = x;
+      if (pos < 0 || x == 0.0) atomicOr(missing, 1);
+    }
   }
 }
 void diagonal(const DCsr& a, double* d, int* missing, hipStream_t s) {
-  k_diagonal<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v, d, missing);
-  HBGS_HIP(hipGetLastError());
+  const int L = row_lanes(a.n, a.nnz);
+  LAUNCH_ROW_GROUPS(k_diagonal, L, a.n, s, a.n, a.rp, a.ci, a.v, d, missing);
 }
 
 // (i,j) strong: a_ij*a_ij >= (theta^2 |a_ii|) |a_jj|, or the same test on the
 // transposed entry (j,i); rows with no off-diagonal entry are excluded
+template <int L>
 __global__ void k_strength(int n, const int* rp, const int* ci, const double* v, const double* d, double th2,
                            char* strong, char* excluded) {
-  GRID_STRIDE(i, n) {
-    bool offd = false;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
-      int j = ci[k];
-      if (j == i) {
+  ROW_GROUPS(L, i, gl, n) {
+    int offd = 0;
+    for (int k = rp[i] + gl; k < rp[i + 1]; k += L) {
+      const int j = ci[k];
+      if (j == (int)i) {
         strong[k] = 0;
         continue;
       }
-      offd = true;
+      offd = 1;
       bool st = v[k] * v[k] >= (th2 * fabs(d[i])) * fabs(d[j]);
       if (!st) {
         int lo = rp[j], hi = rp[j + 1] - 1;
         while (lo <= hi) {
-          int mid = (lo + hi) >> 1;
-          int cm = ci[mid];
-          if (cm == i) {
+          const int mid = (lo + hi) >> 1;
+          const int cm = ci[mid];
+          if (cm == (int)i) {
             st = v[mid] * v[mid] >= (th2 * fabs(d[j])) * fabs(d[i]);
             break;
           }
-          if (cm < i)
+          if (cm < (int)i)
             lo = mid + 1;
           else
             hi = mid - 1;
@@ -467,12 +556,13 @@ __global__ void k_strength(int n, const int* rp, const int* ci, const double* v,
       }
       strong[k] = st ? 1 : 0;
     }
-    excluded[i] = offd ? 0 : 1;
+    offd = grp_max<L>(offd);
+    if (gl == 0) excluded[i] = offd ? 0 : 1;
   }
 }
 void strength(const DCsr& a, const double* d, double theta, char* strong, char* excluded, hipStream_t s) {
-  k_strength<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v, d, theta * theta, strong, excluded);
-  HBGS_HIP(hipGetLastError());
+  const int L = row_lanes(a.n, a.nnz);
+  LAUNCH_ROW_GROUPS(k_strength, L, a.n, s, a.n, a.rp, a.ci, a.v, d, theta * theta, strong, excluded);
 }
 
 // ---------------------------------------------------------------- MIS-2
@@ -484,54 +574,72 @@ void strength(const DCsr& a, const double* d, double theta, char* strong, char* 
 __global__ void k_mis2_init(int n, const char* excluded, char* state) {
   GRID_STRIDE(i, n) state[i] = excluded[i] ? 3 : 0;
 }
+template <int L>
 __global__ void k_mis2_max1(int n, const int* rp, const int* ci, const char* strong, uint64_t salt,
                             const char* state, uint64_t* m1) {
-  GRID_STRIDE(i, n) {
-    uint64_t m = state[i] == 0 ? agg_key((int)i, salt) : 0;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
+  ROW_GROUPS(L, i, gl, n) {
+    uint64_t m = (gl == 0 && state[i] == 0) ? agg_key((int)i, salt) : 0;
+    for (int k = rp[i] + gl; k < rp[i + 1]; k += L) {
       if (!strong[k]) continue;
-      int j = ci[k];
+      const int j = ci[k];
       if (state[j] == 0) {
-        uint64_t kj = agg_key(j, salt);
+        const uint64_t kj = agg_key(j, salt);
         m = kj > m ? kj : m;
       }
     }
-    m1[i] = m;
+    m = grp_max<L>(m);
+    if (gl == 0) m1[i] = m;
   }
 }
+template <int L>
 __global__ void k_mis2_max2(int n, const int* rp, const int* ci, const char* strong, uint64_t salt,
                             const uint64_t* m1, char* state) {
-  GRID_STRIDE(i, n) {
+  ROW_GROUPS(L, i, gl, n) {
     if (state[i] != 0) continue;
     uint64_t m = m1[i];
-    for (int k = rp[i]; k < rp[i + 1]; ++k)
+    for (int k = rp[i] + gl; k < rp[i + 1]; k += L)
       if (strong[k]) m = m1[ci[k]] > m ? m1[ci[k]] : m;
-    if (m == agg_key((int)i, salt)) state[i] = 1;
+    m = grp_max<L>(m);
+    if (gl == 0 && m == agg_key((int)i, salt)) state[i] = 1;
   }
 }
+template <int L>
 __global__ void k_mis2_near1(int n, const int* rp, const int* ci, const char* strong, const char* state,
                              char* r1) {
-  GRID_STRIDE(i, n) {
-    char r = state[i] == 1;
-    for (int k = rp[i]; k < rp[i + 1]; ++k)
+  ROW_GROUPS(L, i, gl, n) {
+    int r = state[i] == 1;
+    for (int k = rp[i] + gl; k < rp[i + 1]; k += L)
       if (strong[k] && state[ci[k]] == 1) r = 1;
-    r1[i] = r;
+    r = grp_max<L>(r);
+    if (gl == 0) r1[i] = (char)r;
   }
 }
+template <int L>
 __global__ void k_mis2_near2(int n, const int* rp, const int* ci, const char* strong, const char* r1,
                              char* state, int* undecided) {
   int local = 0;
-  GRID_STRIDE(i, n) {
+  ROW_GROUPS(L, i, gl, n) {
     if (state[i] != 0) continue;
-    bool out = r1[i];
-    for (int k = rp[i]; k < rp[i + 1] && !out; ++k)
-      if (strong[k] && r1[ci[k]]) out = true;
-    if (out)
-      state[i] = 2;
-    else
-      ++local;
+    int out = r1[i];
+    for (int k = rp[i] + gl; k < rp[i + 1] && !out; k += L)
+      if (strong[k] && r1[ci[k]]) out = 1;
+    out = grp_max<L>(out);
+    if (gl == 0) {
+      if (out)
+        state[i] = 2;
+      else
+        ++local;
+    }
   }
-  if (local) atomicAdd(undecided, local);
+  // one atomic per block (the grid is capped, so there are few)
+  __shared__ int red[BLK / 64];
+  for (int off = 32; off > 0; off >>= 1) local += __shfl_xor(local, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = local;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < BLK / 64; ++w) local += red[w];
+    if (local) atomicAdd(undecided, local);
+  }
 }
 
 void mis2_init(int n, const char* excluded, char* state, hipStream_t s) {
@@ -541,13 +649,12 @@ void mis2_init(int n, const char* excluded, char* state, hipStream_t s) {
 
 void mis2_round(const DCsr& a, const char* strong, uint64_t salt, char* state, uint64_t* m1, char* r1,
                 int* undecided, hipStream_t s) {
-  unsigned g = grid_for(a.n, BLK);
-  k_mis2_max1<<<g, BLK, 0, s>>>(a.n, a.rp, a.ci, strong, salt, state, m1);
-  k_mis2_max2<<<g, BLK, 0, s>>>(a.n, a.rp, a.ci, strong, salt, m1, state);
-  k_mis2_near1<<<g, BLK, 0, s>>>(a.n, a.rp, a.ci, strong, state, r1);
+  const int L = row_lanes(a.n, a.nnz);
+  LAUNCH_ROW_GROUPS(k_mis2_max1, L, a.n, s, a.n, a.rp, a.ci, strong, salt, state, m1);
+  LAUNCH_ROW_GROUPS(k_mis2_max2, L, a.n, s, a.n, a.rp, a.ci, strong, salt, m1, state);
+  LAUNCH_ROW_GROUPS(k_mis2_near1, L, a.n, s, a.n, a.rp, a.ci, strong, state, r1);
   HBGS_HIP(hipMemsetAsync(undecided, 0, sizeof(int), s));
-  k_mis2_near2<<<g, BLK, 0, s>>>(a.n, a.rp, a.ci, strong, r1, state, undecided);
-  HBGS_HIP(hipGetLastError());
+  LAUNCH_ROW_GROUPS_CAP(k_mis2_near2, L, a.n, 2048, s, a.n, a.rp, a.ci, strong, r1, state, undecided);
 }
 
 __global__ void k_agg_roots(int n, const char* state, int* flag) {
@@ -561,43 +668,51 @@ void agg_roots(int n, const char* state, int* flag, hipStream_t s) {
 // phase 1: a row next to a root joins it (the root is unique: roots are at
 // least 3 apart); phase 2: other rows join the phase-1 neighbour of largest
 // key; rows left over are flagged for phase 3
+template <int L>
 __global__ void k_agg_phase1(int n, const int* rp, const int* ci, const char* strong, const char* state,
                              const int64_t* root_rank, int* p1) {
-  GRID_STRIDE(i, n) {
+  ROW_GROUPS(L, i, gl, n) {
     int a = -1;
     if (state[i] == 1) {
       a = (int)root_rank[i];
     } else if (state[i] != 3) {
-      for (int k = rp[i]; k < rp[i + 1]; ++k)
+      for (int k = rp[i] + gl; k < rp[i + 1]; k += L)
         if (strong[k] && state[ci[k]] == 1) a = (int)root_rank[ci[k]];
+      a = grp_max<L>(a);
     }
-    p1[i] = a;
+    if (gl == 0) p1[i] = a;
   }
 }
+// the phase-1 neighbour of largest key (keys are distinct, so the maximum
+// is the row's unique choice)
+template <int L>
 __global__ void k_agg_phase2(int n, const int* rp, const int* ci, const char* strong, uint64_t salt,
                              const char* state, const int* p1, int* agg, int* single_flag) {
-  GRID_STRIDE(i, n) {
+  ROW_GROUPS(L, i, gl, n) {
     int a = p1[i];
     int single = 0;
     if (state[i] != 3 && a < 0) {
       uint64_t best = 0;
-      int besta = -1;
-      for (int k = rp[i]; k < rp[i + 1]; ++k) {
+      int bestu = -1;
+      for (int k = rp[i] + gl; k < rp[i + 1]; k += L) {
         if (!strong[k]) continue;
-        int u = ci[k];
+        const int u = ci[k];
         if (p1[u] >= 0 && state[u] != 1) {
-          uint64_t ku = agg_key(u, salt);
-          if (besta < 0 || ku > best) {
+          const uint64_t ku = agg_key(u, salt);
+          if (bestu < 0 || ku > best) {
             best = ku;
-            besta = p1[u];
+            bestu = u;
           }
         }
       }
-      a = besta;
-      single = besta < 0 ? 1 : 0;
+      const uint64_t top = grp_max<L>(bestu < 0 ? 0ull : best + 1);  // 0: no candidate
+      a = top ? p1[(int)(uint32_t)((top - 1) & 0xffffffffull)] : -1;
+      single = top ? 0 : 1;
     }
-    agg[i] = a;
-    single_flag[i] = single;
+    if (gl == 0) {
+      agg[i] = a;
+      single_flag[i] = single;
+    }
   }
 }
 __global__ void k_agg_phase3(int n, const int* single_flag, const int64_t* single_rank, int nroot, int* agg) {
@@ -607,10 +722,9 @@ __global__ void k_agg_phase3(int n, const int* single_flag, const int64_t* singl
 void agg_phase12(const DCsr& a, const char* strong, uint64_t salt, const char* state, const int64_t* root_rank,
                  int* agg, int* single_flag, hipStream_t s) {
   Tmp<int> p1(a.n);
-  unsigned g = grid_for(a.n, BLK);
-  k_agg_phase1<<<g, BLK, 0, s>>>(a.n, a.rp, a.ci, strong, state, root_rank, p1.p);
-  k_agg_phase2<<<g, BLK, 0, s>>>(a.n, a.rp, a.ci, strong, salt, state, p1.p, agg, single_flag);
-  HBGS_HIP(hipGetLastError());
+  const int L = row_lanes(a.n, a.nnz);
+  LAUNCH_ROW_GROUPS(k_agg_phase1, L, a.n, s, a.n, a.rp, a.ci, strong, state, root_rank, p1.p);
+  LAUNCH_ROW_GROUPS(k_agg_phase2, L, a.n, s, a.n, a.rp, a.ci, strong, salt, state, p1.p, agg, single_flag);
   HBGS_HIP(hipStreamSynchronize(s));
 }
 void agg_phase3(int n, const int* single_flag, const int64_t* single_rank, int nroot, int* agg, hipStream_t s) {
@@ -621,46 +735,59 @@ void agg_phase3(int n, const int* single_flag, const int64_t* single_rank, int n
 // ------------------------------------------------------------------ filter
 // A_F: strong off-diagonal entries kept, dropped entries added to the
 // diagonal in ascending column order; D_abs = sum |A_F| along the row
+template <int L>
 __global__ void k_filter_count(int n, const int* rp, const int* ci, const char* strong, int* cnt) {
-  GRID_STRIDE(i, n) {
+  ROW_GROUPS(L, i, gl, n) {
     int c = 0;
-    for (int k = rp[i]; k < rp[i + 1]; ++k) c += (ci[k] == i || strong[k]) ? 1 : 0;
-    cnt[i] = c;
+    for (int k = rp[i] + gl; k < rp[i + 1]; k += L) c += (ci[k] == (int)i || strong[k]) ? 1 : 0;
+    c = grp_sum<L>(c);
+    if (gl == 0) cnt[i] = c;
   }
 }
+template <int L>
 __global__ void k_filter_fill(int n, const int* rp, const int* ci, const double* v, const char* strong,
                               const int* rpf, int* cif, double* vf, double* dabs) {
-  GRID_STRIDE(i, n) {
-    double d = 0.0;
-    for (int k = rp[i]; k < rp[i + 1]; ++k)
-      if (ci[k] == i) d = v[k];
-    for (int k = rp[i]; k < rp[i + 1]; ++k)
-      if (ci[k] != i && !strong[k]) d += v[k];
-    int q = rpf[i];
-    for (int k = rp[i]; k < rp[i + 1]; ++k) {
-      if (ci[k] == i) {
-        cif[q] = (int)i;
-        vf[q] = d;
-        ++q;
-      } else if (strong[k]) {
-        cif[q] = ci[k];
-        vf[q] = v[k];
-        ++q;
-      }
+  ROW_GROUPS(L, i, gl, n) {
+    const int s = rp[i], e = rp[i + 1];
+    int pos = -1;
+    for (int k = s + gl; k < e; k += L)
+      if (ci[k] == (int)i) pos = k;
+    pos = grp_max<L>(pos);
+    // diagonal of A_F: a_ii, then the dropped entries in column order
+    double d = pos >= 0 ? v[pos] : 0.0;
+    for (int b = s; b < e; b += L) {
+      const int k = b + gl;
+      const bool drop = k < e && ci[k] != (int)i && !strong[k];
+      d = grp_ordered_add<L>(d, drop ? v[k] : 0.0, drop);
     }
+    int q = rpf[i];
     double sa = 0.0;
-    for (int k = rpf[i]; k < q; ++k) sa += fabs(vf[k]);
-    dabs[i] = sa;
+    for (int b = s; b < e; b += L) {
+      const int k = b + gl;
+      const int c = k < e ? ci[k] : -1;
+      const bool diag = c == (int)i;
+      const bool keep = k < e && (diag || strong[k]);
+      const double x = keep ? (diag ? d : v[k]) : 0.0;
+      int tot;
+      const int r = grp_rank<L>(keep, &tot);
+      if (keep) {
+        cif[q + r] = c;
+        vf[q + r] = x;
+      }
+      q += tot;
+      sa = grp_ordered_add<L>(sa, fabs(x), keep);
+    }
+    if (gl == 0) dabs[i] = sa;
   }
 }
 void filter_count(const DCsr& a, const char* strong, int* cnt, hipStream_t s) {
-  k_filter_count<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, strong, cnt);
-  HBGS_HIP(hipGetLastError());
+  const int L = row_lanes(a.n, a.nnz);
+  LAUNCH_ROW_GROUPS(k_filter_count, L, a.n, s, a.n, a.rp, a.ci, strong, cnt);
 }
 void filter_fill(const DCsr& a, const char* strong, const int* rp_f, int* ci_f, double* v_f, double* dabs,
                  hipStream_t s) {
-  k_filter_fill<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v, strong, rp_f, ci_f, v_f, dabs);
-  HBGS_HIP(hipGetLastError());
+  const int L = row_lanes(a.n, a.nnz);
+  LAUNCH_ROW_GROUPS(k_filter_fill, L, a.n, s, a.n, a.rp, a.ci, a.v, strong, rp_f, ci_f, v_f, dabs);
 }
 
 // ------------------------------------------------------------ power method
@@ -786,7 +913,9 @@ double power_estimate(const DCsr& b, const double* d, int iters, uint64_t salt, 
   Tmp<double> w(n), y(n), pa((n + 255) / 256 + 1), pb((n + 255) / 256 + 1);
   Tmp<unsigned long long> amax(iters > 0 ? iters : 1);
   const unsigned g = grid_for(n, BLK);
-  const unsigned ga = grid_for(n, PW_RB);
+  // one block per CU slot (8 per CU): each block ends in one atomicMax on a
+  // single address, so the grid stays small and strides over the row blocks
+  const unsigned ga = grid_for(n, PW_RB, 2048);
   k_pw_init<<<g, BLK, 0, s>>>(n, salt, w.p);
   HBGS_HIP(hipGetLastError());
   if (iters > 0) HBGS_HIP(hipMemsetAsync(amax.p, 0, sizeof(unsigned long long) * iters, s));
@@ -827,59 +956,74 @@ double power_estimate(const DCsr& b, const double* d, int iters, uint64_t salt, 
 // Row i of P = P_tent - omega D_abs^-1 A_F P_tent: its columns are the
 // aggregates met along row i of A_F (ascending); entry c is
 // [agg(i)==c] - (omega / D_abs_i) * sum_{k: agg(k)==c} a_F(i,k).
+template <int L>
 __global__ void k_psmooth_count(int n, const int* rp, const int* ci, const int* agg, int* cnt) {
-  GRID_STRIDE(i, n) {
+  ROW_GROUPS(L, i, gl, n) {
     int c = 0;
     if (agg[i] >= 0) {
+      const int s = rp[i], e = rp[i + 1];
       int prev = -1;
       for (;;) {
         int next = INT32_MAX;
-        for (int k = rp[i]; k < rp[i + 1]; ++k) {
-          int a = agg[ci[k]];
+        for (int k = s + gl; k < e; k += L) {
+          const int a = agg[ci[k]];
           if (a > prev && a < next) next = a;
         }
+        next = grp_min<L>(next);
         if (next == INT32_MAX) break;
         ++c;
         prev = next;
       }
     }
-    cnt[i] = c;
+    if (gl == 0) cnt[i] = c;
   }
 }
+template <int L>
 __global__ void k_psmooth_fill(int n, const int* rp, const int* ci, const double* v, const int* agg,
                                const double* dabs, double omega, const int* rpp, int* cip, double* vp) {
-  GRID_STRIDE(i, n) {
-    if (agg[i] < 0) continue;
-    double q = omega / dabs[i];
+  ROW_GROUPS(L, i, gl, n) {
+    const int ai = agg[i];
+    if (ai < 0) continue;
+    const double q = omega / dabs[i];
+    const int s = rp[i], e = rp[i + 1];
     int o = rpp[i];
-    int prev = -1;
-    for (;;) {
-      int next = INT32_MAX;
-      for (int k = rp[i]; k < rp[i + 1]; ++k) {
-        int a = agg[ci[k]];
-        if (a > prev && a < next) next = a;
-      }
-      if (next == INT32_MAX) break;
+    int cur = INT32_MAX;
+    for (int k = s + gl; k < e; k += L) {
+      const int a = agg[ci[k]];
+      if (a >= 0 && a < cur) cur = a;
+    }
+    cur = grp_min<L>(cur);
+    // one pass per aggregate met: its entries summed in column order, and
+    // the next larger aggregate
+    while (cur != INT32_MAX) {
       double sum = 0.0;
-      for (int k = rp[i]; k < rp[i + 1]; ++k)
-        if (agg[ci[k]] == next) sum += v[k];
-      double t = agg[i] == next ? 1.0 : 0.0;
-      cip[o] = next;
-      vp[o] = t - q * sum;
+      int next = INT32_MAX;
+      for (int b = s; b < e; b += L) {
+        const int k = b + gl;
+        const int a = k < e ? agg[ci[k]] : -1;
+        const bool hit = a == cur;
+        sum = grp_ordered_add<L>(sum, hit ? v[k] : 0.0, hit);
+        if (a > cur && a < next) next = a;
+      }
+      next = grp_min<L>(next);
+      if (gl == 0) {
+        const double tent = ai == cur ? 1.0 : 0.0;
+        cip[o] = cur;
+        vp[o] = tent - q * sum;
+      }
       ++o;
-      prev = next;
+      cur = next;
     }
   }
 }
 void psmooth_count(const DCsr& af, const int* agg, int* cnt, hipStream_t s) {
-  k_psmooth_count<<<grid_for(af.n, BLK), BLK, 0, s>>>(af.n, af.rp, af.ci, agg, cnt);
-  HBGS_HIP(hipGetLastError());
+  const int L = row_lanes(af.n, af.nnz);
+  LAUNCH_ROW_GROUPS(k_psmooth_count, L, af.n, s, af.n, af.rp, af.ci, agg, cnt);
 }
 void psmooth_fill(const DCsr& af, const int* agg, const double* dabs, double omega, const int* rp_p, int* ci_p,
                   double* v_p, hipStream_t s) {
-  k_psmooth_fill<<<grid_for(af.n, BLK), BLK, 0, s>>>(af.n, af.rp, af.ci, af.v, agg, dabs, omega, rp_p, ci_p,
-                                                       v_p);
-  HBGS_HIP(hipGetLastError());
+  const int L = row_lanes(af.n, af.nnz);
+  LAUNCH_ROW_GROUPS(k_psmooth_fill, L, af.n, s, af.n, af.rp, af.ci, af.v, agg, dabs, omega, rp_p, ci_p, v_p);
 }
 
 // ------------------------------------------------------------------ SpGEMM
@@ -911,8 +1055,8 @@ __host__ __device__ __forceinline__ int64_t table_size(int64_t ub) {
 __device__ __forceinline__ uint32_t hslot(int c, uint32_t mask) { return ((uint32_t)c * 2654435761u) & mask; }
 
 constexpr int SPG_WAVES = 4;          // rows (waves) per block
-constexpr int SPG_SYM_SLOTS = 4096;   // symbolic: keys per wave (16 KB)
-constexpr int SPG_NUM_SLOTS = 1024;   // numeric: keys and values per wave (12 KB)
+constexpr int SPG_SYM_SLOTS = 1024;   // symbolic: keys per wave (4 KB: 8 blocks of 4 waves per CU)
+constexpr int SPG_NUM_SLOTS = 512;    // numeric: keys and values per wave (6 KB: 6 blocks per CU)
 constexpr int SPG_BLK_SLOTS = 4096;  // numeric, one block per row: keys and values (48 KB)
 // distinct columns of a product row are at most min(ub, columns of B)
 __device__ __forceinline__ int64_t sym_need(int64_t ub, int m) { return ub < m ? ub : (int64_t)m; }
@@ -1045,15 +1189,32 @@ __global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_num_grp(int n, const 
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  // each occupied slot goes to its rank among the row's columns
-  for (int q = gl; q < T; q += LPR) {
-    const int c = keys[q];
-    if (c < 0) continue;
-    int rank = 0;
-    for (int p = 0; p < T; ++p) {
-      const int d = keys[p];
-      rank += (d >= 0) & (d < c);
+  // Compact the occupied slots to the front of the table, LPR slots at a
+  // time (a round's slots are read before its writes, which land at or
+  // before them), then each entry goes to its rank among the row's columns.
+  int m = 0;
+  for (int q0 = 0; q0 < T; q0 += LPR) {
+    const bool in = q0 + gl < T;  // T < LPR for short rows of the wide groups
+    const int c = in ? keys[q0 + gl] : -1;
+    const double x = in ? vals[q0 + gl] : 0.0;
+    int tot;
+    const int r = grp_rank<LPR>(c >= 0, &tot);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (c >= 0) {
+      keys[m + r] = c;
+      vals[m + r] = x;
     }
+    m += tot;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int q = gl; q < m; q += LPR) {
+    const int c = keys[q];
+    int rank = 0;
+    for (int p = 0; p < m; ++p) rank += keys[p] < c;
     cci[o + rank] = c;
     cv[o + rank] = vals[q];
   }
@@ -1658,15 +1819,16 @@ int dense_inverse(const DCsr& a, double* inv, hipStream_t s) {
 // --------------------------------------------- transposes for the solve phase
 // (A^T)_{ji} = A_{ij}: for a structurally symmetric A the pattern is A's own;
 // each entry's value is found in the mirrored row by binary search
+template <int L>
 __global__ void k_transpose_sym(int n, const int* __restrict__ rp, const int* __restrict__ ci,
                                 const double* __restrict__ v, double* __restrict__ vt) {
-  GRID_STRIDE(j, n) {
-    for (int q = rp[j]; q < rp[j + 1]; ++q) {
-      int i = ci[q];
+  ROW_GROUPS(L, j, gl, n) {
+    for (int q = rp[j] + gl; q < rp[j + 1]; q += L) {
+      const int i = ci[q];
       int lo = rp[i], hi = rp[i + 1] - 1;
       double x = 0.0;
       while (lo <= hi) {
-        int mid = (lo + hi) >> 1;
+        const int mid = (lo + hi) >> 1;
         if (ci[mid] == (int)j) {
           x = v[mid];
           break;
@@ -1681,8 +1843,8 @@ __global__ void k_transpose_sym(int n, const int* __restrict__ rp, const int* __
   }
 }
 void transpose_symmetric(const DCsr& a, double* vt, hipStream_t s) {
-  k_transpose_sym<<<grid_for(a.n, BLK), BLK, 0, s>>>(a.n, a.rp, a.ci, a.v, vt);
-  HBGS_HIP(hipGetLastError());
+  const int L = row_lanes(a.n, a.nnz);
+  LAUNCH_ROW_GROUPS(k_transpose_sym, L, a.n, s, a.n, a.rp, a.ci, a.v, vt);
 }
 
 __global__ void k_max_row(int n, const int* __restrict__ rp, int* __restrict__ maxlen) {
@@ -1859,7 +2021,9 @@ __global__ __launch_bounds__(256) void k_col_base(int64_t nnz, const int* __rest
                                                   int* bad) {
   const int lane = threadIdx.x & 63;
   const int64_t nch = (nnz + COL_CHUNK - 1) / COL_CHUNK;
+  int wide = 0;
   for (int64_t ch = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); ch < nch; ch += (int64_t)gridDim.x * 4) {
+    if (*(volatile int*)bad) break;  // another wave already found a wide chunk
     const int64_t k0 = ch * COL_CHUNK + lane;
     int lo = INT32_MAX, hi = INT32_MIN;
 #pragma unroll
@@ -1875,11 +2039,13 @@ __global__ __launch_bounds__(256) void k_col_base(int64_t nnz, const int* __rest
       lo = min(lo, __shfl_xor(lo, off, 64));
       hi = max(hi, __shfl_xor(hi, off, 64));
     }
-    if (lane == 0) {
-      cb[ch] = lo;
-      if ((int64_t)hi - (int64_t)lo > 65535) atomicOr(bad, 1);
+    if (lane == 0) cb[ch] = lo;
+    if ((int64_t)hi - (int64_t)lo > 65535) {
+      wide = 1;
+      break;
     }
   }
+  if (lane == 0 && wide) atomicOr(bad, 1);
 }
 __global__ __launch_bounds__(256) void k_col_pack(int64_t nnz, const int* __restrict__ ci,
                                                   const int* __restrict__ cb, uint16_t* __restrict__ cd) {
@@ -1904,7 +2070,7 @@ void pack_columns(Pool& pool, DCsr& a, hipStream_t s) {
   int* cb = pool.make<int>(nch);
   Tmp<int> bad(1);
   HBGS_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
-  k_col_base<<<g, 256, 0, s>>>(a.nnz, a.ci, cb, bad.p);
+  k_col_base<<<grid_for((nch + 3) / 4, 1, 8192), 256, 0, s>>>(a.nnz, a.ci, cb, bad.p);
   HBGS_HIP(hipGetLastError());
   int h_bad = 0;
   HBGS_HIP(hipMemcpyAsync(&h_bad, bad.p, sizeof(int), hipMemcpyDeviceToHost, s));
