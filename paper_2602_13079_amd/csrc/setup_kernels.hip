@@ -1095,35 +1095,31 @@ __device__ __forceinline__ int lds_claim(int* keys, uint32_t mask, int c, bool* 
 
 // Groups of LPR lanes (64 / LPR rows per wavefront): a group walks its row
 // of A in order and its lanes take the entries of one row of B at a time.
-// Each row owns SLOTS / (64 / LPR) table slots; the kernel takes the rows
-// whose size measure lies in (lo, hi] and leaves the others to the wider
-// kernels (lanes of one wavefront stay in lockstep, so the per-slot order
-// argument above holds group by group).
+// Each row owns SLOTS / (64 / LPR) table slots.  The narrow kernels
+// (LPR < 64) take the rows whose size measure is at most hi and append the
+// others to a list for the one-row-per-wavefront kernels, which stride over
+// that list (or over every row) with a device-side count (lanes of one
+// wavefront stay in lockstep, so the per-slot order argument above holds
+// group by group).
 __device__ __forceinline__ int group_table(int64_t need) {  // power of two >= 2 need, at least 16
   int t = 16;
   while (t < 2 * need) t <<= 1;
   return t;
 }
-// Rows too large for a table of 2 * need slots (big, taken only when
-// allow_big) get the group's whole table with probing bounded by
-// SPG_BIG_PROBES: the distinct count is usually far below the bound need,
-// and a row whose claims fail is marked (cnt = -1) for the global-table pass.
-constexpr uint32_t SPG_BIG_PROBES = 64;
 template <int LPR>
 __global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_sym_grp(int n, int bm, const int* arp, const int* aci,
                                                                   const int* brp, const int* bci, const int64_t* ub,
-                                                                  int64_t lo, int64_t hi, int allow_big, int* cnt,
-                                                                  int* overflow) {
+                                                                  int64_t hi, int* cnt, int* overflow) {
   constexpr int G = 64 / LPR, SLOTS = SPG_SYM_SLOTS / G;
+  static_assert(LPR < 64, "the wide rows use k_spgemm_sym_wave");
   __shared__ int tab[SPG_WAVES][SPG_SYM_SLOTS];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane / LPR, gl = lane % LPR;
   const int64_t i = ((int64_t)blockIdx.x * SPG_WAVES + wave) * G + grp;
   const int64_t need = i < n ? sym_need(ub[i], bm) : 0;
-  const bool big = 2 * need > SLOTS;
-  const bool active = i < n && need > lo && need <= hi && (!big || allow_big);
-  int u = 0, failed = 0;
+  const bool active = i < n && need <= hi && 2 * need <= SLOTS;
+  int u = 0;
   if (active) {
-    const int T = big ? SLOTS : group_table(need);
+    const int T = group_table(need);
     int* keys = tab[wave] + grp * SLOTS;
     for (int q = gl; q < T; q += LPR) keys[q] = -1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1134,35 +1130,124 @@ __global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_sym_grp(int n, int bm
       const int kk = aci[k];
       for (int q = brp[kk] + gl; q < brp[kk + 1]; q += LPR) {
         bool fresh;
-        if (big) {
-          if (lds_claim_bounded(keys, mask, bci[q], SPG_BIG_PROBES, &fresh) < 0) failed = 1;
-        } else if (lds_claim(keys, mask, bci[q], &fresh) < 0) {
-          atomicOr(overflow, 1);
-        }
+        if (lds_claim(keys, mask, bci[q], &fresh) < 0) atomicOr(overflow, 1);
         u += fresh;
       }
     }
   }
-  for (int off = LPR >> 1; off > 0; off >>= 1) {
-    u += __shfl_xor(u, off, LPR);
-    failed |= __shfl_xor(failed, off, LPR);
-  }
-  if (active && gl == 0) cnt[i] = failed ? -1 : u;
+  for (int off = LPR >> 1; off > 0; off >>= 1) u += __shfl_xor(u, off, LPR);
+  if (active && gl == 0) cnt[i] = u;
 }
 
+// Symbolic product of one row per wavefront.  The distinct count does not
+// depend on the order of insertion, so the row's products are flattened:
+// 64 entries of A at a time are loaded together, a prefix sum of their B row
+// lengths maps every lane to one product, and each step claims 64 products.
+// Rows too large for a table of 2 * need slots (big) get the whole table
+// with probing bounded by SPG_BIG_PROBES: the distinct count is usually far
+// below the bound need, and a row whose claims fail is marked (cnt = -1) for
+// the global-table pass.
+constexpr uint32_t SPG_BIG_PROBES = 64;
+__global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_sym_wave(int n, int bm, const int* arp, const int* aci,
+                                                                   const int* brp, const int* bci,
+                                                                   const int64_t* ub, const int* rows,
+                                                                   const int* nrows, int* cnt) {
+  __shared__ int tab[SPG_WAVES][SPG_SYM_SLOTS];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t count = rows ? *nrows : n;
+  int* keys = tab[wave];
+  for (int64_t w = (int64_t)blockIdx.x * SPG_WAVES + wave; w < count; w += (int64_t)gridDim.x * SPG_WAVES) {
+    const int i = rows ? rows[w] : (int)w;
+    const int64_t need = sym_need(ub[i], bm);
+    const bool big = 2 * need > SPG_SYM_SLOTS;
+    const int T = big ? SPG_SYM_SLOTS : group_table(need);
+    const uint32_t mask = (uint32_t)(T - 1);
+    for (int q = lane; q < T; q += 64) keys[q] = -1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    int u = 0, failed = 0;
+    const int ae = arp[i + 1];
+    for (int kb = arp[i]; kb < ae; kb += 64) {
+      const int k = kb + lane;
+      int beg = 0, len = 0;
+      if (k < ae) {
+        const int kk = aci[k];
+        beg = brp[kk];
+        len = brp[kk + 1] - beg;
+      }
+      int incl = len;
+      for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+      }
+      const int total = __shfl(incl, 63, 64);
+      const int excl = incl - len;
+      for (int t0 = 0; t0 < total; t0 += 64) {
+        const int tp = t0 + lane;
+        int j = 0;  // lanes whose products all come before tp
+        for (int step = 32; step > 0; step >>= 1)
+          if (__shfl(incl, j + step - 1, 64) <= tp) j += step;
+        const int bj = __shfl(beg, j & 63, 64), ej = __shfl(excl, j & 63, 64);
+        if (tp < total) {
+          bool fresh;
+          if (lds_claim_bounded(keys, mask, bci[bj + (tp - ej)], big ? SPG_BIG_PROBES : mask + 1, &fresh) < 0)
+            failed = 1;
+          u += fresh;
+        }
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      u += __shfl_xor(u, off, 64);
+      failed |= __shfl_xor(failed, off, 64);
+    }
+    if (lane == 0) cnt[i] = failed ? -1 : u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
+// rows whose size measure lies in (lo, hi]: min(ub, bm) with ub given, else
+// the row length of crp; one atomic per block reserves the block's places
+__global__ __launch_bounds__(BLK) void k_spgemm_list(int n, const int64_t* ub, int bm, const int* crp, int64_t lo,
+                                                     int64_t hi, int* list, int* count) {
+  __shared__ int nb, base;
+  for (int64_t r0 = (int64_t)blockIdx.x * BLK; r0 < n; r0 += (int64_t)gridDim.x * BLK) {
+    if (threadIdx.x == 0) nb = 0;
+    __syncthreads();
+    const int64_t i = r0 + threadIdx.x;
+    bool in = false;
+    if (i < n) {
+      const int64_t m = ub ? sym_need(ub[i], bm) : (int64_t)(crp[i + 1] - crp[i]);
+      in = m > lo && m <= hi;
+    }
+    const int slot = in ? atomicAdd(&nb, 1) : 0;
+    __syncthreads();
+    if (threadIdx.x == 0 && nb) base = atomicAdd(count, nb);
+    __syncthreads();
+    if (in) list[base + slot] = (int)i;
+    __syncthreads();
+  }
+}
+
+// numeric: rows is null for every row, else the listed rows (count *nrows)
 template <int LPR>
 __global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_num_grp(int n, const int* arp, const int* aci,
                                                                   const double* av, const int* brp, const int* bci,
-                                                                  const double* bv, const int* crp, int64_t lo,
-                                                                  int64_t hi, int* cci, double* cv, int* overflow) {
+                                                                  const double* bv, const int* crp, int64_t hi,
+                                                                  const int* rows, const int* nrows, int* cci,
+                                                                  double* cv, int* overflow) {
   constexpr int G = 64 / LPR, SLOTS = SPG_NUM_SLOTS / G;
   __shared__ int tk[SPG_WAVES][SPG_NUM_SLOTS];
   __shared__ double tv[SPG_WAVES][SPG_NUM_SLOTS];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, grp = lane / LPR, gl = lane % LPR;
-  const int64_t i = ((int64_t)blockIdx.x * SPG_WAVES + wave) * G + grp;
-  if (i >= n) return;
+  const int64_t count = rows ? *nrows : n;
+  for (int64_t w = ((int64_t)blockIdx.x * SPG_WAVES + wave) * G + grp; w < count;
+       w += (int64_t)gridDim.x * SPG_WAVES * G) {
+  const int i = rows ? rows[w] : (int)w;
   const int o = crp[i], cnt = crp[i + 1] - o;
-  if (!(cnt > lo && cnt <= hi && 2 * cnt <= SLOTS)) return;
+  if (cnt > hi || 2 * cnt > SLOTS) continue;  // a wider kernel's row
   const int T = group_table(cnt);
   int* keys = tk[wave] + grp * SLOTS;
   double* vals = tv[wave] + grp * SLOTS;
@@ -1217,6 +1302,10 @@ __global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_num_grp(int n, const 
     for (int p = 0; p < m; ++p) rank += keys[p] < c;
     cci[o + rank] = c;
     cv[o + rank] = vals[q];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
 }
 
@@ -1389,18 +1478,27 @@ void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
   const int lpr = bavg <= 8.0 ? 8 : bavg <= 16.0 ? 16 : bavg <= 32.0 ? 32 : 64;
   const int64_t sym_g = SPG_SYM_SLOTS / (64 / lpr) / 2, num_g = SPG_NUM_SLOTS / (64 / lpr) / 2;
   auto groups = [&](int l) { return (unsigned)(((int64_t)n + (int64_t)SPG_WAVES * (64 / l) - 1) / (SPG_WAVES * (64 / l))); };
+  // the wide kernels stride over the listed rows (every row when lpr = 64)
+  Tmp<int> wide(lpr < 64 ? n : 1), nwide(1);
+  int* wl = lpr < 64 ? wide.p : nullptr;
+  int* wn = lpr < 64 ? nwide.p : nullptr;
+  const unsigned wgrid = lpr < 64 ? grid_for(n, SPG_WAVES, 8192) : grid_for(n, SPG_WAVES);
   // symbolic: distinct columns per row
-#define HBGS_SYM(L, LO, HI, BIG)                                                                               \
-  k_spgemm_sym_grp<L><<<groups(L), 64 * SPG_WAVES, 0, s>>>(n, b.m, a.rp, a.ci, b.rp, b.ci, ub.p, LO, HI, BIG, \
-                                                           cnt.p, overflow.p)
+  HBGS_HIP(hipMemsetAsync(nwide.p, 0, sizeof(int), s));
+#define HBGS_SYM(L)                                                                                            \
+  k_spgemm_sym_grp<L><<<groups(L), 64 * SPG_WAVES, 0, s>>>(n, b.m, a.rp, a.ci, b.rp, b.ci, ub.p, sym_g, cnt.p, \
+                                                           overflow.p)
   switch (lpr) {
-    case 8: HBGS_SYM(8, -1, sym_g, 0); break;
-    case 16: HBGS_SYM(16, -1, sym_g, 0); break;
-    case 32: HBGS_SYM(32, -1, sym_g, 0); break;
+    case 8: HBGS_SYM(8); break;
+    case 16: HBGS_SYM(16); break;
+    case 32: HBGS_SYM(32); break;
     default: break;
   }
-  HBGS_SYM(64, lpr < 64 ? sym_g : -1, INT64_MAX, 1);
 #undef HBGS_SYM
+  if (lpr < 64)
+    k_spgemm_list<<<grid_for(n, BLK, 8192), BLK, 0, s>>>(n, ub.p, b.m, nullptr, sym_g, INT64_MAX, wide.p, nwide.p);
+  k_spgemm_sym_wave<<<wgrid, 64 * SPG_WAVES, 0, s>>>(n, b.m, a.rp, a.ci, b.rp, b.ci, ub.p, wl, wn, cnt.p);
+  HBGS_HIP(hipGetLastError());
   k_spgemm_tsize_sym<<<grid_for(n, BLK), BLK, 0, s>>>(n, b.m, ub.p, cnt.p, ts.p);
   HBGS_HIP(hipGetLastError());
   std::vector<int64_t> h_off(n + 1);
@@ -1422,17 +1520,23 @@ void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
   c.ci = pool.make<int>(c.nnz);
   c.v = pool.make<double>(c.nnz);
   // numeric
-#define HBGS_NUM(L, LO, HI)                                                                                  \
-  k_spgemm_num_grp<L><<<groups(L), 64 * SPG_WAVES, 0, s>>>(n, a.rp, a.ci, a.v, b.rp, b.ci, b.v, c.rp, LO, HI, c.ci, \
-                                                           c.v, overflow.p)
+  HBGS_HIP(hipMemsetAsync(nwide.p, 0, sizeof(int), s));
+#define HBGS_NUM(L)                                                                                            \
+  k_spgemm_num_grp<L><<<groups(L), 64 * SPG_WAVES, 0, s>>>(n, a.rp, a.ci, a.v, b.rp, b.ci, b.v, c.rp, num_g,     \
+                                                           nullptr, nullptr, c.ci, c.v, overflow.p)
   switch (lpr) {
-    case 8: HBGS_NUM(8, -1, num_g); break;
-    case 16: HBGS_NUM(16, -1, num_g); break;
-    case 32: HBGS_NUM(32, -1, num_g); break;
+    case 8: HBGS_NUM(8); break;
+    case 16: HBGS_NUM(16); break;
+    case 32: HBGS_NUM(32); break;
     default: break;
   }
-  HBGS_NUM(64, lpr < 64 ? num_g : -1, SPG_NUM_SLOTS / 2);
 #undef HBGS_NUM
+  if (lpr < 64)
+    k_spgemm_list<<<grid_for(n, BLK, 8192), BLK, 0, s>>>(n, nullptr, 0, c.rp, num_g, SPG_NUM_SLOTS / 2, wide.p,
+                                                         nwide.p);
+  k_spgemm_num_grp<64><<<wgrid, 64 * SPG_WAVES, 0, s>>>(n, a.rp, a.ci, a.v, b.rp, b.ci, b.v, c.rp, SPG_NUM_SLOTS / 2,
+                                                         wl, wn, c.ci, c.v, overflow.p);
+  HBGS_HIP(hipGetLastError());
   Tmp<int> nmid(1), mid(n);
   HBGS_HIP(hipMemsetAsync(nmid.p, 0, sizeof(int), s));
   k_spgemm_tsize_num<<<grid_for(n, BLK), BLK, 0, s>>>(n, c.rp, ts.p, nmid.p, mid.p);
