@@ -32,6 +32,10 @@ hipStream_t& tmp_stream() {
   static thread_local hipStream_t s = nullptr;
   return s;
 }
+Scratch*& tmp_scratch() {
+  static thread_local Scratch* s = nullptr;
+  return s;
+}
 
 static void free_block(void* p, const Allocator& a) {
   if (a.free)
@@ -60,6 +64,55 @@ void* Pool::raw(size_t bytes, Allocator& a) {
   return p;
 }
 
+Scratch::~Scratch() {
+  for (auto& c : chunks_) free_block(c.base, c.a);
+}
+void* Scratch::get(size_t bytes) {
+  const size_t need = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+  // the chunk holding the top of the stack, else the first
+  size_t c = stack_.empty() ? 0 : (size_t)stack_.back().chunk;
+  for (; c < chunks_.size(); ++c)
+    if (chunks_[c].size - chunks_[c].used >= need) break;
+  if (c == chunks_.size()) {  // grow: a new chunk at least twice the last
+    Chunk k{};
+    k.size = std::max<size_t>(need, chunks_.empty() ? size_t(64) << 20 : 2 * chunks_.back().size);
+    k.a = current_allocator();
+    if (k.a.alloc) {
+      k.base = static_cast<char*>(k.a.alloc(k.size, k.a.user));
+      if (!k.base) {
+        set_error("device allocation of " + std::to_string(k.size) + " bytes failed in the user allocator");
+        throw Error{HBGS_ENOMEM};
+      }
+    } else {
+      hipError_t e = hipMalloc(&k.base, k.size);
+      if (e != hipSuccess) {
+        set_error(std::string("device allocation of ") + std::to_string(k.size) + " bytes failed: " +
+                  hipGetErrorString(e));
+        throw Error{HBGS_ENOMEM};
+      }
+    }
+    k.used = 0;
+    chunks_.push_back(k);
+  }
+  Chunk& k = chunks_[c];
+  void* p = k.base + k.used;
+  stack_.push_back({p, k.used, (int)c, false});
+  k.used += need;
+  return p;
+}
+void Scratch::put(void* p) {
+  for (size_t q = stack_.size(); q-- > 0;)
+    if (stack_[q].p == p) {
+      stack_[q].freed = true;
+      break;
+    }
+  while (!stack_.empty() && stack_.back().freed) {
+    chunks_[stack_.back().chunk].used = stack_.back().off;
+    stack_.pop_back();
+  }
+}
+
+Pool::Pool(FromScratch) : arena_(false), scratch_(tmp_scratch()) {}
 Pool::~Pool() {
   clear();
   for (auto& c : chunks_) free_block(c.base, c.a);
@@ -67,7 +120,13 @@ Pool::~Pool() {
 }
 void Pool::clear() {
   std::lock_guard<std::mutex> lk(mu_);
-  for (auto& b : blocks_) free_block(b.p, b.a);
+  for (size_t q = blocks_.size(); q-- > 0;) {
+    Block& b = blocks_[q];
+    if (b.scratch)
+      scratch_->put(b.p);
+    else
+      free_block(b.p, b.a);
+  }
   blocks_.clear();
   for (auto& c : chunks_) c.used = 0;
   total_ = 0;
@@ -93,9 +152,16 @@ void* Pool::get(size_t bytes) {
     return c.base;
   }
   Allocator a;
+  if (scratch_) {
+    void* p = scratch_->get(bytes);
+    std::lock_guard<std::mutex> lk(mu_);
+    blocks_.push_back({p, bytes, a, true});
+    total_ += bytes;
+    return p;
+  }
   void* p = raw(bytes, a);
   std::lock_guard<std::mutex> lk(mu_);
-  blocks_.push_back({p, bytes, a});
+  blocks_.push_back({p, bytes, a, false});
   total_ += bytes;
   return p;
 }
@@ -104,7 +170,10 @@ void Pool::release(void* p) {
   std::lock_guard<std::mutex> lk(mu_);
   for (size_t i = 0; i < blocks_.size(); ++i)
     if (blocks_[i].p == p) {
-      free_block(p, blocks_[i].a);
+      if (blocks_[i].scratch)
+        scratch_->put(p);
+      else
+        free_block(p, blocks_[i].a);
       total_ -= blocks_[i].bytes;
       blocks_.erase(blocks_.begin() + i);
       return;
@@ -306,6 +375,9 @@ struct hbgs_ctx {
   int64_t nnz = 0;
   hbgs::Pool pool;
   hbgs::Pool hier{true};  // value-dependent hierarchy (rebuilt by set_values; arena)
+  // setup temporaries: one scratch per field's build thread, the last for
+  // the calling thread
+  hbgs::Scratch scratch[HBGS_MAX_FIELDS + 1];
   int *rp0 = nullptr, *ci0 = nullptr;  // caller's pattern
   int *perm = nullptr, *iperm = nullptr, *src = nullptr;
   int* srcT = nullptr;  // caller's value index of each A_p^T entry
@@ -459,7 +531,7 @@ static solve::ChebCoef cheb_coef(const hbgs_options& o, double lam) {
 // pattern of a equals the pattern of its transpose
 static bool structurally_symmetric_dev(const DCsr& a, hipStream_t s) {
   DCsr t;
-  Pool tmp;
+  Pool tmp{Pool::FromScratch{}};
   t.rp = tmp.make<int>(a.m + 1);
   t.ci = tmp.make<int>(a.nnz);
   t.v = nullptr;
@@ -586,7 +658,7 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
         DCsr R = transpose_new(pool, P, s);
         clk.to(4);
         DCsr AP, Ac;
-        Pool tmp_pool;
+        Pool tmp_pool{Pool::FromScratch{}};
         setup::spgemm(A, P, AP, tmp_pool, s);
         setup::spgemm(R, AP, Ac, pool, s);
         F.lv[l].P = P;
@@ -781,6 +853,7 @@ static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
 // its own stream (the latency-bound steps of one field, such as the
 // aggregation rounds and the factorisation steps, overlap the others').
 static void build_values(hbgs_ctx* c, hipStream_t s) {
+  ScratchScope main_scratch(&c->scratch[HBGS_MAX_FIELDS]);
   c->clear_graphs();
   c->hier.clear();
   c->group_of.assign(c->nf, 0);
@@ -795,6 +868,7 @@ static void build_values(hbgs_ctx* c, hipStream_t s) {
   }
   if (c->nf == 1 || !c->o.setup_concurrent) {
     StreamScope scope(s);
+    ScratchScope scratch(&c->scratch[HBGS_MAX_FIELDS]);
     for (int f = 0; f < c->nf; ++f) build_field(c, c->F[f], s);
   } else {
     int dev = 0;
@@ -812,6 +886,7 @@ static void build_values(hbgs_ctx* c, hipStream_t s) {
         HBGS_HIP(hipSetDevice(dev));
         HBGS_HIP(hipStreamWaitEvent(sf, c->setup_in, 0));
         StreamScope scope(sf);
+        ScratchScope scratch(&c->scratch[f]);
         build_field(c, c->F[f], sf);
       } catch (const Error& e) {
         code[f] = e.code;

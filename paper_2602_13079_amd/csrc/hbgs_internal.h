@@ -49,9 +49,14 @@ Allocator current_allocator();
 // An arena pool (the value-dependent hierarchy) carves allocations out of
 // large chunks and keeps the chunks when cleared, so a rebuild of the same
 // pattern allocates nothing.  Safe to use from several host threads.
+class Scratch;
 class Pool {
  public:
   explicit Pool(bool arena = false) : arena_(arena) {}
+  // a temporary pool whose blocks come from the thread's scratch (when one
+  // is set) and go back to it when the pool is cleared or destroyed
+  struct FromScratch {};
+  explicit Pool(FromScratch);
   ~Pool();
   void* get(size_t bytes);  // persistent
   void release(void* p);    // free one allocation early (arena: kept until clear)
@@ -67,6 +72,7 @@ class Pool {
     void* p;
     size_t bytes;
     Allocator a;
+    bool scratch;
   };
   struct Chunk {
     char* base;
@@ -76,6 +82,7 @@ class Pool {
   void* raw(size_t bytes, Allocator& a);
   std::mutex mu_;
   bool arena_;
+  Scratch* scratch_ = nullptr;
   std::vector<Block> blocks_;
   std::vector<Chunk> chunks_;
   size_t total_ = 0;
@@ -90,20 +97,65 @@ struct StreamScope {
   ~StreamScope() { tmp_stream() = prev; }
 };
 
-// Temporary device buffer (setup only): stream-ordered on the thread's
-// setup stream when one is set, else hipMalloc / hipFree.
+// Scratch memory for the setup temporaries of one host thread: a stack of
+// device chunks that is kept across rebuilds, so a rebuild of the same size
+// makes no allocation call (allocation calls from several setup threads
+// serialise in the runtime, and a free waits for the device).  The thread's
+// temporaries are ordered on its one stream, so a freed block can back the
+// next temporary at once.  Blocks are freed in any order; the stack shrinks
+// when its top is free.  One thread at a time.
+class Scratch {
+ public:
+  Scratch() = default;
+  ~Scratch();
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
+  void* get(size_t bytes);
+  void put(void* p);
+
+ private:
+  struct Chunk {
+    char* base;
+    size_t size, used;
+    Allocator a;
+  };
+  struct Rec {
+    void* p;
+    size_t off;
+    int chunk;
+    bool freed;
+  };
+  std::vector<Chunk> chunks_;
+  std::vector<Rec> stack_;
+};
+// the calling thread's scratch (null: temporaries use the runtime allocator)
+Scratch*& tmp_scratch();
+struct ScratchScope {
+  Scratch* prev;
+  explicit ScratchScope(Scratch* s) : prev(tmp_scratch()) { tmp_scratch() = s; }
+  ~ScratchScope() { tmp_scratch() = prev; }
+};
+
+// Temporary device buffer (setup only): from the thread's scratch when one
+// is set, else stream-ordered on the thread's setup stream when one is set,
+// else hipMalloc / hipFree.
 template <class T>
 struct Tmp {
   T* p = nullptr;
   size_t count = 0;
   hipStream_t s = nullptr;
   bool async = false;
+  Scratch* sc = nullptr;
   Tmp() = default;
   explicit Tmp(size_t n) { alloc(n); }
   void alloc(size_t n) {
     release();
     count = n;
     const size_t bytes = (n ? n : 1) * sizeof(T);
+    if ((sc = tmp_scratch()) != nullptr) {
+      p = static_cast<T*>(sc->get(bytes));
+      return;
+    }
     s = tmp_stream();
     async = false;
     if (s) {
@@ -120,12 +172,15 @@ struct Tmp {
   }
   void release() {
     if (p) {
-      if (async)
+      if (sc)
+        sc->put(p);
+      else if (async)
         (void)hipFreeAsync(p, s);
       else
         (void)hipFree(p);
     }
     p = nullptr;
+    sc = nullptr;
   }
   ~Tmp() { release(); }
   Tmp(const Tmp&) = delete;

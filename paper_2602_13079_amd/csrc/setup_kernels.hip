@@ -1501,9 +1501,10 @@ void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
   HBGS_HIP(hipGetLastError());
   k_spgemm_tsize_sym<<<grid_for(n, BLK), BLK, 0, s>>>(n, b.m, ub.p, cnt.p, ts.p);
   HBGS_HIP(hipGetLastError());
-  std::vector<int64_t> h_off(n + 1);
+  std::vector<int64_t> h_off;  // row offsets of the global tables, only when some row needs one
   std::vector<int> cuts;
   if (scan_i64(ts.p, toff.p, n, s) > 0) {
+    h_off.resize(n + 1);
     HBGS_HIP(hipMemcpyAsync(h_off.data(), toff.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
     HBGS_HIP(hipStreamSynchronize(s));
     Tmp<int> keys(batch_rows(h_off, n, cuts));
@@ -1549,6 +1550,7 @@ void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
     HBGS_HIP(hipGetLastError());
   }
   if (scan_i64(ts.p, toff.p, n, s) > 0) {
+    h_off.resize(n + 1);
     HBGS_HIP(hipMemcpyAsync(h_off.data(), toff.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
     HBGS_HIP(hipStreamSynchronize(s));
     const int64_t maxbatch = batch_rows(h_off, n, cuts);
