@@ -1642,11 +1642,11 @@ constexpr int LU_R = 2;
 constexpr int LU_MAXN = LU_PT * LU_R;
 
 __global__ __launch_bounds__(LU_PT) void k_lu_panel(int n, int k0, double* m, int* piv, int* singular) {
-  __shared__ double wv[LU_PT / 64];
-  __shared__ int wi[LU_PT / 64];
-  __shared__ double prow[LU_NB], xrow[LU_NB];
-  __shared__ int sp;
-  __shared__ double spv;
+  // per-column exchange buffers, alternating between consecutive columns so
+  // that one barrier per hand-over suffices
+  __shared__ double wv[2][LU_PT / 64];
+  __shared__ int wi[2][LU_PT / 64];
+  __shared__ double prow[2][LU_NB], xrow[2][LU_NB];
   const int rows = n - k0, nb = min(LU_NB, n - k0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double a[LU_R][LU_NB];
@@ -1659,6 +1659,7 @@ __global__ __launch_bounds__(LU_PT) void k_lu_panel(int n, int k0, double* m, in
   bool failed = false;
 #pragma unroll
   for (int j = 0; j < LU_NB; ++j) {
+    const int b = j & 1;
     if (j >= nb || failed) continue;  // uniform across the block
     // pivot: largest |a_rj| over r >= j, first index on ties
     double best = -1.0;
@@ -1683,28 +1684,31 @@ __global__ __launch_bounds__(LU_PT) void k_lu_panel(int n, int k0, double* m, in
       }
     }
     if (lane == 0) {
-      wv[wave] = best;
-      wi[wave] = bi;
+      wv[b][wave] = best;
+      wi[b][wave] = bi;
     }
     __syncthreads();
+    // every wavefront combines the per-wave candidates itself
+    constexpr int NW = LU_PT / 64;
+    best = lane < NW ? wv[b][lane] : -1.0;
+    bi = lane < NW ? wi[b][lane] : INT32_MAX;
+    for (int off = NW / 2; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(best, off, 64);
+      const int oi = __shfl_xor(bi, off, 64);
+      if (ov > best || (ov == best && oi < bi)) {
+        best = ov;
+        bi = oi;
+      }
+    }
+    best = __shfl(best, 0, 64);
+    const int p = __shfl(bi, 0, 64);
     if (tid == 0) {
-      double b = wv[0];
-      int ib = wi[0];
-      for (int w = 1; w < LU_PT / 64; ++w)
-        if (wv[w] > b || (wv[w] == b && wi[w] < ib)) {
-          b = wv[w];
-          ib = wi[w];
-        }
-      sp = ib;
-      spv = b;
-      if (b > 0.0)
-        piv[k0 + j] = k0 + ib;
+      if (best > 0.0)
+        piv[k0 + j] = k0 + p;
       else
         *singular = 1;
     }
-    __syncthreads();
-    const int p = sp;
-    if (!(spv > 0.0)) {  // uniform: the factorisation has failed
+    if (!(best > 0.0)) {  // uniform: the factorisation has failed
       failed = true;
       continue;
     }
@@ -1714,10 +1718,10 @@ __global__ __launch_bounds__(LU_PT) void k_lu_panel(int n, int k0, double* m, in
       const int r = tid + q * LU_PT;
       if (r == p)
 #pragma unroll
-        for (int t = 0; t < LU_NB; ++t) prow[t] = a[q][t];
+        for (int t = 0; t < LU_NB; ++t) prow[b][t] = a[q][t];
       if (r == j)
 #pragma unroll
-        for (int t = 0; t < LU_NB; ++t) xrow[t] = a[q][t];
+        for (int t = 0; t < LU_NB; ++t) xrow[b][t] = a[q][t];
     }
     __syncthreads();
 #pragma unroll
@@ -1725,13 +1729,13 @@ __global__ __launch_bounds__(LU_PT) void k_lu_panel(int n, int k0, double* m, in
       const int r = tid + q * LU_PT;
       if (r == j)
 #pragma unroll
-        for (int t = 0; t < LU_NB; ++t) a[q][t] = prow[t];
+        for (int t = 0; t < LU_NB; ++t) a[q][t] = prow[b][t];
       else if (r == p)
 #pragma unroll
-        for (int t = 0; t < LU_NB; ++t) a[q][t] = xrow[t];
+        for (int t = 0; t < LU_NB; ++t) a[q][t] = xrow[b][t];
     }
     // multipliers and the update of the panel's remaining columns
-    const double d = prow[j];
+    const double d = prow[b][j];
 #pragma unroll
     for (int q = 0; q < LU_R; ++q) {
       const int r = tid + q * LU_PT;
@@ -1740,10 +1744,9 @@ __global__ __launch_bounds__(LU_PT) void k_lu_panel(int n, int k0, double* m, in
         a[q][j] = l;
 #pragma unroll
         for (int t = 0; t < LU_NB; ++t)
-          if (t > j) a[q][t] -= l * prow[t];
+          if (t > j) a[q][t] -= l * prow[b][t];
       }
     }
-    __syncthreads();
   }
   if (failed) return;
 #pragma unroll
@@ -1757,24 +1760,62 @@ __global__ __launch_bounds__(LU_PT) void k_lu_panel(int n, int k0, double* m, in
 }
 
 // every column outside the panel: the panel's interchanges; trailing
-// columns also get U12 = L11^-1 A12 (L11 unit lower)
-__global__ void k_lu_swap_trsm(int n, int k0, int nb, double* m, const int* piv) {
-  GRID_STRIDE(c, n - nb) {
-    const int j = c < k0 ? (int)c : (int)c + nb;
+// columns also get U12 = L11^-1 A12 (L11 unit lower).  The interchanges,
+// applied in order, move values among at most 2 LU_NB rows: one thread
+// works out where each of those rows takes its value from, then every
+// column gathers them at once (no chain of dependent swaps) and solves in
+// registers with L11 from LDS.
+__global__ __launch_bounds__(BLK) void k_lu_swap_trsm(int n, int k0, int nb, double* m, const int* piv) {
+  __shared__ int dst[2 * LU_NB], src[2 * LU_NB];
+  __shared__ int nrow;
+  __shared__ double sl[LU_NB][LU_NB + 1];
+  if (threadIdx.x == 0) {
+    int cnt = nb;  // the panel rows first, then the other rows met
+    for (int t = 0; t < nb; ++t) dst[t] = src[t] = k0 + t;
     for (int t = 0; t < nb; ++t) {
       const int p = piv[k0 + t];
       if (p > k0 + t && p < n) {
-        const double x = m[(int64_t)(k0 + t) * n + j];
-        m[(int64_t)(k0 + t) * n + j] = m[(int64_t)p * n + j];
-        m[(int64_t)p * n + j] = x;
+        int q = -1;
+        for (int e = 0; e < cnt; ++e)
+          if (dst[e] == p) q = e;
+        if (q < 0) {
+          q = cnt++;
+          dst[q] = src[q] = p;
+        }
+        const int x = src[t];
+        src[t] = src[q];
+        src[q] = x;
       }
     }
-    if (j >= k0 + nb)
-      for (int t = 1; t < nb; ++t) {
-        double s = m[(int64_t)(k0 + t) * n + j];
-        for (int u = 0; u < t; ++u) s -= m[(int64_t)(k0 + t) * n + k0 + u] * m[(int64_t)(k0 + u) * n + j];
-        m[(int64_t)(k0 + t) * n + j] = s;
+    nrow = cnt;
+  }
+  for (int e = threadIdx.x; e < LU_NB * LU_NB; e += BLK) {
+    const int r = e / LU_NB, u = e % LU_NB;
+    sl[r][u] = (r < nb && u < nb) ? m[(int64_t)(k0 + r) * n + k0 + u] : 0.0;
+  }
+  __syncthreads();
+  const int cnt = nrow;
+  const int64_t c = (int64_t)blockIdx.x * BLK + threadIdx.x;  // one column per thread
+  if (c < n - nb) {
+    const int j = c < k0 ? (int)c : (int)c + nb;
+    double v[2 * LU_NB];
+#pragma unroll
+    for (int q = 0; q < 2 * LU_NB; ++q) v[q] = q < cnt ? m[(int64_t)src[q] * n + j] : 0.0;
+    if (j >= k0 + nb) {
+#pragma unroll
+      for (int t = 1; t < LU_NB; ++t) {
+        if (t < nb) {
+          double s = v[t];
+#pragma unroll
+          for (int u = 0; u < t; ++u) s -= sl[t][u] * v[u];
+          v[t] = s;
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep the LDS reads row by row (registers)
       }
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * LU_NB; ++q)
+      if (q < cnt) m[(int64_t)dst[q] * n + j] = v[q];
   }
 }
 
@@ -1817,23 +1858,45 @@ __global__ void k_inv_init(int n, const int* pinv, double* x) {
     x[e] = pinv[c] == i ? 1.0 : 0.0;
   }
 }
-// rows kb..kb+nb of X: unit lower (forward) or upper (backward) block solve
+// rows kb..kb+nb of X: unit lower (forward) or upper (backward) block solve,
+// one thread per column with the block's rows in registers and the diagonal
+// block of the factors in LDS (rows beyond nb: zero, with a unit diagonal)
 template <bool UPPER>
-__global__ void k_inv_trsm(int n, int kb, int nb, const double* f, double* x) {
-  GRID_STRIDE(c, n) {
-    if (!UPPER) {
-      for (int t = 1; t < nb; ++t) {
-        double s = x[(int64_t)(kb + t) * n + c];
-        for (int u = 0; u < t; ++u) s -= f[(int64_t)(kb + t) * n + kb + u] * x[(int64_t)(kb + u) * n + c];
-        x[(int64_t)(kb + t) * n + c] = s;
-      }
-    } else {
-      for (int t = nb - 1; t >= 0; --t) {
-        double s = x[(int64_t)(kb + t) * n + c];
-        for (int u = t + 1; u < nb; ++u) s -= f[(int64_t)(kb + t) * n + kb + u] * x[(int64_t)(kb + u) * n + c];
-        x[(int64_t)(kb + t) * n + c] = s / f[(int64_t)(kb + t) * n + kb + t];
-      }
-    }
+__global__ __launch_bounds__(BLK) void k_inv_trsm(int n, int kb, int nb, const double* f, double* x) {
+  // The unit lower solve is run as an upper solve on reversed indices
+  // (position i holds row INV_NB-1-i, with unit diagonal), so both use the
+  // one loop below.
+  __shared__ double sf[INV_NB][INV_NB + 1];
+  for (int e = threadIdx.x; e < INV_NB * INV_NB; e += BLK) {
+    const int i = e / INV_NB, w = e % INV_NB;
+    const int r = UPPER ? i : INV_NB - 1 - i, u = UPPER ? w : INV_NB - 1 - w;
+    double val = r == u ? 1.0 : 0.0;
+    if (r < nb && u < nb && (UPPER || r != u)) val = f[(int64_t)(kb + r) * n + kb + u];
+    sf[i][w] = val;
+  }
+  __syncthreads();
+  // one column per thread.  The terms are fused multiply-adds, so each row
+  // is one dependent chain that stays in registers; the explicit inverse is
+  // checked through the coarse solve's result, not bit for bit.
+  const int64_t c = (int64_t)blockIdx.x * BLK + threadIdx.x;
+  if (c >= n) return;
+  double v[INV_NB];
+#pragma unroll
+  for (int i = 0; i < INV_NB; ++i) {
+    const int r = UPPER ? i : INV_NB - 1 - i;
+    v[i] = r < nb ? x[(int64_t)(kb + r) * n + c] : 0.0;
+  }
+#pragma unroll
+  for (int i = INV_NB - 1; i >= 0; --i) {
+    double s = v[i];
+#pragma unroll
+    for (int w = i + 1; w < INV_NB; ++w) s = fma(-sf[i][w], v[w], s);
+    v[i] = s / sf[i][i];
+  }
+#pragma unroll
+  for (int i = 0; i < INV_NB; ++i) {
+    const int r = UPPER ? i : INV_NB - 1 - i;
+    if (r < nb) x[(int64_t)(kb + r) * n + c] = v[i];
   }
 }
 // X[i, :] -= F[i, kb..kb+nb) X[kb..kb+nb, :] for rows i in [r_lo, r_hi), in
@@ -1878,7 +1941,7 @@ int dense_inverse(const DCsr& a, double* inv, hipStream_t s) {
     for (int k0 = 0; k0 < n; k0 += LU_NB) {
       const int nb = std::min(LU_NB, n - k0);
       k_lu_panel<<<1, LU_PT, 0, s>>>(n, k0, m.p, piv.p, sing.p);
-      if (n - nb > 0) k_lu_swap_trsm<<<grid_for(n - nb, BLK), BLK, 0, s>>>(n, k0, nb, m.p, piv.p);
+      if (n - nb > 0) k_lu_swap_trsm<<<(n - nb + BLK - 1) / BLK, BLK, 0, s>>>(n, k0, nb, m.p, piv.p);
       const int rest = n - k0 - nb;
       if (rest > 0) k_lu_gemm<<<dim3((rest + 63) / 64, (rest + 31) / 32), BLK, 0, s>>>(n, k0, nb, m.p);
     }
@@ -1907,14 +1970,14 @@ int dense_inverse(const DCsr& a, double* inv, hipStream_t s) {
   const unsigned cgrid = (unsigned)((n + 63) / 64);
   for (int kb = 0; kb < n; kb += INV_NB) {  // L Y = P
     const int nb = std::min(INV_NB, n - kb);
-    k_inv_trsm<false><<<grid_for(n, BLK), BLK, 0, s>>>(n, kb, nb, m.p, inv);
+    k_inv_trsm<false><<<(n + BLK - 1) / BLK, BLK, 0, s>>>(n, kb, nb, m.p, inv);
     const int below = n - kb - nb;
     if (below > 0)
       k_inv_update<<<dim3(cgrid, (below + 31) / 32), BLK, 0, s>>>(n, kb, nb, kb + nb, n, m.p, inv);
   }
   for (int kb = (n - 1) / INV_NB * INV_NB; kb >= 0; kb -= INV_NB) {  // U X = Y
     const int nb = std::min(INV_NB, n - kb);
-    k_inv_trsm<true><<<grid_for(n, BLK), BLK, 0, s>>>(n, kb, nb, m.p, inv);
+    k_inv_trsm<true><<<(n + BLK - 1) / BLK, BLK, 0, s>>>(n, kb, nb, m.p, inv);
     if (kb > 0) k_inv_update<<<dim3(cgrid, (kb + 31) / 32), BLK, 0, s>>>(n, kb, nb, 0, kb, m.p, inv);
   }
   HBGS_HIP(hipGetLastError());
