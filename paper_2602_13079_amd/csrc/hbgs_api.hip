@@ -349,7 +349,9 @@ struct Krylov {
     g = pool.make<double>(m + 1);
     y = pool.make<double>(m);
     scal = pool.make<double>(4);
-    HBGS_HIP(hipHostMalloc((void**)&host, 8 * sizeof(double), hipHostMallocDefault));
+    // coherent (fine-grained): the Givens kernel's stores reach the host
+    // while the rest of the step still runs
+    HBGS_HIP(hipHostMalloc((void**)&host, 8 * sizeof(double), hipHostMallocCoherent));
     HBGS_HIP(hipHostGetDevicePointer((void**)&host_dev, host, 0));
   }
 };
@@ -1233,6 +1235,30 @@ static void run_iteration(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, int
   HBGS_HIP(hipGraphLaunch(it->second.exec, s));
 }
 
+// The Givens kernel stores ||w||, h_{j+1,j} and then, after a system-scope
+// fence, the residual estimate into coherent pinned memory.  The host waits
+// for the estimate slot to leave its sentinel instead of synchronising the
+// stream, so it decides and enqueues the next step while the basis update
+// of this one still runs.  Should the store not arrive, the stream's
+// completion ends the wait (and an idle stream with the sentinel still in
+// place is an error).
+constexpr double kEstPending = -1.0;  // estimates are norms (>= 0, or NaN)
+static void wait_estimate(const double* host, hipStream_t s) {
+  const volatile double* slot = host;
+  for (unsigned spins = 1;; ++spins) {
+    if (*slot != kEstPending) return;
+    if ((spins & 4095u) == 0) {
+      const hipError_t e = hipStreamQuery(s);
+      if (e == hipSuccess) {
+        if (*slot != kEstPending) return;
+        HBGS_FAIL(HBGS_EHIP, "GMRES step ended without a residual estimate");
+      }
+      if (e != hipErrorNotReady) HBGS_HIP(e);
+    }
+    __builtin_ia32_pause();
+  }
+}
+
 // Flexible GMRES(K.m) for A x = b with b in K.bp and x in K.xp (zero start
 // unless use_x0); the relative residual target is rtol, at most max_iters
 // Arnoldi steps.  hist (optional) receives the residual estimates, the true
@@ -1276,8 +1302,9 @@ static hbgs_status fgmres(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, dou
     HBGS_HIP(hipMemcpyAsync(K.g, g0.data(), sizeof(double) * (m + 1), hipMemcpyHostToDevice, s));
     int jend = 0;
     for (int j = 0; j < m; ++j) {
+      K.host[0] = kEstPending;
       run_iteration(c, K, A, prec, j, graph_key, s);  // its Givens step writes the estimate to K.host
-      HBGS_HIP(hipStreamSynchronize(s));
+      wait_estimate(K.host, s);
       (*iters)++;
       double est = K.host[0] / bnorm, hn = K.host[1], w0 = K.host[2];
       push(est);

@@ -593,10 +593,12 @@ __device__ void givens_update(const GivensArgs& ga, const double* h2) {
   ga.scal[0] = est;
   ga.scal[1] = hn;
   ga.scal[2] = w0;
-  if (ga.host_scal) {
-    ga.host_scal[0] = est;
+  if (ga.host_scal) {  // the estimate last: the host polls it
     ga.host_scal[1] = hn;
     ga.host_scal[2] = w0;
+    __threadfence_system();
+    ga.host_scal[0] = est;
+    __threadfence_system();
   }
 }
 
