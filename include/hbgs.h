@@ -97,6 +97,12 @@ typedef struct {
                             rows without overlap, incomplete LU with zero fill in each
                             (the species-block choice of Sec. 3.2) */
   int32_t ilu_block;     /* rows per ILU(0) subdomain (default 4096) */
+  int32_t build_transpose; /* 1 (default): the adjoint's operators (A_l^T on every level,
+                              the transposed couplings and outer operator values, the
+                              coarsest inverse transposed, transposed ILU factors) are
+                              built with the hierarchy; 0: on the first transpose apply
+                              or solve after each setup or value update, so forward-only
+                              callers skip that work */
 } hbgs_options;
 
 typedef struct {

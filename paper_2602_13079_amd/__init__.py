@@ -38,7 +38,7 @@ class Options(ctypes.Structure):
         ("setup_concurrent", ctypes.c_int32), ("block_jacobi", ctypes.c_int32), ("nested", ctypes.c_int32),
         ("inner_restart", ctypes.c_int32), ("inner_max_iters", ctypes.c_int32), ("inner_rtol", ctypes.c_double),
         ("field_cheb_degree", ctypes.c_int32 * MAX_FIELDS), ("field_leaf", ctypes.c_int32 * MAX_FIELDS),
-        ("ilu_block", ctypes.c_int32),
+        ("ilu_block", ctypes.c_int32), ("build_transpose", ctypes.c_int32),
     ]
 
 

@@ -382,7 +382,10 @@ struct hbgs_ctx {
   hbgs::Scratch scratch[HBGS_MAX_FIELDS + 1];
   int *rp0 = nullptr, *ci0 = nullptr;  // caller's pattern
   int *perm = nullptr, *iperm = nullptr, *src = nullptr;
-  int* srcT = nullptr;  // caller's value index of each A_p^T entry
+  int* posT = nullptr;  // position in A_p of each A_p^T entry
+  // transposed operators: A_p^T's values follow A_p's (apt_fresh); the
+  // hierarchy's transposed parts exist for the current hierarchy (hier_t)
+  bool apt_fresh = false, hier_t = false;
   hbgs::DCsr Ap, ApT;
   std::vector<int> leaf_order, f_lo, f_hi;
   std::vector<hbgs::Field> F;
@@ -453,6 +456,7 @@ static void validate_options(const hbgs_options& o) {
     if (o.field_leaf[f] < 0 || o.field_leaf[f] > 2) HBGS_FAIL(HBGS_EINVAL, "field_leaf must be 0, 1 or 2");
   }
   if (o.ilu_block < 1) HBGS_FAIL(HBGS_EINVAL, "ilu_block must be >= 1");
+  if (o.build_transpose != 0 && o.build_transpose != 1) HBGS_FAIL(HBGS_EINVAL, "build_transpose must be 0 or 1");
 }
 
 static void parse_tree(hbgs_ctx* c, const int32_t* tree, int len) {
@@ -675,8 +679,6 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
       if (n > 8000) HBGS_FAIL(HBGS_ESETUP, "coarsest level too large for the dense factorisation");
       F.inv = pool.make<double>((size_t)n * n);
       if (setup::dense_inverse(L.A, F.inv, s) != 0) HBGS_FAIL(HBGS_ESINGULAR, "singular coarsest-level matrix");
-      F.invT = pool.make<double>((size_t)n * n);
-      setup::dense_transpose(n, F.inv, F.invT, s);
       break;
     }
     clk.to(6);
@@ -694,18 +696,9 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
     HBGS_FAIL(HBGS_EINVAL, "a diagonal field block is not structurally symmetric");
   for (size_t l = 0; l < F.lv.size(); ++l) {
     Level& L = F.lv[l];
-    // A_l is structurally symmetric (level 0 checked above; Galerkin products
-    // R A P with R = P^T keep the property), so A_l^T shares its pattern
-    L.AT = L.A;
-    L.AT.v = pool.make<double>(L.A.nnz);
-    setup::transpose_symmetric(L.A, L.AT.v, s);
     add_f32(pool, L.A, s);
-    add_f32(pool, L.AT, s);
     setup::row_stats(L.A, s);
     setup::pack_columns(pool, L.A, s);
-    L.AT.maxlen = L.A.maxlen;
-    L.AT.cd = L.A.cd;  // same pattern
-    L.AT.cb = L.A.cb;
     if (l + 1 < F.lv.size()) {
       add_f32(pool, L.P, s);
       add_f32(pool, L.R, s);
@@ -814,6 +807,42 @@ static void plan_sweep(hbgs_ctx* c, const std::vector<int>& leaves, int tr, Swee
 
 // per-field part of the value-dependent setup: diagonal block, couplings,
 // SA-AMG hierarchy
+// The adjoint's parts of one field (A_p^T's values must be current): the
+// transposed couplings read by the reversed sweep; A_l^T on every level (A_l
+// is structurally symmetric -- level 0 is checked, and Galerkin products
+// R A P with R = P^T keep the property -- so A_l^T shares A_l's pattern and
+// packed columns); the coarsest inverse transposed; the transposed ILU
+// factors.  Counted in the solve-data stage.
+static void build_field_T(hbgs_ctx* c, Field& F, hipStream_t s) {
+  StageClock clk(F.stage_seconds);
+  clk.to(7);
+  Pool& pool = c->hier;
+  int glo = 0, ghi = c->n;
+  if (c->o.nested) {
+    const std::vector<int>& gf = c->group_fields[c->group_of[F.id]];
+    glo = c->f_lo[gf.front()];
+    ghi = c->f_hi[gf.back()];
+  }
+  const bool bj = c->o.block_jacobi != 0;
+  F.upperT = extract(pool, c->ApT, F.lo, F.hi, bj ? ghi : F.hi, ghi, glo, ghi - glo, s);
+  add_f32(pool, F.upperT, s);
+  setup::row_stats(F.upperT, s);
+  setup::pack_columns(pool, F.upperT, s);
+  if (F.leaf == 2) setup::ilu_transpose(pool, F.ilu, s);
+  if (F.leaf == 0) {
+    for (Level& L : F.lv) {
+      L.AT = L.A;  // pattern, row statistics and packed columns
+      L.AT.v = pool.make<double>(L.A.nnz);
+      setup::transpose_symmetric(L.A, L.AT.v, s);
+      add_f32(pool, L.AT, s);
+    }
+    const int nc = F.lv.back().A.n;
+    F.invT = pool.make<double>((size_t)nc * nc);
+    setup::dense_transpose(nc, F.inv, F.invT, s);
+  }
+  HBGS_HIP(hipStreamSynchronize(s));
+}
+
 static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
   std::fill(std::begin(F.stage_seconds), std::end(F.stage_seconds), 0.0);
@@ -834,20 +863,56 @@ static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
   }
   const bool bj = c->o.block_jacobi != 0;
   F.lower = extract(c->hier, c->Ap, F.lo, F.hi, glo, bj ? glo : F.lo, glo, ghi - glo, s);
-  F.upperT = extract(c->hier, c->ApT, F.lo, F.hi, bj ? ghi : F.hi, ghi, glo, ghi - glo, s);
   add_f32(c->hier, F.lower, s);
-  add_f32(c->hier, F.upperT, s);
   setup::row_stats(F.lower, s);
-  setup::row_stats(F.upperT, s);
   setup::pack_columns(c->hier, F.lower, s);
-  setup::pack_columns(c->hier, F.upperT, s);
   F.td = c->hier.make<double>(F.n());
   F.tf = c->hier.make<float>(F.n());
   HBGS_HIP(hipStreamSynchronize(s));
   clk.to(-1);
   build_hierarchy(c, F, s);
+  if (c->o.build_transpose) build_field_T(c, F, s);
   HBGS_HIP(hipStreamSynchronize(s));
   F.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// which fields each field's coupling rows read, forward (tr = 0: lower) or
+// adjoint (tr = 1: upperT), with column ranges relative to the coupling's
+// own column origin
+static void field_deps(hbgs_ctx* c, int tr, hipStream_t s) {
+  Tmp<int> masks(c->nf);
+  HBGS_HIP(hipMemsetAsync(masks.p, 0, sizeof(int) * c->nf, s));
+  std::vector<int> lo(c->nf), hi(c->nf);
+  for (int f = 0; f < c->nf; ++f) {
+    const int origin = c->o.nested ? c->f_lo[c->group_fields[c->group_of[f]].front()] : 0;
+    for (int g = 0; g < c->nf; ++g) {
+      lo[g] = c->f_lo[g] - origin;
+      hi[g] = c->f_hi[g] - origin;
+    }
+    solve::column_fields(tr ? c->F[f].upperT : c->F[f].lower, c->nf, lo.data(), hi.data(), masks.p + f, s);
+  }
+  std::vector<int> hm(c->nf);
+  HBGS_HIP(hipMemcpyAsync(hm.data(), masks.p, sizeof(int) * c->nf, hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  for (int f = 0; f < c->nf; ++f) c->F[f].deps[tr] = (uint32_t)hm[f];
+}
+
+// the adjoint's parts above the fields (after every build_field_T): the
+// groups' transposed blocks, the adjoint dependencies and sweep plans
+static void build_rest_T(hbgs_ctx* c, hipStream_t s) {
+  for (Group& g : c->G) {
+    const bool bj = c->o.block_jacobi != 0;
+    g.AT = extract(c->hier, c->ApT, g.lo, g.hi, g.lo, g.hi, g.lo, g.n(), s);
+    g.upperT = extract(c->hier, c->ApT, g.lo, g.hi, bj ? c->n : g.hi, c->n, 0, c->n, s);
+    for (DCsr* a : {&g.AT, &g.upperT}) {
+      setup::row_stats(*a, s);
+      setup::pack_columns(c->hier, *a, s);
+    }
+  }
+  field_deps(c, 1, s);
+  plan_sweep(c, c->leaf_order, 1, c->plan[1]);
+  for (Group& g : c->G) plan_sweep(c, g.fields, 1, g.plan[1]);
+  c->hier_t = true;
 }
 
 // value-dependent part of setup: blocks, couplings, hierarchies.  The
@@ -856,6 +921,7 @@ static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
 // aggregation rounds and the factorisation steps, overlap the others').
 static void build_values(hbgs_ctx* c, hipStream_t s) {
   ScratchScope main_scratch(&c->scratch[HBGS_MAX_FIELDS]);
+  c->hier_t = false;
   c->clear_graphs();
   c->hier.clear();
   c->group_of.assign(c->nf, 0);
@@ -920,42 +986,17 @@ static void build_values(hbgs_ctx* c, hipStream_t s) {
     g.lo = c->f_lo[g.fields.front()];
     g.hi = c->f_hi[g.fields.back()];
     g.A = extract(c->hier, c->Ap, g.lo, g.hi, g.lo, g.hi, g.lo, g.n(), s);
-    g.AT = extract(c->hier, c->ApT, g.lo, g.hi, g.lo, g.hi, g.lo, g.n(), s);
     const bool bj = c->o.block_jacobi != 0;
     g.lower = extract(c->hier, c->Ap, g.lo, g.hi, 0, bj ? 0 : g.lo, 0, c->n, s);
-    g.upperT = extract(c->hier, c->ApT, g.lo, g.hi, bj ? c->n : g.hi, c->n, 0, c->n, s);
-    for (DCsr* a : {&g.A, &g.AT, &g.lower, &g.upperT}) {
+    for (DCsr* a : {&g.A, &g.lower}) {
       setup::row_stats(*a, s);
       setup::pack_columns(c->hier, *a, s);
     }
   }
-  // which fields each coupling reads (column ranges relative to the
-  // coupling's own column origin)
-  {
-    Tmp<int> masks(2 * c->nf);
-    HBGS_HIP(hipMemsetAsync(masks.p, 0, sizeof(int) * 2 * c->nf, s));
-    std::vector<int> lo(c->nf), hi(c->nf);
-    for (int f = 0; f < c->nf; ++f) {
-      const int origin = c->o.nested ? c->f_lo[c->group_fields[c->group_of[f]].front()] : 0;
-      for (int g = 0; g < c->nf; ++g) {
-        lo[g] = c->f_lo[g] - origin;
-        hi[g] = c->f_hi[g] - origin;
-      }
-      solve::column_fields(c->F[f].lower, c->nf, lo.data(), hi.data(), masks.p + 2 * f, s);
-      solve::column_fields(c->F[f].upperT, c->nf, lo.data(), hi.data(), masks.p + 2 * f + 1, s);
-    }
-    std::vector<int> hm(2 * c->nf);
-    HBGS_HIP(hipMemcpyAsync(hm.data(), masks.p, sizeof(int) * 2 * c->nf, hipMemcpyDeviceToHost, s));
-    HBGS_HIP(hipStreamSynchronize(s));
-    for (int f = 0; f < c->nf; ++f) {
-      c->F[f].deps[0] = (uint32_t)hm[2 * f];
-      c->F[f].deps[1] = (uint32_t)hm[2 * f + 1];
-    }
-  }
-  for (int tr = 0; tr < 2; ++tr) {
-    plan_sweep(c, c->leaf_order, tr, c->plan[tr]);
-    for (Group& g : c->G) plan_sweep(c, g.fields, tr, g.plan[tr]);
-  }
+  field_deps(c, 0, s);
+  plan_sweep(c, c->leaf_order, 0, c->plan[0]);
+  for (Group& g : c->G) plan_sweep(c, g.fields, 0, g.plan[0]);
+  if (c->o.build_transpose) build_rest_T(c, s);
   HBGS_HIP(hipStreamSynchronize(s));
   compute_stats(c);
 }
@@ -1394,9 +1435,27 @@ __global__ void k_gather_vals(int64_t nnz, const double* v, const int* src, doub
 __global__ void k_iota_f64(int64_t nnz, double* p) {
   HBGS_FOR_ALL(k, nnz) p[k] = (double)k;
 }
-// srcT[k] = src[position of A_p^T entry k in A_p]
-__global__ void k_compose(int64_t nnz, const double* pos, const int* src, int* srcT) {
-  HBGS_FOR_ALL(k, nnz) srcT[k] = src[(int64_t)pos[k]];
+__global__ void k_pos_int(int64_t nnz, const double* pos, int* posT) {
+  HBGS_FOR_ALL(k, nnz) posT[k] = (int)pos[k];
+}
+
+// A_p^T's values from A_p's
+static void gather_apt(hbgs_ctx* c, hipStream_t s) {
+  k_gather_vals<<<grid_for(c->nnz, 256), 256, 0, s>>>(c->nnz, c->Ap.v, c->posT, c->ApT.v);
+  HBGS_HIP(hipGetLastError());
+  c->apt_fresh = true;
+}
+
+// Everything a transpose apply or solve reads, built on first use when the
+// options defer it (build_transpose = 0), on the caller's stream.
+static void ensure_transpose(hbgs_ctx* c, hipStream_t s) {
+  if (!c->apt_fresh) gather_apt(c, s);
+  if (c->hier_t) return;
+  ScratchScope scratch(&c->scratch[HBGS_MAX_FIELDS]);
+  StreamScope scope(s);
+  for (Field& F : c->F) build_field_T(c, F, s);
+  build_rest_T(c, s);
+  HBGS_HIP(hipStreamSynchronize(s));
 }
 #undef HBGS_FOR_ALL
 
@@ -1441,6 +1500,7 @@ void hbgs_default_options(hbgs_options* o) {
   o->inner_max_iters = 300;
   o->inner_rtol = 1e-6;
   o->ilu_block = 4096;
+  o->build_transpose = 1;
 }
 
 const char* hbgs_last_error(void) { return g_last_error.c_str(); }
@@ -1547,11 +1607,10 @@ hbgs_status hbgs_setup(hbgs_ctx** out, int32_t n, int64_t nnz, const int32_t* ro
     DCsr idx = c->Ap;
     idx.v = pos.p;
     c->ApT = transpose_new(c->pool, idx, s);
-    c->srcT = c->pool.make<int>(nnz);
-    k_compose<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, c->ApT.v, c->src, c->srcT);
+    c->posT = c->pool.make<int>(nnz);
+    k_pos_int<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, c->ApT.v, c->posT);
     HBGS_HIP(hipGetLastError());
-    k_gather_vals<<<grid_for(nnz, 256), 256, 0, s>>>(nnz, val, c->srcT, c->ApT.v);
-    HBGS_HIP(hipGetLastError());
+    if (c->o.build_transpose) gather_apt(c, s);  // else on first use
   }
   setup::row_stats(c->Ap, s);
   setup::row_stats(c->ApT, s);
@@ -1582,9 +1641,13 @@ hbgs_status hbgs_set_values(hbgs_ctx* c, const double* val, int32_t rebuild_hier
   HBGS_API_BEGIN
   hipStream_t s = (hipStream_t)stream;
   auto t0 = std::chrono::steady_clock::now();
+  // a kept hierarchy keeps its adjoint consistent with it: its transposed
+  // parts are built from the old values before they change
+  if (!rebuild_hierarchy && !c->hier_t) ensure_transpose(c, s);
   k_gather_vals<<<grid_for(c->nnz, 256), 256, 0, s>>>(c->nnz, val, c->src, c->Ap.v);
-  k_gather_vals<<<grid_for(c->nnz, 256), 256, 0, s>>>(c->nnz, val, c->srcT, c->ApT.v);
   HBGS_HIP(hipGetLastError());
+  c->apt_fresh = false;
+  if (c->o.build_transpose) gather_apt(c, s);
   if (rebuild_hierarchy) {
     build_values(c, s);
     c->stats.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -1622,6 +1685,7 @@ hbgs_status hbgs_apply(hbgs_ctx* c, const double* r, double* z, int32_t transpos
   HBGS_API_BEGIN
   hipStream_t s = (hipStream_t)stream;
   ensure_workspace(c);
+  if (transpose) ensure_transpose(c, s);
   Krylov& K = c->K;
   solve::permute_in(c->n, c->perm, r, K.bp, s);
   apply_perm(c, transpose ? 1 : 0, K.bp, 0, s);
@@ -1653,6 +1717,7 @@ hbgs_status hbgs_solve(hbgs_ctx* c, const double* b, double* x, int32_t use_x0, 
   hipStream_t s = c->sm;
   HBGS_HIP(hipEventRecord(c->join_in, us));
   HBGS_HIP(hipStreamWaitEvent(s, c->join_in, 0));
+  if (transpose) ensure_transpose(c, s);
   solve::permute_in(c->n, c->perm, b, c->K.bp, s);
   if (use_x0) solve::permute_in(c->n, c->perm, x, c->K.xp, s);
   hbgs_status st = gmres(c, transpose ? 1 : 0, use_x0, &it, hist, hist_cap, &hl, s);
@@ -1695,6 +1760,7 @@ hbgs_status hbgs_get_level(hbgs_ctx* c, int32_t field, int32_t level, int32_t wh
     return HBGS_EINVAL;
   }
   HBGS_API_BEGIN
+  if (which == 3) ensure_transpose(c, nullptr);
   const Level& L = c->F[field].lv[level];
   bool coarsest = level + 1 == (int)c->F[field].lv.size();
   if ((which == 1 || which == 2) && coarsest) HBGS_FAIL(HBGS_EINVAL, "the coarsest level has no transfer operators");

@@ -296,6 +296,7 @@ void row_stats(DCsr& a, hipStream_t s);
 // DD(0)-ILU(0) of the n x n block a with subdomains of `sub` rows (factors,
 // transposed factors, schedules, FP32 copies); returns -4 on a zero pivot
 int ilu_setup(Pool& pool, const DCsr& a, int sub, IluLeaf& out, hipStream_t s);
+void ilu_transpose(Pool& pool, IluLeaf& leaf, hipStream_t s);
 // builds a.cd / a.cb when every chunk of COL_CHUNK entries fits a 16-bit
 // offset from its smallest column (leaves them null otherwise)
 void pack_columns(Pool& pool, DCsr& a, hipStream_t s);

@@ -2169,16 +2169,21 @@ int ilu_setup(Pool& pool, const DCsr& a, int sub, IluLeaf& out, hipStream_t s) {
   HBGS_HIP(hipMemcpyAsync(&h_zero, zp.p, sizeof(int), hipMemcpyDeviceToHost, s));
   HBGS_HIP(hipStreamSynchronize(s));
   if (h_zero) return -4;
-  out.vT = pool.make<double>(F.nnz);
-  transpose_symmetric(F, out.vT, s);
   F.vf = pool.make<float>(F.nnz);
-  out.vTf = pool.make<float>(F.nnz);
   cast_f32(F.nnz, F.v, F.vf, s);
-  cast_f32(F.nnz, out.vT, out.vTf, s);
   out.yd = pool.make<double>(n);
   out.yf = pool.make<float>(n);
   HBGS_HIP(hipStreamSynchronize(s));
   return 0;
+}
+
+// the factors transposed (same pattern), for the adjoint sweep
+void ilu_transpose(Pool& pool, IluLeaf& leaf, hipStream_t s) {
+  const DCsr& F = leaf.F;
+  leaf.vT = pool.make<double>(F.nnz);
+  transpose_symmetric(F, leaf.vT, s);
+  leaf.vTf = pool.make<float>(F.nnz);
+  cast_f32(F.nnz, leaf.vT, leaf.vTf, s);
 }
 
 // One wavefront per chunk of COL_CHUNK entries.  k_col_base: the chunk's

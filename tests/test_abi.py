@@ -29,6 +29,7 @@ def test_options_defaults_and_struct_layout():
     assert (o.restart, o.max_iters, o.cheb_degree, o.coarse_max) == (50, 2000, 2, 2000)
     assert o.rtol == 1e-8 and o.theta[0] == 0.04 and o.theta[1] == 0.0
     assert abs(o.sa_damping - 4 / 3) < 1e-15
+    assert o.build_transpose == 1 and o.use_graphs == 0 and o.setup_concurrent == 1
 
 
 def test_struct_layouts_match_header(tmp_path):

@@ -518,3 +518,51 @@ def test_config3_j0_gradient_fd(torch_dev):
         assert gj[c] == pytest.approx(fd, rel=1e-3), (c, gj[c], fd)
         assert gj[c] == pytest.approx(tangent, rel=1e-6), (c, gj[c], tangent)
     print(f"max relative error vs FD over 8 cells: {max(errs):.2e}")
+
+
+@pytest.mark.parametrize("case", ["ragged7x5x9_6f_cm40", "cfg0_cm64"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_deferred_transpose_build(torch_dev, case, precision):
+    """build_transpose = 0 defers the adjoint's operators to the first
+    transpose call after each setup or value update: every result equals
+    the eager build's bitwise, through rebuilding and keeping value
+    updates."""
+    torch, dev = torch_dev
+    s = _system(case)
+    cm = CASES[case]["coarse_max"]
+    ge = _solver(torch, dev, s, coarse_max=cm, precision=precision)
+    gl = _solver(torch, dev, s, coarse_max=cm, precision=precision, build_transpose=0)
+    r = torch.from_numpy(np.random.default_rng(12).standard_normal(s.n)).to(dev)
+    b = torch.from_numpy(s.b).to(dev)
+    xt = torch.from_numpy(s.x_t).to(dev)
+
+    def same(tag):
+        assert torch.equal(ge.apply(r), gl.apply(r)), tag
+        xe, ste, ite, he = ge.solve(b)
+        xl, stl, itl, hl = gl.solve(b)
+        assert ste == stl and ite == itl and torch.equal(xe, xl), tag
+        ze, zl = ge.apply(r, transpose=True), gl.apply(r, transpose=True)
+        assert torch.equal(ze, zl), tag
+        le, ste, ite, _ = ge.solve(xt, transpose=True)
+        ll, stl, itl, _ = gl.solve(xt, transpose=True)
+        assert ste == stl == 0 and ite == itl and torch.equal(le, ll), tag
+
+    same("setup")
+    for f in range(s.nf):
+        a, b_ = ge.get_level(f, 0, "AT"), gl.get_level(f, 0, "AT")
+        assert all(np.array_equal(p, q) for p, q in zip(a[:3], b_[:3])), f
+    v2 = torch.from_numpy(s.val * (1.0 + 0.05 * np.random.default_rng(13).random(s.nnz))).to(dev)
+    ge.set_values(v2)
+    gl.set_values(v2)
+    same("rebuild")
+    # a value update that keeps the hierarchy: the deferred adjoint is built
+    # from the kept hierarchy's values, as the eager one was
+    ge2 = _solver(torch, dev, s, coarse_max=cm, precision=precision)
+    gl2 = _solver(torch, dev, s, coarse_max=cm, precision=precision, build_transpose=0)
+    ge2.set_values(v2, rebuild=False)
+    gl2.set_values(v2, rebuild=False)
+    ze, zl = ge2.apply(r, transpose=True), gl2.apply(r, transpose=True)
+    assert torch.equal(ze, zl)
+    le, ste, ite, _ = ge2.solve(xt, transpose=True)
+    ll, stl, itl, _ = gl2.solve(xt, transpose=True)
+    assert ste == stl and ite == itl and torch.equal(le, ll)

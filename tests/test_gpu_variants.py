@@ -157,3 +157,21 @@ def test_leaf_solvers(torch_dev, case, leaf, precision):
     ro = o.solve(s.b)
     assert st == 0 and ro["status"] == 0 and abs(it - ro["iters"]) <= 2
     assert _res(s, x.cpu().numpy(), s.b) <= 1e-8
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_nested_deferred_transpose(torch_dev, case):
+    """The nested form with the adjoint's operators deferred
+    (build_transpose = 0): transposed applies equal the eager build's."""
+    torch, dev = torch_dev
+    import paper_2602_13079_amd as H
+    s = _system(case)
+    cm = CASES[case]["coarse_max"]
+    opt = dict(nested=1, inner_rtol=0.0, inner_max_iters=3, inner_restart=3, coarse_max=cm)
+    args = (torch.from_numpy(s.rowptr).to(dev), torch.from_numpy(s.col).to(dev), torch.from_numpy(s.val).to(dev),
+            torch.from_numpy(s.field_of_row).to(dev), s.nf, _tree(s))
+    ge = H.Solver(*args, **opt)
+    gl = H.Solver(*args, build_transpose=0, **opt)
+    r = torch.from_numpy(np.random.default_rng(14).standard_normal(s.n)).to(dev)
+    assert torch.equal(ge.apply(r), gl.apply(r))
+    assert torch.equal(ge.apply(r, transpose=True), gl.apply(r, transpose=True))
