@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -876,6 +878,13 @@ static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
   F.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
+// hardware queues per process: HIP's GPU_MAX_HW_QUEUES, 4 when unset
+static int hw_queues() {
+  const char* e = std::getenv("GPU_MAX_HW_QUEUES");
+  const int q = e ? std::atoi(e) : 4;
+  return std::max(1, std::min(q, (int)HBGS_MAX_FIELDS));
+}
+
 // which fields each field's coupling rows read, forward (tr = 0: lower) or
 // adjoint (tr = 1: upperT), with column ranges relative to the coupling's
 // own column origin
@@ -939,33 +948,44 @@ static void build_values(hbgs_ctx* c, hipStream_t s) {
     ScratchScope scratch(&c->scratch[HBGS_MAX_FIELDS]);
     for (int f = 0; f < c->nf; ++f) build_field(c, c->F[f], s);
   } else {
+    // One build thread per hardware queue the runtime gives this process
+    // (streams beyond that share queues and would run one after another):
+    // thread 0 works on the caller's stream, the others on their own, and
+    // each takes the next unbuilt field until none is left.
     int dev = 0;
     HBGS_HIP(hipGetDevice(&dev));
+    const int nw = std::min(c->nf, hw_queues());
     if (!c->setup_in) HBGS_HIP(hipEventCreateWithFlags(&c->setup_in, hipEventDisableTiming));
-    for (int f = 0; f < c->nf; ++f)
-      if (!c->sstream[f]) HBGS_HIP(hipStreamCreateWithFlags(&c->sstream[f], hipStreamNonBlocking));
+    for (int w = 1; w < nw; ++w)
+      if (!c->sstream[w]) HBGS_HIP(hipStreamCreateWithFlags(&c->sstream[w], hipStreamNonBlocking));
     HBGS_HIP(hipEventRecord(c->setup_in, s));
     std::vector<int> code(c->nf, HBGS_OK);
     std::vector<std::string> msg(c->nf);
     std::vector<std::thread> th;
-    auto work = [&](int f) {
-      hipStream_t sf = c->sstream[f];
+    std::atomic<int> next{0};
+    auto work = [&](int w) {
+      hipStream_t sw = w == 0 ? s : c->sstream[w];
+      int f = -1;
       try {
         HBGS_HIP(hipSetDevice(dev));
-        HBGS_HIP(hipStreamWaitEvent(sf, c->setup_in, 0));
-        StreamScope scope(sf);
-        ScratchScope scratch(&c->scratch[f]);
-        build_field(c, c->F[f], sf);
+        if (w > 0) HBGS_HIP(hipStreamWaitEvent(sw, c->setup_in, 0));
+        StreamScope scope(sw);
+        ScratchScope scratch(&c->scratch[w]);
+        while ((f = next.fetch_add(1)) < c->nf) build_field(c, c->F[f], sw);
       } catch (const Error& e) {
+        if (f < 0 || f >= c->nf) f = 0;
         code[f] = e.code;
         msg[f] = g_last_error;
+        next.store(c->nf);  // the others stop after their current field
       } catch (const std::exception& e) {
+        if (f < 0 || f >= c->nf) f = 0;
         code[f] = HBGS_EHIP;
         msg[f] = std::string("exception: ") + e.what();
+        next.store(c->nf);
       }
     };
     try {
-      for (int f = 0; f < c->nf; ++f) th.emplace_back(work, f);
+      for (int w = 0; w < nw; ++w) th.emplace_back(work, w);
     } catch (...) {
       for (auto& t : th) t.join();
       throw;
