@@ -213,6 +213,16 @@ struct Profiler {
     HBGS_HIP(hipEventCreate(&e));
     return e;
   }
+  // events for a launch of class k that stamps them itself (null when the
+  // class is not being timed)
+  void stamp(int k, double b, hipEvent_t* e0, hipEvent_t* e1) {
+    *e0 = *e1 = nullptr;
+    if (!on || !(mask >> k & 1u)) return;
+    *e0 = ev();
+    *e1 = ev();
+    pending.push_back({*e0, *e1, k, b});
+    if (pending.size() > 4096) flush();
+  }
   void flush() {
     for (auto& r : pending) {
       HBGS_HIP(hipEventSynchronize(r.b));
@@ -1226,11 +1236,12 @@ static void iteration_body(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, in
   double* w = K.V + (size_t)(j + 1) * ld;
   prec(j, (const double*)vj, s);
   {
-    Prof p(c->prof, s, solve::K_SPMV_OUTER, spmv_bytes(A, 8, c->precision ? 4 : 8, 8, 0));
+    hipEvent_t e0, e1;  // stamped by the dispatch itself when this class is timed
+    c->prof.stamp(solve::K_SPMV_OUTER, spmv_bytes(A, 8, c->precision ? 4 : 8, 8, 0), &e0, &e1);
     if (c->precision == 1)
-      solve::spmv_outer_mixed(A, K.Zf + (size_t)j * ld, w, s);
+      solve::spmv_outer_mixed(A, K.Zf + (size_t)j * ld, w, s, e0, e1);
     else
-      solve::spmv_outer_f64(A, K.Zd + (size_t)j * ld, w, s);
+      solve::spmv_outer_f64(A, K.Zd + (size_t)j * ld, w, s, e0, e1);
   }
   {
     Prof p(c->prof, s, solve::K_DOT1, 8.0 * n * (j + 2));

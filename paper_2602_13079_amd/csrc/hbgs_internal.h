@@ -348,8 +348,11 @@ struct ChebCoef {
 };
 
 // outer SpMV, y = A x with x double or float; resid: y = b - A x
-void spmv_outer_f64(const DCsr& a, const double* x, double* y, hipStream_t s);
-void spmv_outer_mixed(const DCsr& a, const float* x, double* y, hipStream_t s);
+// w = A z; e0/e1 (optional) are stamped with the kernel's start and end
+void spmv_outer_f64(const DCsr& a, const double* x, double* y, hipStream_t s, hipEvent_t e0 = nullptr,
+                    hipEvent_t e1 = nullptr);
+void spmv_outer_mixed(const DCsr& a, const float* x, double* y, hipStream_t s, hipEvent_t e0 = nullptr,
+                      hipEvent_t e1 = nullptr);
 // t = v - a z (FP64 values and result; z FP32 or FP64)
 template <class TZ>
 void couple_f64(const DCsr& a, const double* v, const TZ* z, double* t, hipStream_t s);

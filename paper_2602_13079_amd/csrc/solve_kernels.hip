@@ -7,6 +7,7 @@
 // the partial products are combined with cross-lane shuffles and the row's
 // epilogue (residual, Chebyshev update, transfer accumulation) is fused into
 // the same kernel, so each vector is read and written once per step.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -112,12 +113,20 @@ __global__ __launch_bounds__(SBLK) void k_csr_rows(int n, const int* __restrict_
   }
 }
 
+// e0/e1 (optional): events that the dispatch itself stamps with the
+// kernel's start and end (no extra packets in the stream), for timing one
+// class of launches inside a timed run
 template <class TV, class TACC, class Col, class LoadX, class Epi>
-static void launch_csr_cols(const DCsr& a, Col col, const TV* v, LoadX lx, Epi epi, hipStream_t s) {
+static void launch_csr_cols(const DCsr& a, Col col, const TV* v, LoadX lx, Epi epi, hipStream_t s,
+                            hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   constexpr int cap = ROWS_LDS_BYTES / (int)sizeof(TACC);
 #define HBGS_ROWS(RB)                                                                                      \
   if (a.maxlen > 0 && a.maxlen <= cap / RB) {                                                              \
-    k_csr_rows<RB, TV, TACC, Col, LoadX, Epi><<<(a.n + RB - 1) / RB, SBLK, 0, s>>>(a.n, a.rp, col, v, lx, epi); \
+    if (e0)                                                                                                \
+      hipExtLaunchKernelGGL(k_csr_rows<RB, TV, TACC, Col, LoadX, Epi>, dim3((a.n + RB - 1) / RB), dim3(SBLK), \
+                            0, s, e0, e1, 0, a.n, a.rp, col, v, lx, epi);                                  \
+    else                                                                                                   \
+      k_csr_rows<RB, TV, TACC, Col, LoadX, Epi><<<(a.n + RB - 1) / RB, SBLK, 0, s>>>(a.n, a.rp, col, v, lx, epi); \
     HBGS_HIP(hipGetLastError());                                                                           \
     return;                                                                                                \
   }
@@ -130,9 +139,14 @@ static void launch_csr_cols(const DCsr& a, Col col, const TV* v, LoadX lx, Epi e
   float avg = a.avg_row();
   int lpr = avg <= 1.5f ? 1 : avg <= 3.f ? 2 : avg <= 6.f ? 4 : avg <= 16.f ? 8 : avg <= 64.f ? 16 : avg <= 128.f ? 32 : 64;
   unsigned grid = (unsigned)(((int64_t)a.n * lpr + BLK - 1) / BLK);
-#define HBGS_CASE(L) \
-  case L:            \
-    k_csr<L, TV, TACC, Col, LoadX, Epi><<<grid, BLK, 0, s>>>(a.n, a.rp, col, v, lx, epi); break;
+#define HBGS_CASE(L)                                                                                       \
+  case L:                                                                                                  \
+    if (e0)                                                                                                \
+      hipExtLaunchKernelGGL(k_csr<L, TV, TACC, Col, LoadX, Epi>, dim3(grid), dim3(BLK), 0, s, e0, e1, 0, a.n, \
+                            a.rp, col, v, lx, epi);                                                        \
+    else                                                                                                   \
+      k_csr<L, TV, TACC, Col, LoadX, Epi><<<grid, BLK, 0, s>>>(a.n, a.rp, col, v, lx, epi);                \
+    break;
   switch (lpr) {
     HBGS_CASE(1)
     HBGS_CASE(2)
@@ -147,17 +161,20 @@ static void launch_csr_cols(const DCsr& a, Col col, const TV* v, LoadX lx, Epi e
 }
 
 template <class TV, class TACC, class LoadX, class Epi>
-static void launch_csr(const DCsr& a, const TV* v, LoadX lx, Epi epi, hipStream_t s) {
+static void launch_csr(const DCsr& a, const TV* v, LoadX lx, Epi epi, hipStream_t s, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr) {
   if (a.n == 0) return;
   if (a.nnz == 0) {  // rows without entries: epilogue of an empty sum
+    if (e0) HBGS_HIP(hipEventRecord(e0, s));
     k_empty<TACC, Epi><<<grid_for(a.n, 256), 256, 0, s>>>(a.n, epi);
     HBGS_HIP(hipGetLastError());
+    if (e1) HBGS_HIP(hipEventRecord(e1, s));
     return;
   }
   if (a.cd)
-    launch_csr_cols<TV, TACC>(a, ColPacked{a.cd, a.cb}, v, lx, epi, s);
+    launch_csr_cols<TV, TACC>(a, ColPacked{a.cd, a.cb}, v, lx, epi, s, e0, e1);
   else
-    launch_csr_cols<TV, TACC>(a, ColPlain{a.ci}, v, lx, epi, s);
+    launch_csr_cols<TV, TACC>(a, ColPlain{a.ci}, v, lx, epi, s, e0, e1);
 }
 
 // operand loaders
@@ -305,11 +322,11 @@ struct EpiSubFrom {
 };
 
 // ---------------------------------------------------------- outer SpMV
-void spmv_outer_f64(const DCsr& a, const double* x, double* y, hipStream_t s) {
-  launch_csr<double, double>(a, a.v, LoadArr<double>{x}, EpiStore<double, double>{y}, s);
+void spmv_outer_f64(const DCsr& a, const double* x, double* y, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  launch_csr<double, double>(a, a.v, LoadArr<double>{x}, EpiStore<double, double>{y}, s, e0, e1);
 }
-void spmv_outer_mixed(const DCsr& a, const float* x, double* y, hipStream_t s) {
-  launch_csr<double, double>(a, a.v, LoadArr<float>{x}, EpiStore<double, double>{y}, s);
+void spmv_outer_mixed(const DCsr& a, const float* x, double* y, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  launch_csr<double, double>(a, a.v, LoadArr<float>{x}, EpiStore<double, double>{y}, s, e0, e1);
 }
 template <class TZ>
 void couple_f64(const DCsr& a, const double* v, const TZ* z, double* t, hipStream_t s) {
