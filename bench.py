@@ -124,8 +124,9 @@ def main():
                 f"{v['bytes'] / max(v['ms'], 1e-9) / 1e6:8.1f} GB/s")
 
     # timed region.  Every launch of the dominant class in the mixed solves
-    # is bracketed by HIP events on the stream it runs on (two event records
-    # per launch; the other classes are not timed)
+    # is timed with HIP events on the stream it runs on (stamped by the
+    # dispatch for the outer SpMV, event records around it otherwise); the
+    # other classes are not timed
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rs = [step(prof_kinds=[dominant]) for _ in range(args.steps)]
