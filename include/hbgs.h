@@ -75,9 +75,12 @@ typedef struct {
                             kernel timing is on).  A value update drops the graphs.
                             0 (default): launch kernels one by one */
   int32_t setup_concurrent; /* 1 (default): the fields' blocks and hierarchies are
-                               built concurrently, one host thread and HIP stream per
-                               field (the results do not depend on it); 0: one after
-                               another on the caller's stream */
+                               built concurrently by one host thread per hardware
+                               queue of the process (HIP's GPU_MAX_HW_QUEUES, 4 when
+                               unset), each on its own stream (the first on the
+                               caller's) taking the next unbuilt field; the results
+                               do not depend on it.  0: one after another on the
+                               caller's stream */
   int32_t block_jacobi;  /* 1: every coupling block is dropped, each field is solved on
                             its own (block Jacobi; all fields run concurrently); 0
                             (default): block Gauss-Seidel */
@@ -223,12 +226,13 @@ int32_t hbgs_kernel_times(hbgs_ctx *ctx, char (*names)[48], double *total_ms, in
  * framework's caching allocator: alloc(bytes, user) returns device memory of
  * the current device or NULL (setup then fails with HBGS_ENOMEM);
  * free(ptr, user) releases it.  alloc may be called from the library's setup
- * threads (one per field) concurrently.  NULL for both restores hipMalloc /
- * hipFree.  Each allocation is freed with the hook that made it, so the hook
- * may change while contexts are alive; setup temporaries stay with HIP's
- * stream-ordered allocator (whose default pool hbgs_setup lets keep freed
- * memory, so that rebuilds recycle it).  Returns HBGS_EINVAL if exactly one of the two is
- * NULL.  Process-wide; not to be called concurrently with hbgs_setup. */
+ * threads concurrently.  NULL for both restores hipMalloc / hipFree.  Each
+ * allocation is freed with the hook that made it, so the hook may change while
+ * contexts are alive.  The chunks of the setup threads' scratch stacks (kept
+ * for rebuilds until the context is destroyed) come from the hook too; the
+ * few temporaries of hbgs_setup's pattern phase use HIP's stream-ordered
+ * allocator.  Returns HBGS_EINVAL if exactly one of the two is NULL.
+ * Process-wide; not to be called concurrently with hbgs_setup. */
 hbgs_status hbgs_set_allocator(void *(*alloc)(size_t bytes, void *user), void (*free)(void *ptr, void *user),
                                void *user);
 

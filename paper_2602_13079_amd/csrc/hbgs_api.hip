@@ -1552,8 +1552,9 @@ hbgs_status hbgs_setup(hbgs_ctx** out, int32_t n, int64_t nnz, const int32_t* ro
   if (n_fields < 1 || n_fields > HBGS_MAX_FIELDS) HBGS_FAIL(HBGS_EINVAL, "n_fields out of range");
   if (!rowptr || !col || !val || !field_of_row || !group_tree) HBGS_FAIL(HBGS_EINVAL, "NULL argument");
   {
-    // setup temporaries come from HIP's default stream-ordered pool: let it
-    // keep freed memory so that rebuilds recycle it instead of reallocating
+    // the pattern phase's temporaries (before the build threads' scratch
+    // stacks exist) come from HIP's default stream-ordered pool: let it keep
+    // freed memory instead of returning it to the device
     int dev = 0;
     hipMemPool_t mp = nullptr;
     if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&mp, dev) == hipSuccess && mp) {
