@@ -1641,127 +1641,184 @@ constexpr int LU_PT = 1024;
 constexpr int LU_R = 2;
 constexpr int LU_MAXN = LU_PT * LU_R;
 
+constexpr int LU_CH = 256;  // panel rows per staging pass through LDS
+
+// Register-only (DPP) reductions within rows of 16 lanes; all 64 lanes must
+// be active.  Every lane of a 16-lane row ends with the row's result: pairs
+// within quads (quad_perm [1,0,3,2] and [2,3,0,1]), then quads (rotate right
+// by 4 and by 8 lanes).  A lane whose source is unavailable keeps its own
+// value (old = own).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = (int)bits, hi = (int)(bits >> 32);
+  const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xF, 0xF, false);
+  const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)ohi << 32) | (unsigned int)olo);
+}
+__device__ __forceinline__ double max_row16(double v) {
+  v = fmax(v, dpp_f64<0xB1>(v));
+  v = fmax(v, dpp_f64<0x4E>(v));
+  v = fmax(v, dpp_f64<0x124>(v));
+  return fmax(v, dpp_f64<0x128>(v));
+}
+__device__ __forceinline__ int min_row16(int r) {
+  r = min(r, __builtin_amdgcn_update_dpp(r, r, 0xB1, 0xF, 0xF, false));
+  r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x4E, 0xF, 0xF, false));
+  r = min(r, __builtin_amdgcn_update_dpp(r, r, 0x124, 0xF, 0xF, false));
+  return min(r, __builtin_amdgcn_update_dpp(r, r, 0x128, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)bits, lane), hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// the wavefront's maximum (uniform); fmax passes over NaN
+__device__ __forceinline__ double wave_max(double v) {
+  v = max_row16(v);
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)), fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+__device__ __forceinline__ int wave_min(int r) {
+  r = min_row16(r);
+  return min(min(__builtin_amdgcn_readlane(r, 0), __builtin_amdgcn_readlane(r, 16)),
+             min(__builtin_amdgcn_readlane(r, 32), __builtin_amdgcn_readlane(r, 48)));
+}
+
+// The panel's rows move between memory and registers through LDS in passes
+// of LU_CH rows, so that consecutive lanes touch consecutive columns of a row
+// (a row's LU_NB values are one contiguous run) rather than one row each.
+// Each column's pivot search runs in registers (DPP within 16-lane rows,
+// lane reads across rows) and needs one barrier to combine the wavefronts.
 __global__ __launch_bounds__(LU_PT) void k_lu_panel(int n, int k0, double* m, int* piv, int* singular) {
-  // per-column exchange buffers, alternating between consecutive columns so
-  // that one barrier per hand-over suffices
-  __shared__ double wv[2][LU_PT / 64];
-  __shared__ int wi[2][LU_PT / 64];
-  __shared__ double prow[2][LU_NB], xrow[2][LU_NB];
+  static_assert(LU_PT / 64 <= 16, "the wavefronts' candidates are combined within one 16-lane row");
+  const int PT = blockDim.x, NW = PT / 64;  // a multiple of 64, at least half the rows
+  __shared__ double stage[LU_CH][LU_NB + 1];
+  // per column: each wavefront's pivot candidate (|value|, row, the row's
+  // values) and row j before the interchange; two sets, used by alternate
+  // columns, so one barrier per column suffices
+  __shared__ double cv[2][LU_PT / 64];
+  __shared__ int cr[2][LU_PT / 64];
+  __shared__ double crow[2][LU_PT / 64][LU_NB];
+  __shared__ double xrow[2][LU_NB];
   const int rows = n - k0, nb = min(LU_NB, n - k0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double a[LU_R][LU_NB];
 #pragma unroll
-  for (int q = 0; q < LU_R; ++q) {
-    const int r = tid + q * LU_PT;
+  for (int q = 0; q < LU_R; ++q)
 #pragma unroll
-    for (int t = 0; t < LU_NB; ++t) a[q][t] = (r < rows && t < nb) ? m[(int64_t)(k0 + r) * n + k0 + t] : 0.0;
+    for (int t = 0; t < LU_NB; ++t) a[q][t] = 0.0;
+  for (int c0 = 0; c0 < rows; c0 += LU_CH) {
+    const int ce = min(LU_CH, rows - c0) * LU_NB;
+    for (int e = tid; e < ce; e += PT) {
+      const int i = e / LU_NB, t = e % LU_NB;
+      stage[i][t] = t < nb ? m[(int64_t)(k0 + c0 + i) * n + k0 + t] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < LU_R; ++q) {
+      const int r = tid + q * PT;
+      if (r >= c0 && r < c0 + LU_CH && r < rows)
+#pragma unroll
+        for (int t = 0; t < LU_NB; ++t) a[q][t] = stage[r - c0][t];
+    }
+    __syncthreads();
   }
-  bool failed = false;
 #pragma unroll
   for (int j = 0; j < LU_NB; ++j) {
     const int b = j & 1;
-    if (j >= nb || failed) continue;  // uniform across the block
-    // pivot: largest |a_rj| over r >= j, first index on ties
+    if (j >= nb) break;  // uniform across the block
+    // this wavefront's candidate: the largest |a_rj| over its rows r >= j,
+    // then the first of its rows holding that value (two branch-free
+    // reductions; NaN is never chosen)
     double best = -1.0;
+#pragma unroll
+    for (int q = 0; q < LU_R; ++q) {
+      const int r = tid + q * PT;
+      if (r >= j && r < rows) best = fmax(best, fabs(a[q][j]));
+    }
+    best = wave_max(best);
     int bi = INT32_MAX;
 #pragma unroll
     for (int q = 0; q < LU_R; ++q) {
-      const int r = tid + q * LU_PT;
-      if (r >= j && r < rows) {
-        const double v = fabs(a[q][j]);
-        if (v > best) {
-          best = v;
-          bi = r;
-        }
-      }
+      const int r = tid + q * PT;
+      if (r >= j && r < rows && fabs(a[q][j]) == best) bi = min(bi, r);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ov > best || (ov == best && oi < bi)) {
-        best = ov;
-        bi = oi;
-      }
-    }
+    bi = wave_min(bi);
     if (lane == 0) {
-      wv[b][wave] = best;
-      wi[b][wave] = bi;
+      cv[b][wave] = best;
+      cr[b][wave] = bi;
     }
+#pragma unroll
+    for (int q = 0; q < LU_R; ++q) {
+      const int r = tid + q * PT;
+      if (r == bi)
+#pragma unroll
+        for (int t = 0; t < LU_NB; ++t) crow[b][wave][t] = a[q][t];
+    }
+    if (tid == j)  // row j lives in a[0] of thread j (j < LU_NB <= PT)
+#pragma unroll
+      for (int t = 0; t < LU_NB; ++t) xrow[b][t] = a[0][t];
     __syncthreads();
-    // every wavefront combines the per-wave candidates itself
-    constexpr int NW = LU_PT / 64;
-    best = lane < NW ? wv[b][lane] : -1.0;
-    bi = lane < NW ? wi[b][lane] : INT32_MAX;
-    for (int off = NW / 2; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(best, off, 64);
-      const int oi = __shfl_xor(bi, off, 64);
-      if (ov > best || (ov == best && oi < bi)) {
-        best = ov;
-        bi = oi;
-      }
-    }
-    best = __shfl(best, 0, 64);
-    const int p = __shfl(bi, 0, 64);
-    if (tid == 0) {
-      if (best > 0.0)
-        piv[k0 + j] = k0 + p;
-      else
-        *singular = 1;
+    // lanes 0..NW-1 of every wavefront hold the wavefronts' candidates
+    {
+      const double cvl = lane < NW ? cv[b][lane] : -1.0;
+      const int crl = lane < NW ? cr[b][lane] : INT32_MAX;
+      best = readlane_f64(max_row16(cvl), 0);
+      bi = __builtin_amdgcn_readlane(min_row16(cvl == best ? crl : INT32_MAX), 0);
     }
     if (!(best > 0.0)) {  // uniform: the factorisation has failed
-      failed = true;
-      continue;
+      if (tid == 0) *singular = 1;
+      return;
     }
-    // interchange panel rows j and p; the pivot row goes to prow
+    const int p = bi;
+    if (tid == 0) piv[k0 + j] = k0 + p;
+    const double* prow = crow[b][(p % PT) / 64];  // the pivot row (LDS)
+    // interchange rows j and p
 #pragma unroll
     for (int q = 0; q < LU_R; ++q) {
-      const int r = tid + q * LU_PT;
-      if (r == p)
-#pragma unroll
-        for (int t = 0; t < LU_NB; ++t) prow[b][t] = a[q][t];
+      const int r = tid + q * PT;
       if (r == j)
 #pragma unroll
-        for (int t = 0; t < LU_NB; ++t) xrow[b][t] = a[q][t];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < LU_R; ++q) {
-      const int r = tid + q * LU_PT;
-      if (r == j)
-#pragma unroll
-        for (int t = 0; t < LU_NB; ++t) a[q][t] = prow[b][t];
+        for (int t = 0; t < LU_NB; ++t) a[q][t] = prow[t];
       else if (r == p)
 #pragma unroll
         for (int t = 0; t < LU_NB; ++t) a[q][t] = xrow[b][t];
     }
     // multipliers and the update of the panel's remaining columns
-    const double d = prow[b][j];
+    const double d = prow[j];
 #pragma unroll
     for (int q = 0; q < LU_R; ++q) {
-      const int r = tid + q * LU_PT;
+      const int r = tid + q * PT;
       if (r > j && r < rows) {
         const double l = a[q][j] / d;
         a[q][j] = l;
 #pragma unroll
         for (int t = 0; t < LU_NB; ++t)
-          if (t > j) a[q][t] -= l * prow[b][t];
+          if (t > j) a[q][t] -= l * prow[t];
       }
     }
   }
-  if (failed) return;
+  for (int c0 = 0; c0 < rows; c0 += LU_CH) {
 #pragma unroll
-  for (int q = 0; q < LU_R; ++q) {
-    const int r = tid + q * LU_PT;
-    if (r < rows)
+    for (int q = 0; q < LU_R; ++q) {
+      const int r = tid + q * PT;
+      if (r >= c0 && r < c0 + LU_CH && r < rows)
 #pragma unroll
-      for (int t = 0; t < LU_NB; ++t)
-        if (t < nb) m[(int64_t)(k0 + r) * n + k0 + t] = a[q][t];
+        for (int t = 0; t < LU_NB; ++t) stage[r - c0][t] = a[q][t];
+    }
+    __syncthreads();
+    const int ce = min(LU_CH, rows - c0) * LU_NB;
+    for (int e = tid; e < ce; e += PT) {
+      const int i = e / LU_NB, t = e % LU_NB;
+      if (t < nb) m[(int64_t)(k0 + c0 + i) * n + k0 + t] = stage[i][t];
+    }
+    __syncthreads();
   }
 }
 
 // every column outside the panel: the panel's interchanges; trailing
 // columns also get U12 = L11^-1 A12 (L11 unit lower).  The interchanges,
-// applied in order, move values among at most 2 LU_NB rows: one thread
+// applied in order, move values among at most 2 LU_NB rows: one wavefront
 // works out where each of those rows takes its value from, then every
 // column gathers them at once (no chain of dependent swaps) and solves in
 // registers with L11 from LDS.
@@ -1769,25 +1826,37 @@ __global__ __launch_bounds__(BLK) void k_lu_swap_trsm(int n, int k0, int nb, dou
   __shared__ int dst[2 * LU_NB], src[2 * LU_NB];
   __shared__ int nrow;
   __shared__ double sl[LU_NB][LU_NB + 1];
-  if (threadIdx.x == 0) {
-    int cnt = nb;  // the panel rows first, then the other rows met
-    for (int t = 0; t < nb; ++t) dst[t] = src[t] = k0 + t;
+  // The walk over the interchanges runs in the registers of wavefront 0
+  // (all 64 lanes active): lane e holds slot e's (dst, src), the panel rows
+  // first, then each other row as it is met; a row's slot is found by a
+  // ballot and two slots' sources are swapped through lane reads.
+  static_assert(2 * LU_NB <= 64, "one slot per lane");
+  if (threadIdx.x < 64) {
+    const int e = threadIdx.x;
+    const int mp = e < nb ? piv[k0 + e] : 0;
+    int d = e < nb ? k0 + e : -1, sr = d;
+    int cnt = nb;
     for (int t = 0; t < nb; ++t) {
-      const int p = piv[k0 + t];
+      const int p = __builtin_amdgcn_readlane(mp, t);
       if (p > k0 + t && p < n) {
-        int q = -1;
-        for (int e = 0; e < cnt; ++e)
-          if (dst[e] == p) q = e;
-        if (q < 0) {
+        const unsigned long long hit = __ballot(d == p);  // at most one slot holds row p
+        int q;
+        if (hit) {
+          q = __ffsll(hit) - 1;
+        } else {
           q = cnt++;
-          dst[q] = src[q] = p;
+          if (e == q) d = sr = p;
         }
-        const int x = src[t];
-        src[t] = src[q];
-        src[q] = x;
+        const int st = __builtin_amdgcn_readlane(sr, t), sq = __builtin_amdgcn_readlane(sr, q);
+        if (e == t) sr = sq;
+        if (e == q) sr = st;
       }
     }
-    nrow = cnt;
+    if (e < 2 * LU_NB) {
+      dst[e] = d;
+      src[e] = sr;
+    }
+    if (e == 0) nrow = cnt;
   }
   for (int e = threadIdx.x; e < LU_NB * LU_NB; e += BLK) {
     const int r = e / LU_NB, u = e % LU_NB;
@@ -1807,7 +1876,7 @@ __global__ __launch_bounds__(BLK) void k_lu_swap_trsm(int n, int k0, int nb, dou
         if (t < nb) {
           double s = v[t];
 #pragma unroll
-          for (int u = 0; u < t; ++u) s -= sl[t][u] * v[u];
+          for (int u = 0; u < t; ++u) s = fma(-sl[t][u], v[u], s);
           v[t] = s;
         }
         __builtin_amdgcn_sched_barrier(0);  // keep the LDS reads row by row (registers)
@@ -1819,7 +1888,7 @@ __global__ __launch_bounds__(BLK) void k_lu_swap_trsm(int n, int k0, int nb, dou
   }
 }
 
-// A22 -= L21 U12 in tiles of 32 rows x 64 columns
+// A22 -= L21 U12 in tiles of 32 rows x 64 columns (fused multiply-adds)
 __global__ __launch_bounds__(BLK) void k_lu_gemm(int n, int k0, int nb, double* m) {
   __shared__ double sL[32][LU_NB];
   __shared__ double sU[LU_NB][64];
@@ -1841,7 +1910,7 @@ __global__ __launch_bounds__(BLK) void k_lu_gemm(int n, int k0, int nb, double* 
     if (i >= n) break;
     double acc = 0.0;
 #pragma unroll
-    for (int t = 0; t < LU_NB; ++t) acc += sL[ib + u][t] * sU[t][jj];
+    for (int t = 0; t < LU_NB; ++t) acc = fma(sL[ib + u][t], sU[t][jj], acc);
     m[(int64_t)i * n + c0 + jj] -= acc;
   }
 }
@@ -1900,7 +1969,7 @@ __global__ __launch_bounds__(BLK) void k_inv_trsm(int n, int kb, int nb, const d
   }
 }
 // X[i, :] -= F[i, kb..kb+nb) X[kb..kb+nb, :] for rows i in [r_lo, r_hi), in
-// tiles of 32 rows x 64 columns
+// tiles of 32 rows x 64 columns (fused multiply-adds, like the block solves)
 __global__ __launch_bounds__(BLK) void k_inv_update(int n, int kb, int nb, int r_lo, int r_hi, const double* f,
                                                     double* x) {
   __shared__ double sF[32][INV_NB];
@@ -1923,7 +1992,7 @@ __global__ __launch_bounds__(BLK) void k_inv_update(int n, int kb, int nb, int r
     if (i >= r_hi) break;
     double acc = 0.0;
 #pragma unroll
-    for (int t = 0; t < INV_NB; ++t) acc += sF[ib + u][t] * sX[t][jj];
+    for (int t = 0; t < INV_NB; ++t) acc = fma(sF[ib + u][t], sX[t][jj], acc);
     x[(int64_t)i * n + c0 + jj] -= acc;
   }
 }
@@ -1940,7 +2009,10 @@ int dense_inverse(const DCsr& a, double* inv, hipStream_t s) {
     HBGS_HIP(hipGetLastError());
     for (int k0 = 0; k0 < n; k0 += LU_NB) {
       const int nb = std::min(LU_NB, n - k0);
-      k_lu_panel<<<1, LU_PT, 0, s>>>(n, k0, m.p, piv.p, sing.p);
+      // as many wavefronts as the panel's rows need (LU_R rows per thread):
+      // every wavefront runs each column's pivot search, so fewer is faster
+      const int pt = std::min(LU_PT, std::max(64, ((n - k0 + LU_R - 1) / LU_R + 63) / 64 * 64));
+      k_lu_panel<<<1, pt, 0, s>>>(n, k0, m.p, piv.p, sing.p);
       if (n - nb > 0) k_lu_swap_trsm<<<(n - nb + BLK - 1) / BLK, BLK, 0, s>>>(n, k0, nb, m.p, piv.p);
       const int rest = n - k0 - nb;
       if (rest > 0) k_lu_gemm<<<dim3((rest + 63) / 64, (rest + 31) / 32), BLK, 0, s>>>(n, k0, nb, m.p);
