@@ -644,42 +644,47 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // Givens rotation update of Hessenberg column j (H is (m+1) x m, row-major
-// with leading dimension m) by one thread.  h1/h2: first and second
-// Gram-Schmidt coefficients (k <= j); h2[j+1] = ||w||^2 after the first
-// pass; h1[j+1] = ||w||^2 before orthogonalisation.  scal (device) and
-// host_scal (pinned host memory) receive |g_{j+1}|, h_{j+1,j} and ||w||.
-__device__ void givens_update(const GivensArgs& ga, const double* h2) {
-  const int j = ga.j, m = ga.m;
-  double* H = ga.H;
-  for (int k = 0; k <= j; ++k) H[(size_t)k * m + j] = ga.h1[k] + h2[k];
+// with leading dimension m) by one thread, on a copy of the column in LDS:
+// col[k] = h1[k] + h2[k] (k <= j) on entry; the earlier rotations' cosines
+// and sines in cs/sn (LDS).  h1/h2: first and second Gram-Schmidt
+// coefficients; h2[j+1] = ||w||^2 after the first pass; ga.h1[j+1] = ||w||^2
+// before orthogonalisation.  On exit col[0..j+1] is the rotated column;
+// scal (device) and host_scal (pinned host memory) receive |g_{j+1}|,
+// h_{j+1,j} and ||w||.
+__device__ void givens_update(const GivensArgs& ga, const double* h2, double* col, const double* cs,
+                              const double* sn) {
+  const int j = ga.j;
   // ||w - V h2||^2 = ||w||^2 - ||h2||^2 for orthonormal V
   double ss = h2[j + 1];
   for (int k = 0; k <= j; ++k) ss -= h2[k] * h2[k];
-  double hn = ss > 0.0 ? sqrt(ss) : 0.0;
-  H[(size_t)(j + 1) * m + j] = hn;
+  const double hn = ss > 0.0 ? sqrt(ss) : 0.0;
+  col[j + 1] = hn;
+  // the rotated entry k+1 is carried in a register to the next rotation
+  double a = col[0];
   for (int k = 0; k < j; ++k) {
-    double a = H[(size_t)k * m + j], b = H[(size_t)(k + 1) * m + j];
-    H[(size_t)k * m + j] = ga.cs[k] * a + ga.sn[k] * b;
-    H[(size_t)(k + 1) * m + j] = -ga.sn[k] * a + ga.cs[k] * b;
+    const double b = col[k + 1];
+    col[k] = cs[k] * a + sn[k] * b;
+    a = -sn[k] * a + cs[k] * b;
   }
-  double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
-  double den = sqrt(a * a + b * b);
-  ga.cs[j] = a / den;
-  ga.sn[j] = b / den;
-  H[(size_t)j * m + j] = den;
-  H[(size_t)(j + 1) * m + j] = 0.0;
-  ga.g[j + 1] = -ga.sn[j] * ga.g[j];
-  ga.g[j] = ga.cs[j] * ga.g[j];
-  const double est = fabs(ga.g[j + 1]), w0 = sqrt(ga.h1[j + 1]);
+  const double b = hn;
+  const double den = sqrt(a * a + b * b);
+  const double c = a / den, sj = b / den;
+  ga.cs[j] = c;
+  ga.sn[j] = sj;
+  col[j] = den;
+  col[j + 1] = 0.0;
+  const double gj = ga.g[j];
+  ga.g[j + 1] = -sj * gj;
+  ga.g[j] = c * gj;
+  const double est = fabs(-sj * gj), w0 = sqrt(ga.h1[j + 1]);
   ga.scal[0] = est;
   ga.scal[1] = hn;
   ga.scal[2] = w0;
   if (ga.host_scal) {  // the estimate last: the host polls it
     ga.host_scal[1] = hn;
     ga.host_scal[2] = w0;
-    __threadfence_system();
-    ga.host_scal[0] = est;
-    __threadfence_system();
+    __threadfence_system();  // orders the two values before the estimate
+    ga.host_scal[0] = est;   // no wait for its arrival: the thread has nothing left to do
   }
 }
 
@@ -763,13 +768,22 @@ void mdot_reduce(int nvec, int nblocks, const double* part, double* out, hipStre
 }
 
 // one block: out[k] = sum over blocks of part[k*nb + b] for k < nvec (one
-// wave per vector, fixed order), then the Givens update from out
+// wave per vector, fixed order), then the Givens update from out.  The
+// column's first-pass coefficients and the earlier rotations are read by
+// many threads at once into LDS, so the one thread's sequential update
+// waits on no global loads.
 constexpr int RG_BLK = 1024;
 constexpr int RG_MAXV = 66;
 __global__ __launch_bounds__(RG_BLK) void k_reduce_givens(int nvec, int nb, const double* __restrict__ part,
                                                           double* __restrict__ out, GivensArgs ga) {
-  __shared__ double red[RG_MAXV];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __shared__ double red[RG_MAXV], col[RG_MAXV], scs[RG_MAXV], ssn[RG_MAXV];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int j = ga.j;
+  const double h1 = tid <= j ? ga.h1[tid] : 0.0;
+  if (tid < j) {
+    scs[tid] = ga.cs[tid];
+    ssn[tid] = ga.sn[tid];
+  }
   for (int k = wave; k < nvec; k += RG_BLK / 64) {
     const double* p = part + (size_t)k * nb;
     double a = 0.0;
@@ -778,8 +792,12 @@ __global__ __launch_bounds__(RG_BLK) void k_reduce_givens(int nvec, int nb, cons
     if (lane == 0) red[k] = a;
   }
   __syncthreads();
-  if ((int)threadIdx.x < nvec) out[threadIdx.x] = red[threadIdx.x];
-  if (threadIdx.x == 0) givens_update(ga, red);
+  if (tid < nvec) out[tid] = red[tid];
+  if (tid <= j) col[tid] = h1 + red[tid];
+  __syncthreads();
+  if (tid == 0) givens_update(ga, red, col, scs, ssn);
+  __syncthreads();
+  if (tid <= j + 1) ga.H[(size_t)tid * ga.m + j] = col[tid];
 }
 
 void cgs_dots(int n, int j, const double* V, size_t ldv, const double* w, double* part, hipStream_t s) {
@@ -812,16 +830,32 @@ void upd_scale(int n, int j, const double* V, size_t ldv, double* w, const doubl
   HBGS_HIP(hipGetLastError());
 }
 
-__global__ void k_backsolve(int jend, int m, const double* H, const double* g, double* y) {
-  if (threadIdx.x != 0) return;
-  for (int i = jend - 1; i >= 0; --i) {
-    double s = g[i];
-    for (int k = i + 1; k < jend; ++k) s -= H[(size_t)i * m + k] * y[k];
-    y[i] = s / H[(size_t)i * m + i];
+// y = R^-1 g with R the leading jend x jend upper triangle of H: the block
+// stages R and g in LDS, then one thread substitutes backwards (no global
+// loads inside the dependent chain)
+constexpr int BS_MAX = 64;
+__global__ __launch_bounds__(BLK) void k_backsolve(int jend, int m, const double* __restrict__ H,
+                                                   const double* __restrict__ g, double* __restrict__ y) {
+  __shared__ double sr[BS_MAX][BS_MAX + 1];
+  __shared__ double sy[BS_MAX], sg[BS_MAX];
+  for (int e = threadIdx.x; e < jend * jend; e += BLK) {
+    const int i = e / jend, k = e % jend;
+    if (k >= i) sr[i][k] = H[(size_t)i * m + k];
   }
+  if ((int)threadIdx.x < jend) sg[threadIdx.x] = g[threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int i = jend - 1; i >= 0; --i) {
+      double t = sg[i];
+      for (int k = i + 1; k < jend; ++k) t -= sr[i][k] * sy[k];
+      sy[i] = t / sr[i][i];
+    }
+  __syncthreads();
+  if ((int)threadIdx.x < jend) y[threadIdx.x] = sy[threadIdx.x];
 }
 void backsolve(int jend, int m, const double* H, const double* g, double* y, hipStream_t s) {
-  k_backsolve<<<1, 64, 0, s>>>(jend, m, H, g, y);
+  if (jend > BS_MAX) HBGS_FAIL(HBGS_EINVAL, "least-squares system too large");
+  k_backsolve<<<1, BLK, 0, s>>>(jend, m, H, g, y);
   HBGS_HIP(hipGetLastError());
 }
 
