@@ -109,9 +109,9 @@ constexpr int ROWS_LDS_BYTES = 16384;
 static bool g_vec_entries = true;  // grouped entry loads where the arrays are aligned
 
 // vec: the entry stream in groups of four (16-byte value and 16/8-byte
-// column loads) over the block's 4-aligned entries, single entries at the two
-// ends; else two single entries per step.  The products and their summation
-// order are the same either way.
+// column loads) over the block's 4-aligned entries, two groups per step,
+// single entries at the two ends; else two single entries per step.  The
+// products and their summation order are the same either way.
 template <int RB, class TV, class TACC, class Col, class LoadX, class Epi>
 __global__ __launch_bounds__(SBLK) void k_csr_rows(int n, const int* __restrict__ rp, Col ci,
                                                    const TV* __restrict__ v, LoadX lx, Epi epi, int vec) {
@@ -132,19 +132,39 @@ __global__ __launch_bounds__(SBLK) void k_csr_rows(int n, const int* __restrict_
   const int a0 = (s0 + 3) & ~3, a1 = s1 & ~3;  // the 4-aligned middle
   if (vec && a0 < a1) {
     const int t = (int)threadIdx.x;
-    if (s0 + t < a0) prod[t] = (TACC)v[s0 + t] * (TACC)lx(ci(s0 + t));
-    if (a1 + t < s1) prod[a1 + t - s0] = (TACC)v[a1 + t] * (TACC)lx(ci(a1 + t));
-    for (int k4 = a0 + 4 * t; k4 < a1; k4 += 4 * SBLK) {
-      TV w[4];
-      int c[4];
-      load4(v + k4, w);
-      ci.load4(k4, c);
-      TACC xv[4];
+    // the (at most 3 + 3) entries outside the 4-aligned middle: values and
+    // columns requested first, operands gathered after the middle's, so
+    // they add no round trip ahead of it (indices clamped into the block)
+    const bool hh = s0 + t < a0, ht = a1 + t < s1;
+    const int kh = hh ? s0 + t : a0, kt = ht ? a1 + t : a1 - 1;
+    const TV vh = v[kh], vt = v[kt];
+    const int ch = ci(kh), ct = ci(kt);
+    // two groups of four per step, both requested before either is used
+    // (a thread without a second group re-reads its first)
+    for (int k4 = a0 + 4 * t; k4 < a1; k4 += 8 * SBLK) {
+      const int k4b = k4 + 4 * SBLK;
+      const bool two = k4b < a1;
+      const int kb = two ? k4b : k4;
+      TV w0[4], w1[4];
+      int c0[4], c1[4];
+      load4(v + k4, w0);
+      ci.load4(k4, c0);
+      load4(v + kb, w1);
+      ci.load4(kb, c1);
+      TACC x0[4], x1[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) xv[q] = (TACC)lx(c[q]);
+      for (int q = 0; q < 4; ++q) x0[q] = (TACC)lx(c0[q]);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) prod[k4 + q - s0] = (TACC)w[q] * xv[q];
+      for (int q = 0; q < 4; ++q) x1[q] = (TACC)lx(c1[q]);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) prod[k4 + q - s0] = (TACC)w0[q] * x0[q];
+      if (two)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) prod[k4b + q - s0] = (TACC)w1[q] * x1[q];
     }
+    const TACC xh = (TACC)lx(ch), xt = (TACC)lx(ct);
+    if (hh) prod[kh - s0] = (TACC)vh * xh;
+    if (ht) prod[kt - s0] = (TACC)vt * xt;
   } else {
     // two independent entries per step keep more gathers in flight
     int k = s0 + threadIdx.x;
