@@ -99,8 +99,8 @@ __global__ void k_empty(int n, Epi epi) {
 }
 // Row-block streaming form for short and medium rows (longest row <=
 // ROWS_LDS / RB).  Block b owns rows [RB b, RB (b+1)) and their entries: the
-// row epilogues' vector loads are issued first, so they overlap the entry
-// stream; the threads then stream the entries' values and column indices
+// row epilogues' vector loads and the rows' bounds are issued first, so they
+// overlap the entry stream; the threads then stream the entries' values and column indices
 // with unit-stride (coalesced) loads, gather the operand and stage the
 // products in LDS; finally SBLK/RB lanes per row (or one thread per row when
 // RB >= SBLK) sum each row's products from LDS and apply the epilogue.
@@ -123,10 +123,13 @@ __global__ __launch_bounds__(SBLK) void k_csr_rows(int n, const int* __restrict_
   const int lane = threadIdx.x & (LPR - 1);
   const int rbase = r0 + (int)threadIdx.x / LPR;
   typename Epi::Pre pre[RPT];
+  int rkb[RPT], rke[RPT];  // row bounds for the sums, requested before the barrier
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = rbase + q * SBLK;
     if (r < r1 && lane == 0) pre[q] = epi.load(r);
+    rkb[q] = r < r1 ? rp[r] : 0;
+    rke[q] = r < r1 ? rp[r + 1] : 0;
   }
   const int s0 = rp[r0], s1 = rp[r1];
   const int a0 = (s0 + 3) & ~3, a1 = s1 & ~3;  // the 4-aligned middle
@@ -183,7 +186,7 @@ __global__ __launch_bounds__(SBLK) void k_csr_rows(int n, const int* __restrict_
     const int r = rbase + q * SBLK;
     TACC acc = 0;
     if (r < r1) {
-      const int kb = rp[r] - s0, ke = rp[r + 1] - s0;
+      const int kb = rkb[q] - s0, ke = rke[q] - s0;
       for (int k = kb + lane; k < ke; k += LPR) acc += prod[k];
     }
     if (LPR > 1) acc = lanes_sum<TACC>(acc, LPR);
