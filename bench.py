@@ -41,8 +41,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the solver is single-device; see the sharding notes in DESIGN.md).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the solver is single-device and has no multi-GPU path.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
