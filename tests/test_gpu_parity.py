@@ -401,6 +401,30 @@ def test_full_size_solve_cfg2(torch_dev, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_apply_cfg2(torch_dev, precision):
+    """4.2M-DOF system: one preconditioner apply of the whole system (every
+    field's V-cycle, the couplings, both sweep directions) against the
+    oracle's, FP64 to 1e-13 and the FP32 V-cycle to 1e-5 relative."""
+    torch, dev = torch_dev
+    key = ("cfg2", 0)
+    s = _cache[key][0] if key in _cache else synth.make_system(cfg=2)
+    if key not in _cache:
+        _cache.clear()
+        _cache[key] = (s, _solver(torch, dev, s), None)
+    g = _cache[key][1]
+    g.set_precision(precision)
+    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, precision=precision)
+    r = np.random.default_rng(11).standard_normal(s.n)
+    tol = 1e-13 if precision == 0 else 1e-5
+    for tr in (False, True):
+        z = g.apply(torch.from_numpy(r).to(dev), transpose=tr).cpu().numpy()
+        zo = o.apply(r, transpose=tr)
+        assert np.linalg.norm(z - zo) <= tol * np.linalg.norm(zo), (tr, np.linalg.norm(z - zo) / np.linalg.norm(zo))
+    del o
+    g.set_precision(0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_graph_replays_match_eager(torch_dev, precision):
     """Each GMRES step is replayed from a captured HIP graph: every replay
     (across solves, forward and adjoint, with eager library work and host
