@@ -424,6 +424,32 @@ def test_full_size_apply_cfg2(torch_dev, precision):
     g.set_precision(0)
 
 
+def test_full_size_solve_locked_cfg2(torch_dev):
+    """4.2M-DOF system, FP64: with rtol = 0 both sides take exactly 12
+    Arnoldi steps; the GPU x equals the oracle's to 1e-9 relative."""
+    torch, dev = torch_dev
+    import paper_2602_13079_amd as H
+    key = ("cfg2", 0)
+    s = _cache[key][0] if key in _cache else synth.make_system(cfg=2)
+    if key not in _cache:
+        _cache.clear()
+        _cache[key] = (s, _solver(torch, dev, s), None)
+    g = _cache[key][1]
+    g.set_precision(0)
+    k = 12
+    g.set_tolerance(0.0, k)
+    try:
+        x, st, it, _ = g.solve(torch.from_numpy(s.b).to(dev))
+    finally:
+        g.set_tolerance(1e-8, 2000)
+    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, rtol=0.0, max_iters=k)
+    ro = o.solve(s.b)
+    del o
+    assert st == 1 and ro["status"] == 1 and it == ro["iters"] == k
+    x = x.cpu().numpy()
+    assert np.linalg.norm(x - ro["x"]) <= 1e-9 * np.linalg.norm(ro["x"])
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_graph_replays_match_eager(torch_dev, precision):
     """Each GMRES step is replayed from a captured HIP graph: every replay
