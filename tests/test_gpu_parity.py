@@ -424,9 +424,13 @@ def test_full_size_apply_cfg2(torch_dev, precision):
     g.set_precision(0)
 
 
-def test_full_size_solve_locked_cfg2(torch_dev):
-    """4.2M-DOF system, FP64: with rtol = 0 both sides take exactly 12
-    Arnoldi steps; the GPU x equals the oracle's to 1e-9 relative."""
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_solve_locked_cfg2(torch_dev, precision):
+    """4.2M-DOF system: with rtol = 0 both sides take exactly 12 Arnoldi
+    steps; the GPU x equals the oracle's to 1e-12 relative in FP64 (observed
+    3e-15).  In the mixed mode (the benchmark's) both sides run FP32 V-cycles
+    whose sums are ordered differently (each apply agrees to 1e-5), and x
+    agrees to 1e-5 (observed 1e-6)."""
     torch, dev = torch_dev
     import paper_2602_13079_amd as H
     key = ("cfg2", 0)
@@ -435,19 +439,23 @@ def test_full_size_solve_locked_cfg2(torch_dev):
         _cache.clear()
         _cache[key] = (s, _solver(torch, dev, s), None)
     g = _cache[key][1]
-    g.set_precision(0)
+    g.set_precision(precision)
     k = 12
     g.set_tolerance(0.0, k)
     try:
         x, st, it, _ = g.solve(torch.from_numpy(s.b).to(dev))
     finally:
         g.set_tolerance(1e-8, 2000)
-    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, rtol=0.0, max_iters=k)
+        g.set_precision(0)
+    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, rtol=0.0, max_iters=k,
+                      precision=precision)
     ro = o.solve(s.b)
     del o
     assert st == 1 and ro["status"] == 1 and it == ro["iters"] == k
     x = x.cpu().numpy()
-    assert np.linalg.norm(x - ro["x"]) <= 1e-9 * np.linalg.norm(ro["x"])
+    rel = np.linalg.norm(x - ro["x"]) / np.linalg.norm(ro["x"])
+    print(f"locked solve precision {precision}: x relative difference {rel:.2e}")
+    assert rel <= (1e-12 if precision == 0 else 1e-5)
 
 
 @pytest.mark.parametrize("precision", [0, 1])
