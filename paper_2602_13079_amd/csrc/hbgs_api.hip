@@ -1003,6 +1003,10 @@ static void build_values(hbgs_ctx* c, hipStream_t s) {
     for (auto& t : th) t.join();
     for (int f = 0; f < c->nf; ++f)
       if (code[f] != HBGS_OK) {
+        // a failed build may leave work in flight on its stream: drain every
+        // build stream before the caller can free what that work touches
+        for (int w = 1; w < nw; ++w) (void)hipStreamSynchronize(c->sstream[w]);
+        (void)hipStreamSynchronize(s);
         set_error(msg[f]);
         throw Error{(hbgs_status)code[f]};
       }

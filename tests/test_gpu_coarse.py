@@ -104,3 +104,32 @@ def test_singular_coarsest_rejected(torch_dev):
     with pytest.raises(H.HBGSError) as e:
         H.Solver(rp, ci, v, fl, 1, s.tree, coarse_max=n)
     assert e.value.code == -4
+
+
+def test_singular_field_in_concurrent_setup(torch_dev):
+    """Two uncoupled fields built by concurrent build threads, the second one
+    singular: the worker's ESINGULAR reaches the caller, and a valid solver
+    built afterwards on the same device works."""
+    torch, dev = torch_dev
+    import paper_2602_13079_amd as H
+    n = 40
+    good = sp.diags([-1.0, 2.5, -1.0], [-1, 0, 1], shape=(n, n)).toarray()
+    bad = np.eye(n)
+    bad[:2, :2] = 1.0
+    M = np.zeros((2 * n, 2 * n))
+    M[:n, :n] = good
+    M[n:, n:] = bad
+    A = sp.csr_matrix(M)
+    A.sort_indices()
+    fl = np.repeat(np.arange(2, dtype=np.int32), n)
+    rp, ci, v, f = (torch.from_numpy(a).to(dev) for a in (A.indptr.astype(np.int32), A.indices.astype(np.int32),
+                                                           A.data.astype(np.float64), fl))
+    with pytest.raises(H.HBGSError) as e:
+        H.Solver(rp, ci, v, f, 2, [-1, 0, 1, -2], coarse_max=64, setup_concurrent=1)
+    assert e.value.code == -4
+    s = _one_field(good)
+    rp, ci, v, f = (torch.from_numpy(a).to(dev) for a in (s.rowptr, s.col, s.val, s.field_of_row))
+    g = H.Solver(rp, ci, v, f, 1, s.tree, coarse_max=64)
+    b = good @ np.ones(n)
+    x, st, it, _ = g.solve(torch.from_numpy(b).to(dev))
+    assert st == 0 and np.allclose(x.cpu().numpy(), 1.0, rtol=1e-8)
