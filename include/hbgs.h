@@ -179,7 +179,8 @@ hbgs_status hbgs_apply(hbgs_ctx *ctx, const double *r, double *z, int32_t transp
  * (Givens estimate inside a cycle, true residual at each cycle end);
  * *hist_len = number of entries produced (may exceed hist_cap).
  * Returns HBGS_OK when the true relative residual <= rtol,
- * HBGS_NOT_CONVERGED when max_iters is reached first. b = 0 gives x = 0. */
+ * HBGS_NOT_CONVERGED when max_iters is reached first. b = 0 gives x = 0.
+ * A b with a NaN or infinite entry returns HBGS_EINVAL (x unspecified). */
 hbgs_status hbgs_solve(hbgs_ctx *ctx, const double *b, double *x, int32_t use_x0, int32_t transpose,
                        int32_t *iters, double *hist, int32_t hist_cap, int32_t *hist_len,
                        void *stream);

@@ -1351,6 +1351,7 @@ static hbgs_status fgmres(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, dou
     (*hlen)++;
   };
   double bnorm = std::sqrt(norm2(c, K, K.bp, s));
+  if (!std::isfinite(bnorm)) HBGS_FAIL(HBGS_EINVAL, "non-finite right-hand side");
   if (bnorm == 0.0) {
     HBGS_HIP(hipMemsetAsync(K.xp, 0, sizeof(double) * n, s));
     push(0.0);

@@ -258,6 +258,15 @@ def test_edge_cases(torch_dev):
         H.Solver(rp, ci, v, fl, s.nf, [-1, 0, 1, 2, -2])  # field 3 missing
     with pytest.raises(H.HBGSError):
         H.Solver(rp, ci, v, fl, s.nf, s.tree, restart=100)
+    # a non-finite right-hand side is rejected, and the context still solves
+    bn = torch.from_numpy(s.b).to(dev).clone()
+    for bad_value in (float("nan"), float("inf")):
+        bn[5] = bad_value
+        with pytest.raises(H.HBGSError) as e:
+            g3.solve(bn)
+        assert e.value.code == -1
+    x, st, it, _ = g3.solve(torch.from_numpy(s.b).to(dev))
+    assert st == 0 and _true_res(s, x.cpu().numpy()) <= 1e-8
     # a single field (plain SA-AMG preconditioned GMRES)
     A = sp.csr_matrix((s.val, s.col, s.rowptr), shape=(s.n, s.n))
     m = s.field_of_row == 2
