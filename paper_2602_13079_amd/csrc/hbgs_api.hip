@@ -1228,9 +1228,14 @@ static double norm2(hbgs_ctx* c, Krylov& K, const double* x, hipStream_t s) {
 }
 
 // One Arnoldi step j of the flexible GMRES on A with workspace K:
-// z_j = M(v_j) (written by prec into column j of K's Z), w = A z_j (into
-// column j+1 of V), two classical Gram-Schmidt passes, Givens update,
-// v_{j+1} = w / h_{j+1,j}.
+// z_j = M(u_j) (written by prec into column j of K's Z), w = A z_j (into
+// column j+1 of V), two classical Gram-Schmidt passes, Givens update.
+// Column j+1 keeps the once-orthogonalised w' = w - V h1; its second
+// correction and normalisation, v_{j+1} = (w' - V h2) / h_{j+1,j}, happen in
+// the first pass of step j+1, which reads V anyway.  The preconditioner of
+// step j+1 therefore reads u_{j+1} = w' = h_{j+1,j} v_{j+1} + V h2: in exact
+// arithmetic (h2 = 0) a multiple of v_{j+1}, and flexible GMRES takes any z,
+// a scale included (the least-squares coefficient absorbs it).
 template <class Prec>
 static void iteration_body(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, int j, hipStream_t s) {
   const int n = K.n, m = K.m;
@@ -1248,8 +1253,14 @@ static void iteration_body(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, in
       solve::spmv_outer_f64(A, K.Zd + (size_t)j * ld, w, s, e0, e1);
   }
   {
-    Prof p(c->prof, s, solve::K_DOT1, 8.0 * n * (j + 2));
-    solve::cgs_dots(n, j, K.V, ld, w, K.part, s);
+    // column j holds the previous step's once-orthogonalised vector: this
+    // pass finishes it (its second correction and normalisation) before
+    // projecting w on it
+    Prof p(c->prof, s, solve::K_DOT1, 8.0 * n * (j + (j > 0 ? 3 : 2)));
+    if (j == 0)
+      solve::cgs_dots(n, j, K.V, ld, w, K.part, s);
+    else
+      solve::cgs_finish_dots(n, j, K.V, ld, w, K.h2, K.scal, K.part, s);
   }
   {
     Prof p(c->prof, s, solve::K_REDUCE, 8.0 * nb * (j + 2));
@@ -1272,10 +1283,6 @@ static void iteration_body(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, in
     ga.host_scal = K.host_dev;
     Prof p(c->prof, s, solve::K_GIVENS, 8.0 * nb * (j + 2));
     solve::reduce_givens(n, j, K.part, K.h2, ga, s);
-  }
-  {
-    Prof p(c->prof, s, solve::K_UPD_SCALE, 8.0 * n * (j + 3));
-    solve::upd_scale(n, j, K.V, ld, w, K.h2, K.scal, s);
   }
 }
 

@@ -323,7 +323,6 @@ enum Kind {
   K_COUPLE,
   K_DOT1,
   K_UPD_DOT2,
-  K_UPD_SCALE,
   K_REDUCE,
   K_GIVENS,
   K_SCALE,
@@ -411,8 +410,13 @@ struct GivensArgs {
 // Gram-Schmidt passes over the basis V_0..V_j (w = column j+1 of V), as
 // per-block partial sums part[k * dot_blocks(n) + block]:
 //   cgs_dots:        V_k . w (k <= j) and w . w
+//   cgs_finish_dots: first V_j = (V_j - sum_{k<j} hp_k V_k) / scal[1] in
+//                    place (finishing the previous step's basis vector),
+//                    then as cgs_dots
 //   cgs_update_dots: w -= V h1, then V_k . w (k <= j) and w . w
 void cgs_dots(int n, int j, const double* V, size_t ldv, const double* w, double* part, hipStream_t s);
+void cgs_finish_dots(int n, int j, double* V, size_t ldv, const double* w, const double* hp, const double* scal,
+                     double* part, hipStream_t s);
 void cgs_update_dots(int n, int j, const double* V, size_t ldv, double* w, const double* h1, double* part,
                      hipStream_t s);
 // reduce the second pass into h2[0..j+1], then the Givens update of column
@@ -420,9 +424,6 @@ void cgs_update_dots(int n, int j, const double* V, size_t ldv, double* w, const
 // orthogonalisation, also written to host_scal)
 void reduce_givens(int n, int j, const double* part, double* h2, const GivensArgs& ga, hipStream_t s);
 void mdot_reduce(int nvec, int nblocks, const double* part, double* out, hipStream_t s);
-// w = (w - V h) / scal[1] (new basis vector), when scal[1] > 0
-void upd_scale(int n, int j, const double* V, size_t ldv, double* w, const double* h, const double* scal,
-               hipStream_t s);
 void backsolve(int jend, int m, const double* H, const double* g, double* y, hipStream_t s);
 template <class TZ>
 void xupdate(int n, int jend, const TZ* Z, size_t ldz, const double* y, double* x, hipStream_t s);

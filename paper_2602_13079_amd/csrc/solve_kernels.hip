@@ -21,7 +21,7 @@ constexpr int BLK = 256;
 
 const char* kind_names[K_COUNT] = {
     "spmv_outer", "spmv_resid", "cheb_pre",  "cheb_post_a", "cheb_post_b", "cheb_other", "resid", "restrict",
-    "prolong",    "coarse",     "couple",    "dot1",        "upd_dot2",    "upd_scale",  "reduce",
+    "prolong",    "coarse",     "couple",    "dot1",        "upd_dot2",    "reduce",
     "givens",     "scale",      "xupdate",   "permute",     "cheb_pre_c", "cheb_post_a_c", "cheb_post_b_c",
     "cheb_other_c", "resid_c",  "restrict_c", "prolong_c"};
 
@@ -714,13 +714,19 @@ __device__ void givens_update(const GivensArgs& ga, const double* h2, double* co
 // Classical Gram-Schmidt pass over rows: w holds column j+1 of V.
 //   UPD:  w -= sum_k h_k V_k           (k <= j)
 //   DOTS: part_k = sum V_k . w          (k <= j), after the update
+//   FIN:  (with DOTS, not UPD) column j still holds the previous step's
+//         once-orthogonalised vector u; it is finished first, in place, as
+//         V_j = (u - sum_{k<j} hp_k V_k) / scal[1] (the previous step's
+//         second-pass coefficients hp and h_{j,j-1}), then used in the dots
 //   always: part_{j+1} = w . w
 // (per-block partial sums; the reduction over blocks is a separate launch,
 // since a grid-wide completion fence costs more than the launch)
-template <int MAXV, bool UPD, bool DOTS>
-__global__ __launch_bounds__(BLK) void k_cgs(int n, int nv, const double* __restrict__ V, size_t ldv,
+template <int MAXV, bool UPD, bool DOTS, bool FIN>
+__global__ __launch_bounds__(BLK) void k_cgs(int n, int nv, double* __restrict__ V, size_t ldv,
                                              double* __restrict__ w, const double* __restrict__ h,
-                                             double* __restrict__ part) {
+                                             double* __restrict__ part, const double* __restrict__ hp,
+                                             const double* __restrict__ scal) {
+  static_assert(!(FIN && UPD) && (!FIN || DOTS), "FIN finishes a basis vector ahead of a dots-only pass");
   __shared__ double sh[BLK / 64];
   double acc[DOTS ? MAXV : 1];
   double hh[UPD ? MAXV : 1];
@@ -730,11 +736,22 @@ __global__ __launch_bounds__(BLK) void k_cgs(int n, int nv, const double* __rest
 #pragma unroll
     for (int k = 0; k < MAXV; ++k) hh[k] = k < nv ? h[k < nv ? k : 0] : 0.0;
   }
+  const int nrd = FIN ? nv - 1 : nv;  // columns read as they stand
+  const double hn = FIN ? scal[1] : 1.0;
   double ww = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
     double vk[MAXV];
 #pragma unroll
-    for (int k = 0; k < MAXV; ++k) vk[k] = k < nv ? V[(size_t)(k < nv ? k : 0) * ldv + i] : 0.0;
+    for (int k = 0; k < MAXV; ++k) vk[k] = k < nrd ? V[(size_t)(k < nrd ? k : 0) * ldv + i] : 0.0;
+    double vf = 0.0;
+    if (FIN) {
+      double u = V[(size_t)nrd * ldv + i];
+#pragma unroll
+      for (int k = 0; k < MAXV; ++k)
+        if (k < nrd) u -= hp[k] * vk[k];
+      vf = u / hn;
+      V[(size_t)nrd * ldv + i] = vf;
+    }
     double wi = w[i];
     if (UPD) {
 #pragma unroll
@@ -743,7 +760,7 @@ __global__ __launch_bounds__(BLK) void k_cgs(int n, int nv, const double* __rest
     }
     if (DOTS) {
 #pragma unroll
-      for (int k = 0; k < MAXV; ++k) acc[k] += vk[k] * wi;
+      for (int k = 0; k < MAXV; ++k) acc[k] += (FIN && k == nrd ? vf : vk[k]) * wi;
     }
     ww += wi * wi;
   }
@@ -761,20 +778,20 @@ __global__ __launch_bounds__(BLK) void k_cgs(int n, int nv, const double* __rest
   if (threadIdx.x == 0) part[(size_t)nv * nb + blockIdx.x] = t;
 }
 
-template <bool UPD, bool DOTS>
-static void launch_cgs(int n, int nv, const double* V, size_t ldv, double* w, const double* h, double* part,
-                       hipStream_t s) {
+template <bool UPD, bool DOTS, bool FIN = false>
+static void launch_cgs(int n, int nv, double* V, size_t ldv, double* w, const double* h, double* part,
+                       const double* hp, const double* scal, hipStream_t s) {
   int nb = dot_blocks(n);
   if (nv <= 8)
-    k_cgs<8, UPD, DOTS><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part);
+    k_cgs<8, UPD, DOTS, FIN><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part, hp, scal);
   else if (nv <= 16)
-    k_cgs<16, UPD, DOTS><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part);
+    k_cgs<16, UPD, DOTS, FIN><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part, hp, scal);
   else if (nv <= 32)
-    k_cgs<32, UPD, DOTS><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part);
+    k_cgs<32, UPD, DOTS, FIN><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part, hp, scal);
   else if (nv <= 48)  // 16-25% faster than the 64-vector form (one wave per SIMD) at 33-48 vectors
-    k_cgs<48, UPD, DOTS><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part);
+    k_cgs<48, UPD, DOTS, FIN><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part, hp, scal);
   else
-    k_cgs<64, UPD, DOTS><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part);
+    k_cgs<64, UPD, DOTS, FIN><<<nb, BLK, 0, s>>>(n, nv, V, ldv, w, h, part, hp, scal);
   HBGS_HIP(hipGetLastError());
 }
 
@@ -826,35 +843,22 @@ __global__ __launch_bounds__(RG_BLK) void k_reduce_givens(int nvec, int nb, cons
 }
 
 void cgs_dots(int n, int j, const double* V, size_t ldv, const double* w, double* part, hipStream_t s) {
-  launch_cgs<false, true>(n, j + 1, V, ldv, const_cast<double*>(w), nullptr, part, s);
+  launch_cgs<false, true>(n, j + 1, const_cast<double*>(V), ldv, const_cast<double*>(w), nullptr, part, nullptr,
+                          nullptr, s);
+}
+void cgs_finish_dots(int n, int j, double* V, size_t ldv, const double* w, const double* hp, const double* scal,
+                     double* part, hipStream_t s) {
+  launch_cgs<false, true, true>(n, j + 1, V, ldv, const_cast<double*>(w), nullptr, part, hp, scal, s);
 }
 void cgs_update_dots(int n, int j, const double* V, size_t ldv, double* w, const double* h1, double* part,
                      hipStream_t s) {
-  launch_cgs<true, true>(n, j + 1, V, ldv, w, h1, part, s);
+  launch_cgs<true, true>(n, j + 1, const_cast<double*>(V), ldv, w, h1, part, nullptr, nullptr, s);
 }
 void reduce_givens(int n, int j, const double* part, double* h2, const GivensArgs& ga, hipStream_t s) {
   if (j + 2 > RG_MAXV) HBGS_FAIL(HBGS_EINVAL, "Gram-Schmidt basis too large");
   k_reduce_givens<<<1, RG_BLK, 0, s>>>(j + 2, dot_blocks(n), part, h2, ga);
   HBGS_HIP(hipGetLastError());
 }
-// w = (w - sum_k h_k V_k) / scal[1]  (k <= j); skipped when scal[1] == 0
-__global__ __launch_bounds__(BLK) void k_upd_scale(int n, int nv, const double* __restrict__ V, size_t ldv,
-                                                   double* __restrict__ w, const double* __restrict__ h,
-                                                   const double* __restrict__ scal) {
-  const double hn = scal[1];
-  if (!(hn > 0.0)) return;
-  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
-    double wi = w[i];
-    for (int k = 0; k < nv; ++k) wi -= h[k] * V[(size_t)k * ldv + i];
-    w[i] = wi / hn;
-  }
-}
-void upd_scale(int n, int j, const double* V, size_t ldv, double* w, const double* h, const double* scal,
-               hipStream_t s) {
-  k_upd_scale<<<grid_for(n, BLK, 2048), BLK, 0, s>>>(n, j + 1, V, ldv, w, h, scal);
-  HBGS_HIP(hipGetLastError());
-}
-
 // y = R^-1 g with R the leading jend x jend upper triangle of H: the block
 // stages R and g in LDS, then one thread substitutes backwards (no global
 // loads inside the dependent chain)
