@@ -738,7 +738,12 @@ __global__ __launch_bounds__(BLK) void k_cgs(int n, int nv, double* __restrict__
   }
   const int nrd = FIN ? nv - 1 : nv;  // columns read as they stand
   const double hn = FIN ? scal[1] : 1.0;
-  double ww = 0.0;
+  double hq[FIN ? MAXV : 1];  // in registers: zero beyond nrd, where vk is zero too
+  if (FIN) {
+#pragma unroll
+    for (int k = 0; k < MAXV; ++k) hq[k] = k < nrd ? hp[k < nrd ? k : 0] : 0.0;
+  }
+  double ww = 0.0, accf = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
     double vk[MAXV];
 #pragma unroll
@@ -747,8 +752,7 @@ __global__ __launch_bounds__(BLK) void k_cgs(int n, int nv, double* __restrict__
     if (FIN) {
       double u = V[(size_t)nrd * ldv + i];
 #pragma unroll
-      for (int k = 0; k < MAXV; ++k)
-        if (k < nrd) u -= hp[k] * vk[k];
+      for (int k = 0; k < MAXV; ++k) u -= hq[k] * vk[k];
       vf = u / hn;
       V[(size_t)nrd * ldv + i] = vf;
     }
@@ -760,7 +764,8 @@ __global__ __launch_bounds__(BLK) void k_cgs(int n, int nv, double* __restrict__
     }
     if (DOTS) {
 #pragma unroll
-      for (int k = 0; k < MAXV; ++k) acc[k] += (FIN && k == nrd ? vf : vk[k]) * wi;
+      for (int k = 0; k < MAXV; ++k) acc[k] += vk[k] * wi;
+      if (FIN) accf += vf * wi;  // the finished column's dot: acc[nrd] only saw zeros
     }
     ww += wi * wi;
   }
@@ -769,7 +774,7 @@ __global__ __launch_bounds__(BLK) void k_cgs(int n, int nv, double* __restrict__
 #pragma unroll
     for (int k = 0; k < MAXV; ++k) {
       if (k < nv) {
-        double t = block_sum(acc[k], sh);
+        double t = block_sum(FIN && k == nrd ? accf : acc[k], sh);
         if (threadIdx.x == 0) part[(size_t)k * nb + blockIdx.x] = t;
       }
     }
