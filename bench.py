@@ -160,7 +160,7 @@ def main():
     vbytes = st["vcycle_bytes"][1]
 
     achieved = dk["bytes"] / (dk["ms"] * 1e-3) / 1e9 if dk["ms"] > 0 else 0.0
-    traffic, traffic_src = measured_traffic(dominant)
+    traffic, traffic_src = measured_traffic(dominant, round(dk["bytes"] / max(dk["launches"], 1)))
     out = {
         "metric": METRIC,
         "value": round(mean("mixed_s"), 6),
@@ -298,11 +298,12 @@ def copy_probe(torch, dev, mib=512, reps=5):
     return 2 * n * 4 / best / 1e9
 
 
-def measured_traffic(kind):
+def measured_traffic(kind, alg_bytes):
     """HBM bytes per launch of the `kind` kernel from the committed PMC summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading for
-    the copy probe of known size), or None when the summary does not cover
-    this kind or the solve kernels have changed since it was taken."""
+    the copy probe of known size), or None when no summary covers this kind
+    on this workload (its algorithmic bytes per launch, `alg_bytes`, differ)
+    or the solve kernels have changed since it was taken."""
     import glob
     import hashlib
     src = os.path.join(ROOT, "paper_2602_13079_amd", "csrc", "solve_kernels.hip")
@@ -312,12 +313,12 @@ def measured_traffic(kind):
         if "```json" not in text:
             continue
         rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-        if rec.get("kind") != kind:
+        if rec.get("kind") != kind or rec.get("algorithmic_bytes_per_launch") != alg_bytes:
             continue
         if rec.get("solve_kernels_sha256") != digest:
             return None, f"{os.path.relpath(path, ROOT)} is stale (solve kernels changed since)"
         return round(rec["hbm_bytes_per_launch"]), os.path.relpath(path, ROOT)
-    return None, "no PMC summary for this kernel class"
+    return None, "no PMC summary for this kernel class on this workload"
 
 
 def cpu_baseline(s):
