@@ -156,6 +156,43 @@ def test_solve_iteration_locked(torch_dev, case):
     assert np.linalg.norm(x - ro["x"]) <= 1e-9 * np.linalg.norm(ro["x"])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_solve_iteration_locked_restarts(torch_dev, precision):
+    """Locked at 11 Arnoldi steps with restart 4: three cycles, each ending
+    with a basis vector that is never finished, each starting afresh from
+    the true residual.  x and the residual history must follow the oracle's
+    (same precision mode, same steps) across both restarts, forward and
+    transposed."""
+    torch, dev = torch_dev
+    case = "ragged7x5x9_6f_cm40"
+    s = _system(case)
+    cm = CASES[case]["coarse_max"]
+    k, m = 11, 4
+    g = _solver(torch, dev, s, coarse_max=cm, rtol=0.0, max_iters=k, restart=m)
+    g.set_precision(precision)
+    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, coarse_max=cm, rtol=0.0,
+                      max_iters=k, restart=m, precision=precision)
+    # mixed: both sides run FP32 V-cycles with differently ordered sums (each
+    # apply within 1e-5 of the other's), and the unconverged iterate of three
+    # restarted cycles compounds those differences: x is held to the bound the
+    # mixed mode meets against FP64 at convergence.  The history entries are
+    # residual estimates whose relative sensitivity grows as they shrink (in
+    # FP64 they differ ~1e4 times more than x), hence the looser 1e-3
+    tol_x, tol_h = (1e-9, 1e-6) if precision == 0 else (1e-4, 1e-3)
+    for tr in (False, True):
+        b = s.b if not tr else s.x_t
+        x, st, it, hist = g.solve(torch.from_numpy(b).to(dev), transpose=tr)
+        ro = o.solve(b, transpose=tr)
+        assert st == 1 and ro["status"] == 1 and it == ro["iters"] == k, (st, it, ro["iters"])
+        x = x.cpu().numpy()
+        dx = np.linalg.norm(x - ro["x"]) / np.linalg.norm(ro["x"])
+        print(f"restart-locked precision {precision} transpose {tr}: x relative difference {dx:.2e}, "
+              f"history {np.max(np.abs(hist - ro['hist']) / ro['hist']):.2e}")
+        assert dx <= tol_x
+        assert len(hist) == len(ro["hist"])
+        assert np.allclose(hist, ro["hist"], rtol=tol_h, atol=0.0)
+
+
 @pytest.mark.parametrize("case", ["cfg0_cm64", "ragged7x5x9_6f_cm40", "cfg1"])
 def test_solve_mixed_precision(torch_dev, case):
     torch, dev = torch_dev
