@@ -110,7 +110,7 @@ typedef struct {
   double cheb_boost;    // lambda_max = boost * estimate
   int32_t eig_iters;    // power iterations for eigenvalue estimates
   double sa_damping;    // omega = sa_damping / lambda(D_abs^-1 A_F)
-  double omega_override;// > 0: use this omega instead (tests)
+  double omega_override;// >= 0: use this omega instead (tests); < 0: sa_damping / lambda
   int32_t coarse_max;   // stop coarsening at or below this many rows
   int32_t max_levels;   // including the finest level
   uint64_t seed;        // salt for aggregation priorities and start vectors
@@ -288,28 +288,19 @@ void filter(const CsrD& a, const std::vector<char>& strong, CsrD& af, std::vecto
   }
 }
 
-// Sum of a long vector of products with a fixed association: each run of
-// 256 consecutive terms is summed in order; while more than one partial sum
-// remains, runs of 256 consecutive partial sums are summed in order again.
+// Sum of a long vector of products with a fixed association (the paper does
+// not say how its eigenvalue estimate sums; this order is part of the
+// reading): each run of 256 consecutive terms is summed in order, then the
+// run sums are added in order.
 double chunked_dot(const std::vector<double>& x, const std::vector<double>& y) {
+  double total = 0.0;
   const size_t n = x.size();
-  std::vector<double> part;
   for (size_t c = 0; c < n; c += 256) {
     double s = 0.0;
     for (size_t i = c; i < std::min(n, c + 256); ++i) s += x[i] * y[i];
-    part.push_back(s);
+    total += s;
   }
-  if (part.empty()) return 0.0;
-  while (part.size() > 1) {
-    std::vector<double> next;
-    for (size_t c = 0; c < part.size(); c += 256) {
-      double s = 0.0;
-      for (size_t i = c; i < std::min(part.size(), c + 256); ++i) s += part[i];
-      next.push_back(s);
-    }
-    part.swap(next);
-  }
-  return part[0];
+  return total;
 }
 
 // Eigenvalue estimate of D^-1 B (reading: the usual power method with a
@@ -512,7 +503,7 @@ int setup_amg(const CsrD& a0, double theta, const or_options& o, uint64_t salt_b
           g_err = {-5, "non-positive eigenvalue estimate for prolongator smoothing"};
           return -5;
         }
-        L.omega = o.omega_override > 0 ? o.omega_override : o.sa_damping / L.lam_p;
+        L.omega = o.omega_override >= 0 ? o.omega_override : o.sa_damping / L.lam_p;
         L.agg = ag.agg;
         L.P = smooth_prolongator(af, dabs, ag.agg, ag.nagg, L.omega);
         L.R = transpose(L.P);
@@ -1075,7 +1066,7 @@ void or_default_options(or_options* o) {
   o->cheb_boost = 1.1;
   o->eig_iters = 10;
   o->sa_damping = 4.0 / 3.0;
-  o->omega_override = 0.0;
+  o->omega_override = -1.0;
   o->coarse_max = 2000;
   o->max_levels = 10;
   o->seed = 0x2602ull;

@@ -217,22 +217,231 @@ def test_mis2_path_graph():
         assert mem.max() - mem.min() + 1 == len(mem)
 
 
+def _splitmix64(x):
+    m = 0xFFFFFFFFFFFFFFFF
+    x = (x + 0x9E3779B97F4A7C15) & m
+    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & m
+    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & m
+    return x ^ (x >> 31)
+
+
+def _priority(i, salt):
+    """Aggregation priority: upper 32 bits of splitmix64(i ^ salt), then i."""
+    return ((_splitmix64((i & 0xFFFFFFFF) ^ salt) >> 32) << 32) | i
+
+
+def _aggregates_from_roots(adj, root, excluded, keys):
+    """Aggregation phases 1-3 restated from the reading: roots numbered by
+    ascending row; a non-root row next to a root joins that root (the root is
+    unique: roots are at least 3 apart); a row with no root next to it joins
+    the phase-1 row next to it with the largest priority; rows still left are
+    singletons numbered after the roots in row order."""
+    n = len(adj)
+    roots = [i for i in range(n) if root[i]]
+    agg = np.full(n, -1, dtype=np.int64)
+    for a, r in enumerate(roots):
+        agg[r] = a
+    phase1 = np.full(n, -1, dtype=np.int64)
+    for i in range(n):
+        if excluded[i] or root[i]:
+            continue
+        near = sorted({u for u in adj[i] if root[u]})
+        assert len(near) <= 1
+        if near:
+            phase1[i] = agg[near[0]]
+    for i in range(n):
+        if excluded[i] or root[i]:
+            continue
+        if phase1[i] >= 0:
+            agg[i] = phase1[i]
+            continue
+        cand = [u for u in adj[i] if phase1[u] >= 0]
+        if cand:
+            agg[i] = phase1[max(cand, key=lambda u: keys[u])]
+    nxt = len(roots)
+    for i in range(n):
+        if not excluded[i] and agg[i] < 0:
+            agg[i] = nxt
+            nxt += 1
+    return agg, nxt
+
+
+@pytest.mark.parametrize("seed,density", [(0, 0.02), (1, 0.04), (2, 0.08), (3, 0.015)])
+def test_aggregation_phases_by_definition(seed, density):
+    """Whole aggregation (roots from the synchronous-round MIS-2, phases 1-3
+    restated) equals the oracle's on random symmetric strength graphs with
+    identity rows (excluded) and rows whose entries are all weak."""
+    rng = np.random.default_rng(100 + seed)
+    n = 300
+    M = sp.random(n, n, density=density, random_state=seed, format="csr")
+    M = ((M + M.T) != 0).astype(float)
+    M = M.tolil()
+    ident = rng.choice(n, 12, replace=False)
+    for i in ident:
+        M.rows[i] = []
+        M.data[i] = []
+    M = M.tocsr()
+    M = ((M + M.T) != 0).astype(float)  # identity rows are referenced by no row either
+    M = M.tolil()
+    for i in ident:
+        M[:, i] = 0
+        M[i, :] = 0
+    M = (M.tocsr() + sp.identity(n) * 4).tocsr()
+    M.sort_indices()
+    rp, ci, v = csr_args(M)
+    row = np.repeat(np.arange(n), np.diff(rp))
+    # a symmetric strong mask: each structural pair strong with probability 0.8
+    pair_strong = {}
+    strong = np.zeros(len(ci), dtype=bool)
+    for q in range(len(ci)):
+        i, j = row[q], ci[q]
+        if i == j:
+            continue
+        key = (min(i, j), max(i, j))
+        if key not in pair_strong:
+            pair_strong[key] = rng.random() < 0.8
+        strong[q] = pair_strong[key]
+    salt = 4242 + seed
+    agg, root, nagg = oracle.aggregate(rp, ci, v, strong, salt)
+    adj = _graph(rp, ci, strong)
+    excluded = np.array([rp[i + 1] - rp[i] == 1 for i in range(n)])
+    keys = np.array([_priority(i, salt) for i in range(n)], dtype=np.uint64)
+    assert all(oracle.agg_key(i, salt) == int(keys[i]) for i in range(n))
+    ref_root = _mis2_rounds(adj, keys, excluded)
+    assert np.array_equal(root, ref_root)
+    ref_agg, ref_n = _aggregates_from_roots(adj, ref_root, excluded, keys)
+    assert nagg == ref_n
+    assert np.array_equal(agg, ref_agg)
+    assert np.all(agg[excluded] == -1)
+    phase2 = [i for i in range(n) if not excluded[i] and not root[i] and not any(root[u] for u in adj[i])]
+    assert len(phase2) > 0  # phase 2 is exercised
+
+
+def test_aggregation_phase3_singleton():
+    """Phase 3 needs a row that a root covered but that has no strong entry
+    towards it (a one-sided strength mask): two rows coupled both ways, only
+    (0,1) strong.  If row 0 has the larger priority it becomes the root, row 1
+    is covered but has no strong neighbour, so it becomes a singleton numbered
+    after the roots; otherwise both rows are roots."""
+    A = sp.csr_matrix(np.array([[2.0, -1.0], [-1.0, 2.0]]))
+    rp, ci, v = csr_args(A)
+    strong = np.array([False, True, False, False])  # entries (0,0) (0,1) (1,0) (1,1)
+    seen = set()
+    for salt in range(1, 40):
+        agg, root, nagg = oracle.aggregate(rp, ci, v, strong, salt)
+        if _priority(0, salt) > _priority(1, salt):
+            assert list(root) == [True, False] and list(agg) == [0, 1] and nagg == 2
+            seen.add("phase3")
+        else:
+            assert list(root) == [True, True] and list(agg) == [0, 1] and nagg == 2
+            seen.add("two roots")
+    assert seen == {"phase3", "two roots"}
+
+
+def test_power_estimate_rayleigh_quotient():
+    """With no power steps the estimate is the Rayleigh quotient of the hashed
+    start vector w (2 u - 1, u from the top 53 bits of splitmix64(i ^ salt)):
+    (w . D^-1 B w) / (w . w).  Its sums follow the fixed association (256-term
+    runs in order, then the run sums in order), bitwise, and lie within the
+    summation error bound of the exactly rounded quotient."""
+    import math
+    A = poisson2d(31, 29)  # 899 rows: three full 256-term runs and a ragged one
+    rp, ci, v = csr_args(A)
+    n = A.shape[0]
+    d = 1.0 + np.arange(n) % 7
+    salt = 99
+    w = np.array([2.0 * float(_splitmix64(i ^ salt) >> 11) * 2.0 ** -53 - 1.0 for i in range(n)])
+    y = np.empty(n)
+    for i in range(n):
+        s_ = 0.0
+        for q in range(rp[i], rp[i + 1]):
+            s_ = s_ + float(v[q]) * float(w[ci[q]])
+        y[i] = s_ / d[i]
+
+    def runs(x, z):
+        total = 0.0
+        for c in range(0, n, 256):
+            s_ = 0.0
+            for i in range(c, min(n, c + 256)):
+                s_ = s_ + float(x[i]) * float(z[i])
+            total = total + s_
+        return total
+
+    lam = oracle.power_estimate(rp, ci, v, d, 0, salt)
+    assert lam == runs(w, y) / runs(w, w)
+    exact = math.fsum(w * y) / math.fsum(w * w)
+    bound = 2 * n * 2.0 ** -53 * (np.abs(w * y).sum() / math.fsum(w * w) + abs(exact))
+    assert abs(lam - exact) <= bound
+
+
 # -------------------------------------------------- prolongator and filter
 def test_tentative_prolongator_reproduces_constants():
-    """With omega -> 0 the smoothed prolongator is the tentative one; here the
-    tentative operator is rebuilt from the aggregates and P_tent 1_c = 1."""
+    """Required check 3 on the oracle's own prolongator.  With omega = 0 the
+    smoothing term vanishes, so the P the oracle builds is the tentative
+    operator: every aggregated row has the value 1 at its aggregate and 0
+    elsewhere, and P 1_c = 1 exactly on aggregated rows (0 on excluded
+    rows)."""
     s = synth.make_system(8, 8, 10, 1, seed=4)
     for f in range(4):
         B = block_of(s, f)
         h = oracle.Amg(*csr_args(B), theta=0.04 if f == 0 else 0.0, salt=5,
-                       opts=oracle.options(coarse_max=50))
+                       opts=oracle.options(coarse_max=50, omega_override=0.0))
+        assert h.levels >= 2
         agg = h.agg(0)
-        nagg = h.get(1, "A")[0].shape[0] - 1
-        Pt = sp.csr_matrix((np.ones((agg >= 0).sum()), (np.flatnonzero(agg >= 0), agg[agg >= 0])),
-                           shape=(len(agg), nagg))
-        one = Pt @ np.ones(nagg)
+        prp, pci, pv, nc = h.get(0, "P")
+        P = sp.csr_matrix((pv, pci, prp), shape=(len(agg), nc))
+        one = P @ np.ones(nc)
         assert np.array_equal(one[agg >= 0], np.ones((agg >= 0).sum()))
         assert np.all(one[agg < 0] == 0)
+        rows = np.repeat(np.arange(len(agg)), np.diff(prp))
+        assert np.all(pv[pci == agg[rows]] == 1.0)
+        assert np.all(pv[pci != agg[rows]] == 0.0)
+        assert np.all(np.diff(prp)[agg < 0] == 0)
+
+
+def _filtered_from_definition(B, theta):
+    """A_F and D_abs written from their definitions (strong pairs by squares,
+    dropped entries added to the diagonal, absolute row sums)."""
+    Bd = B.toarray()
+    d = np.diag(Bd).copy()
+    n = Bd.shape[0]
+    F = np.zeros_like(Bd)
+    for i in range(n):
+        for j in np.flatnonzero(Bd[i]):
+            if j == i:
+                continue
+            strong = (Bd[i, j] ** 2 >= theta ** 2 * abs(d[i]) * abs(d[j])) or \
+                     (Bd[j, i] ** 2 >= theta ** 2 * abs(d[j]) * abs(d[i]))
+            if strong:
+                F[i, j] = Bd[i, j]
+            else:
+                F[i, i] += Bd[i, j]
+        F[i, i] += d[i]
+    return F, abs(F).sum(axis=1)
+
+
+def test_smoothed_prolongator_row_sums():
+    """P = P_tent - omega D_abs^-1 A_F P_tent with P_tent 1_c = 1 gives
+    P 1_c = 1 - omega D_abs^-1 A_F 1 on rows whose filtered neighbours are all
+    aggregated; where A's row sum is 0 (lumping keeps row sums) that is 1."""
+    s = synth.make_system(8, 8, 10, 1, seed=4)
+    for f, th in ((0, 0.04), (2, 0.0), (3, 0.0)):
+        B = block_of(s, f)
+        h = oracle.Amg(*csr_args(B), theta=th, salt=5, opts=oracle.options(coarse_max=50))
+        agg = h.agg(0)
+        om = h.scalars(0)["omega"]
+        prp, pci, pv, nc = h.get(0, "P")
+        P = sp.csr_matrix((pv, pci, prp), shape=(len(agg), nc))
+        F, dabs = _filtered_from_definition(B, th)
+        full = np.array([np.all(agg[np.flatnonzero(F[i])] >= 0) for i in range(len(agg))]) & (agg >= 0)
+        expect = 1.0 - om * (F @ np.ones(len(agg))) / dabs
+        got = P @ np.ones(nc)
+        assert full.sum() > len(agg) // 2
+        assert np.allclose(got[full], expect[full], rtol=0, atol=1e-13)
+        zero_sum = full & (B @ np.ones(len(agg)) == 0)
+        if f == 2:  # pressure: interior rows of a pure Darcy block
+            assert zero_sum.sum() > 50
+        assert np.allclose(got[zero_sum], 1.0, rtol=0, atol=1e-13)
 
 
 def test_filter_lumping_preserves_row_sums():
