@@ -869,7 +869,7 @@ __global__ void k_pw_scale(int n, const double* y, const unsigned long long* ama
   if (mx > 0.0) frexp(mx, &e);
   GRID_STRIDE(i, n) w[i] = mx > 0.0 ? ldexp(y[i], -e) : 0.0;
 }
-// fixed-association sum: consecutive runs of 256 terms summed in order
+// fixed-association sum: consecutive runs of 256 terms summed in order ...
 __global__ void k_chunk_dot(int64_t n, const double* x, const double* y, double* part) {
   GRID_STRIDE(c, (n + 255) / 256) {
     double s = 0.0;
@@ -878,39 +878,40 @@ __global__ void k_chunk_dot(int64_t n, const double* x, const double* y, double*
     part[c] = s;
   }
 }
-__global__ void k_chunk_sum(int64_t n, const double* x, double* part) {
-  GRID_STRIDE(c, (n + 255) / 256) {
-    double s = 0.0;
-    int64_t e = (c + 1) * 256 < n ? (c + 1) * 256 : n;
-    for (int64_t i = c * 256; i < e; ++i) s += x[i];
-    part[c] = s;
+// ... then the m run sums added in order: the block stages 1024 of them in
+// LDS at a time, one thread adds them
+constexpr int RUN_STAGE = 1024;
+__global__ void __launch_bounds__(256) k_chunk_total(int64_t m, const double* part, double* out) {
+  __shared__ double sh[RUN_STAGE];
+  double s = 0.0;
+  for (int64_t c0 = 0; c0 < m; c0 += RUN_STAGE) {
+    const int e = (int)(m - c0 < RUN_STAGE ? m - c0 : RUN_STAGE);
+    for (int t = threadIdx.x; t < e; t += blockDim.x) sh[t] = part[c0 + t];
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int t = 0; t < e; ++t) s += sh[t];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *out = s;
 }
 
-static double tree_dot(int64_t n, const double* x, const double* y, double* buf_a, double* buf_b,
-                       hipStream_t s) {
+static double chunked_dot(int64_t n, const double* x, const double* y, double* part, double* out,
+                          hipStream_t s) {
   if (n == 0) return 0.0;
-  int64_t m = (n + 255) / 256;
-  k_chunk_dot<<<grid_for(m, 64), 64, 0, s>>>(n, x, y, buf_a);
+  const int64_t m = (n + 255) / 256;
+  k_chunk_dot<<<grid_for(m, 64), 64, 0, s>>>(n, x, y, part);
   HBGS_HIP(hipGetLastError());
-  double* cur = buf_a;
-  double* nxt = buf_b;
-  while (m > 1) {
-    int64_t m2 = (m + 255) / 256;
-    k_chunk_sum<<<grid_for(m2, 64), 64, 0, s>>>(m, cur, nxt);
-    HBGS_HIP(hipGetLastError());
-    std::swap(cur, nxt);
-    m = m2;
-  }
+  k_chunk_total<<<1, 256, 0, s>>>(m, part, out);
+  HBGS_HIP(hipGetLastError());
   double r = 0.0;
-  HBGS_HIP(hipMemcpyAsync(&r, cur, sizeof(double), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipMemcpyAsync(&r, out, sizeof(double), hipMemcpyDeviceToHost, s));
   HBGS_HIP(hipStreamSynchronize(s));
   return r;
 }
 
 double power_estimate(const DCsr& b, const double* d, int iters, uint64_t salt, hipStream_t s) {
   const int n = b.n;
-  Tmp<double> w(n), y(n), pa((n + 255) / 256 + 1), pb((n + 255) / 256 + 1);
+  Tmp<double> w(n), y(n), pa((n + 255) / 256 + 1), pb(1);
   Tmp<unsigned long long> amax(iters > 0 ? iters : 1);
   const unsigned g = grid_for(n, BLK);
   // one block per CU slot (8 per CU): each block ends in one atomicMax on a
@@ -941,14 +942,14 @@ double power_estimate(const DCsr& b, const double* d, int iters, uint64_t salt, 
     wl = other;
     k_pw_apply<<<ga, PW_RB, 0, s>>>(n, b.rp, b.ci, b.v, d, other, nullptr, last, nullptr);
     HBGS_HIP(hipGetLastError());
-    double wy = tree_dot(n, wl, last, pa.p, pb.p, s);
-    double ww = tree_dot(n, wl, wl, pa.p, pb.p, s);
+    double wy = chunked_dot(n, wl, last, pa.p, pb.p, s);
+    double ww = chunked_dot(n, wl, wl, pa.p, pb.p, s);
     return wy / ww;
   }
   k_pw_apply<<<ga, PW_RB, 0, s>>>(n, b.rp, b.ci, b.v, d, w.p, nullptr, y.p, nullptr);
   HBGS_HIP(hipGetLastError());
-  double wy = tree_dot(n, w.p, y.p, pa.p, pb.p, s);
-  double ww = tree_dot(n, w.p, w.p, pa.p, pb.p, s);
+  double wy = chunked_dot(n, w.p, y.p, pa.p, pb.p, s);
+  double ww = chunked_dot(n, w.p, w.p, pa.p, pb.p, s);
   return wy / ww;
 }
 
