@@ -1139,11 +1139,12 @@ static void vcycle(hbgs_ctx* c, Field& F, int l, int tr, const T* b, T* x, hipSt
   }
 }
 
-// z = M^-1 v (tr = 0) or M^-T v (tr = 1) over the fields of `plan`, in the
-// permuted ordering shifted by `base` (field f's rows are v[F.lo - base ..]);
-// z has type T
+// z = M^-1 (v / vs) (tr = 0) or M^-T (v / vs) (tr = 1) over the fields of
+// `plan`, in the permuted ordering shifted by `base` (field f's rows are
+// v[F.lo - base ..]); z has type T; vs is a device scalar (null: 1)
 template <class T>
-static void sweep(hbgs_ctx* c, const SweepPlan& plan, int tr, const double* v, T* z, int base, hipStream_t s0) {
+static void sweep(hbgs_ctx* c, const SweepPlan& plan, int tr, const double* v, T* z, int base, const double* vs,
+                  hipStream_t s0) {
   const int nl = (int)plan.order.size();
   const int TS = (int)sizeof(T);
   HBGS_HIP(hipEventRecord(c->fork, s0));
@@ -1170,11 +1171,11 @@ static void sweep(hbgs_ctx* c, const SweepPlan& plan, int tr, const double* v, T
       T* zf = z + off;
       Prof p(c->prof, s, solve::K_COUPLE, (cpl.nnz ? spmv_bytes(cpl, TS, 0, TS, 2) : 0.0) + (8.0 + 2 * TS) * F.n());
       if (cpl.nnz > 0)
-        VcOps<T>::couple(cpl, v + off, z, Buf<T>::t(F), dinv, 1.0, zf, s);
-      else if (sizeof(T) == sizeof(double))
+        VcOps<T>::couple(cpl, v + off, z, Buf<T>::t(F), dinv, 1.0, zf, vs, s);
+      else if (sizeof(T) == sizeof(double) && !vs)
         VcOps<T>::make_d0(F.n(), reinterpret_cast<const T*>(v + off), dinv, 1.0, zf, s);
       else
-        VcOps<T>::cast_in(F.n(), v + off, Buf<T>::t(F), dinv, 1.0, zf, s);
+        VcOps<T>::cast_in(F.n(), v + off, Buf<T>::t(F), dinv, 1.0, zf, vs, s);
       HBGS_HIP(hipEventRecord(c->fdone[F.id], s));
       continue;
     }
@@ -1182,9 +1183,9 @@ static void sweep(hbgs_ctx* c, const SweepPlan& plan, int tr, const double* v, T
     if (cpl.nnz > 0) {
       Prof p(c->prof, s, solve::K_COUPLE,
              spmv_bytes(cpl, TS, 0, TS, d0 ? 2 : 0) + 8.0 * F.n() + (double)std::min<int64_t>(cpl.nnz, c->n) * TS);
-      VcOps<T>::couple(cpl, v + off, z, Buf<T>::t(F), dinv0, L0.cc.c0, d00, s);
+      VcOps<T>::couple(cpl, v + off, z, Buf<T>::t(F), dinv0, L0.cc.c0, d00, vs, s);
       t = Buf<T>::t(F);
-    } else if (sizeof(T) == sizeof(double)) {
+    } else if (sizeof(T) == sizeof(double) && !vs) {
       t = reinterpret_cast<const T*>(v + off);
       if (d0) {
         Prof p(c->prof, s, solve::K_COUPLE, 3.0 * F.n() * TS);
@@ -1192,7 +1193,7 @@ static void sweep(hbgs_ctx* c, const SweepPlan& plan, int tr, const double* v, T
       }
     } else {
       Prof p(c->prof, s, solve::K_COUPLE, (8.0 + TS * (d0 ? 3 : 1)) * F.n());
-      VcOps<T>::cast_in(F.n(), v + off, Buf<T>::t(F), dinv0, L0.cc.c0, d00, s);
+      VcOps<T>::cast_in(F.n(), v + off, Buf<T>::t(F), dinv0, L0.cc.c0, d00, vs, s);
       t = Buf<T>::t(F);
     }
     if (F.leaf == 2) {
@@ -1233,9 +1234,16 @@ static double norm2(hbgs_ctx* c, Krylov& K, const double* x, hipStream_t s) {
 // Column j+1 keeps the once-orthogonalised w' = w - V h1; its second
 // correction and normalisation, v_{j+1} = (w' - V h2) / h_{j+1,j}, happen in
 // the first pass of step j+1, which reads V anyway.  The preconditioner of
-// step j+1 therefore reads u_{j+1} = w' = h_{j+1,j} v_{j+1} + V h2: in exact
-// arithmetic (h2 = 0) a multiple of v_{j+1}, and flexible GMRES takes any z,
-// a scale included (the least-squares coefficient absorbs it).
+// step j+1 therefore reads u_{j+1} = w' / h_{j+1,j} = v_{j+1} + V h2 / h_{j+1,j}
+// (the division is done as the sweep reads its input, with h_{j+1,j} from
+// the device): a unit vector whose part in the span of the earlier basis
+// vectors is of relative size ||h2|| / h_{j+1,j}.  That part lies in the
+// span of the earlier directions z (the sweep is linear), so flexible GMRES
+// is unaffected; ||h2|| is of the order of the rounding of w, and the
+// breakdown test (h_{j+1,j} <= 1e-14 ||w||) ends the cycle before the ratio
+// exceeds O(1).  Without the division the input would carry the scale
+// prod_k h_{k+1,k}, which leaves FP32 range within a long cycle and costs
+// accuracy in FP64 through the widely scaled least-squares columns.
 template <class Prec>
 static void iteration_body(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, int j, hipStream_t s) {
   const int n = K.n, m = K.m;
@@ -1243,7 +1251,7 @@ static void iteration_body(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, in
   const int nb = solve::dot_blocks(n);
   double* vj = K.V + (size_t)j * ld;
   double* w = K.V + (size_t)(j + 1) * ld;
-  prec(j, (const double*)vj, s);
+  prec(j, (const double*)vj, j > 0 ? K.scal + 1 : nullptr, s);
   {
     hipEvent_t e0, e1;  // stamped by the dispatch itself when this class is timed
     c->prof.stamp(solve::K_SPMV_OUTER, spmv_bytes(A, 8, c->precision ? 4 : 8, 8, 0), &e0, &e1);
@@ -1409,18 +1417,18 @@ static hbgs_status fgmres(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, dou
   }
 }
 
-static void nested_apply(hbgs_ctx* c, int tr, const double* v, int j, hipStream_t s);
+static void nested_apply(hbgs_ctx* c, int tr, const double* v, int j, const double* vs, hipStream_t s);
 
-// z_j = M^-1 v (tr = 0) or M^-T v, permuted ordering, into column j of the
-// outer Z
-static void apply_perm(hbgs_ctx* c, int tr, const double* v, int j, hipStream_t s) {
+// z_j = M^-1 (v / vs) (tr = 0) or M^-T (v / vs), permuted ordering, into
+// column j of the outer Z (vs: device scalar or null)
+static void apply_perm(hbgs_ctx* c, int tr, const double* v, int j, const double* vs, hipStream_t s) {
   Krylov& K = c->K;
   if (c->o.nested)
-    nested_apply(c, tr, v, j, s);
+    nested_apply(c, tr, v, j, vs, s);
   else if (c->precision == 1)
-    sweep<float>(c, c->plan[tr], tr, v, K.Zf + (size_t)j * K.ld, 0, s);
+    sweep<float>(c, c->plan[tr], tr, v, K.Zf + (size_t)j * K.ld, 0, vs, s);
   else
-    sweep<double>(c, c->plan[tr], tr, v, K.Zd + (size_t)j * K.ld, 0, s);
+    sweep<double>(c, c->plan[tr], tr, v, K.Zd + (size_t)j * K.ld, 0, vs, s);
 }
 
 // Nested form (Sec. 3.2): the children of the outermost group are visited
@@ -1429,7 +1437,7 @@ static void apply_perm(hbgs_ctx* c, int tr, const double* v, int j, hipStream_t 
 // flexible GMRES from a zero start, preconditioned by its own sweep, to the
 // inner tolerance.  Its result becomes block g of z_j (rounded to FP32 in the
 // mixed mode, where Z is FP32).
-static void nested_apply(hbgs_ctx* c, int tr, const double* v, int j, hipStream_t s) {
+static void nested_apply(hbgs_ctx* c, int tr, const double* v, int j, const double* vs, hipStream_t s) {
   Krylov& K = c->K;
   const int ng = (int)c->G.size();
   for (int q = 0; q < ng; ++q) {
@@ -1439,23 +1447,25 @@ static void nested_apply(hbgs_ctx* c, int tr, const double* v, int j, hipStream_
     if (cpl.nnz > 0) {
       Prof p(c->prof, s, solve::K_COUPLE, spmv_bytes(cpl, 8, c->precision ? 4 : 8, 8, 1));
       if (c->precision == 1)
-        solve::couple_f64<float>(cpl, v + g.lo, K.Zf + (size_t)j * K.ld, KG.bp, s);
+        solve::couple_f64<float>(cpl, v + g.lo, K.Zf + (size_t)j * K.ld, KG.bp, vs, s);
       else
-        solve::couple_f64<double>(cpl, v + g.lo, K.Zd + (size_t)j * K.ld, KG.bp, s);
+        solve::couple_f64<double>(cpl, v + g.lo, K.Zd + (size_t)j * K.ld, KG.bp, vs, s);
+    } else if (vs) {
+      VcOps<double>::cast_in(g.n(), v + g.lo, KG.bp, nullptr, 0.0, nullptr, vs, s);
     } else {
       HBGS_HIP(hipMemcpyAsync(KG.bp, v + g.lo, sizeof(double) * g.n(), hipMemcpyDeviceToDevice, s));
     }
-    auto prec = [&](int jj, const double* vv, hipStream_t st) {
+    auto prec = [&](int jj, const double* vv, const double* vvs, hipStream_t st) {
       if (c->precision == 1)
-        sweep<float>(c, g.plan[tr], tr, vv, KG.Zf + (size_t)jj * KG.ld, g.lo, st);
+        sweep<float>(c, g.plan[tr], tr, vv, KG.Zf + (size_t)jj * KG.ld, g.lo, vvs, st);
       else
-        sweep<double>(c, g.plan[tr], tr, vv, KG.Zd + (size_t)jj * KG.ld, g.lo, st);
+        sweep<double>(c, g.plan[tr], tr, vv, KG.Zd + (size_t)jj * KG.ld, g.lo, vvs, st);
     };
     int32_t it = 0, hl = 0;
     (void)fgmres(c, KG, tr ? g.AT : g.A, prec, c->o.inner_rtol, c->o.inner_max_iters, 0, &it, nullptr, 0, &hl, -1,
                  s);
     if (c->precision == 1)
-      VcOps<float>::cast_in(g.n(), KG.xp, K.Zf + (size_t)j * K.ld + g.lo, nullptr, 0.0, nullptr, s);
+      VcOps<float>::cast_in(g.n(), KG.xp, K.Zf + (size_t)j * K.ld + g.lo, nullptr, 0.0, nullptr, nullptr, s);
     else
       HBGS_HIP(hipMemcpyAsync(K.Zd + (size_t)j * K.ld + g.lo, KG.xp, sizeof(double) * g.n(),
                               hipMemcpyDeviceToDevice, s));
@@ -1464,7 +1474,7 @@ static void nested_apply(hbgs_ctx* c, int tr, const double* v, int j, hipStream_
 
 static hbgs_status gmres(hbgs_ctx* c, int tr, int use_x0, int32_t* iters, double* hist, int cap, int32_t* hlen,
                          hipStream_t s) {
-  auto prec = [&](int j, const double* v, hipStream_t st) { apply_perm(c, tr, v, j, st); };
+  auto prec = [&](int j, const double* v, const double* vs, hipStream_t st) { apply_perm(c, tr, v, j, vs, st); };
   const int graph_key = c->o.nested ? -1 : c->precision * 2 + tr;
   return fgmres(c, c->K, tr ? c->ApT : c->Ap, prec, c->o.rtol, c->o.max_iters, use_x0, iters, hist, cap, hlen,
                 graph_key, s);
@@ -1732,7 +1742,7 @@ hbgs_status hbgs_apply(hbgs_ctx* c, const double* r, double* z, int32_t transpos
   if (transpose) ensure_transpose(c, s);
   Krylov& K = c->K;
   solve::permute_in(c->n, c->perm, r, K.bp, s);
-  apply_perm(c, transpose ? 1 : 0, K.bp, 0, s);
+  apply_perm(c, transpose ? 1 : 0, K.bp, 0, nullptr, s);
   const double* zp = K.Zd;
   if (c->precision == 1) {  // widen the FP32 result: tmp = 0 + 1 * Z_0
     K.host[4] = 1.0;

@@ -352,9 +352,10 @@ void spmv_outer_f64(const DCsr& a, const double* x, double* y, hipStream_t s, hi
                     hipEvent_t e1 = nullptr);
 void spmv_outer_mixed(const DCsr& a, const float* x, double* y, hipStream_t s, hipEvent_t e0 = nullptr,
                       hipEvent_t e1 = nullptr);
-// t = v - a z (FP64 values and result; z FP32 or FP64)
+// t = v / vs - a z (FP64 values and result; z FP32 or FP64; vs a device
+// scalar, or null for 1)
 template <class TZ>
-void couple_f64(const DCsr& a, const double* v, const TZ* z, double* t, hipStream_t s);
+void couple_f64(const DCsr& a, const double* v, const TZ* z, double* t, const double* vs, hipStream_t s);
 void spmv_resid_f64(const DCsr& a, const double* x, const double* b, double* r, hipStream_t s);
 
 template <class T>
@@ -381,12 +382,15 @@ struct VcOps {
                         hipStream_t s);
   static void prolong(const DCsr& p, const T* xc, T* x, hipStream_t s);
   static void coarse(int n, const double* inv, int transpose, const T* b, T* x, hipStream_t s);
-  // t = (T)v - sum over coupling columns of a * z, rows of one field; with
-  // d0 given also d0 = (D^-1 t) * c0 for the field's finest level
   static void ilu(const IluLeaf& f, int transpose, const T* t, T* z, hipStream_t s);
+  // t = (T)(v / vs) - sum over coupling columns of a * z, rows of one field;
+  // with d0 given also d0 = (D^-1 t) * c0 for the field's finest level.  vs
+  // is a device scalar (null: 1) by which the sweep's input is divided
   static void couple(const DCsr& c, const double* v, const T* z, T* t, const T* dinv, double c0, T* d0,
-                     hipStream_t s);
-  static void cast_in(int n, const double* v, T* t, const T* dinv, double c0, T* d0, hipStream_t s);
+                     const double* vs, hipStream_t s);
+  // t = (T)(v / vs), and d0 as in couple
+  static void cast_in(int n, const double* v, T* t, const T* dinv, double c0, T* d0, const double* vs,
+                      hipStream_t s);
 };
 
 // GMRES pieces (FP64)

@@ -385,11 +385,12 @@ struct EpiCouple {
   const T* __restrict__ dinv;
   T* __restrict__ d0;
   T c0;
+  const double* __restrict__ vs;  // divisor of v (null: none)
   struct Pre {
     double v;
     T dinv;
   };
-  __device__ Pre load(int i) const { return {v[i], d0 ? dinv[i] : T(0)}; }
+  __device__ Pre load(int i) const { return {vs ? v[i] / *vs : v[i], d0 ? dinv[i] : T(0)}; }
   __device__ void store(int i, T acc, Pre p) const {
     T ti = (T)p.v - acc;
     t[i] = ti;
@@ -397,14 +398,15 @@ struct EpiCouple {
   }
 };
 
-// group right-hand side of the nested form: t = v - sum a z (FP64 out)
+// group right-hand side of the nested form: t = v / vs - sum a z (FP64 out)
 struct EpiSubFrom {
   const double* __restrict__ v;
   double* __restrict__ t;
+  const double* __restrict__ vs;  // divisor of v (null: none)
   struct Pre {
     double v;
   };
-  __device__ Pre load(int i) const { return {v[i]}; }
+  __device__ Pre load(int i) const { return {vs ? v[i] / *vs : v[i]}; }
   __device__ void store(int i, double acc, Pre p) const { t[i] = p.v - acc; }
 };
 
@@ -416,11 +418,11 @@ void spmv_outer_mixed(const DCsr& a, const float* x, double* y, hipStream_t s, h
   launch_csr<double, double>(a, a.v, LoadArr<float>{x}, EpiStore<double, double>{y}, s, e0, e1);
 }
 template <class TZ>
-void couple_f64(const DCsr& a, const double* v, const TZ* z, double* t, hipStream_t s) {
-  launch_csr<double, double>(a, a.v, LoadArr<TZ>{z}, EpiSubFrom{v, t}, s);
+void couple_f64(const DCsr& a, const double* v, const TZ* z, double* t, const double* vs, hipStream_t s) {
+  launch_csr<double, double>(a, a.v, LoadArr<TZ>{z}, EpiSubFrom{v, t, vs}, s);
 }
-template void couple_f64<float>(const DCsr&, const double*, const float*, double*, hipStream_t);
-template void couple_f64<double>(const DCsr&, const double*, const double*, double*, hipStream_t);
+template void couple_f64<float>(const DCsr&, const double*, const float*, double*, const double*, hipStream_t);
+template void couple_f64<double>(const DCsr&, const double*, const double*, double*, const double*, hipStream_t);
 void spmv_resid_f64(const DCsr& a, const double* x, const double* b, double* r, hipStream_t s) {
   launch_csr<double, double>(a, a.v, LoadArr<double>{x}, EpiResid<double>{b, r}, s);
 }
@@ -516,22 +518,24 @@ void VcOps<T>::prolong(const DCsr& p, const T* xc, T* x, hipStream_t s) {
 }
 template <class T>
 void VcOps<T>::couple(const DCsr& c, const double* v, const T* z, T* t, const T* dinv, double c0, T* d0,
-                      hipStream_t s) {
-  launch_csr<T, T>(c, vals_of<T>(c), LoadArr<T>{z}, EpiCouple<T>{v, t, dinv, d0, (T)c0}, s);
+                      const double* vs, hipStream_t s) {
+  launch_csr<T, T>(c, vals_of<T>(c), LoadArr<T>{z}, EpiCouple<T>{v, t, dinv, d0, (T)c0, vs}, s);
 }
 
 template <class T>
 __global__ void k_cast_in(int n, const double* __restrict__ v, T* __restrict__ t, const T* __restrict__ dinv, T c0,
-                          T* __restrict__ d0) {
+                          T* __restrict__ d0, const double* __restrict__ vs) {
+  const double h = vs ? *vs : 1.0;
   for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
-    T ti = (T)v[i];
+    T ti = (T)(vs ? v[i] / h : v[i]);
     t[i] = ti;
     if (d0) d0[i] = dinv[i] * ti * c0;
   }
 }
 template <class T>
-void VcOps<T>::cast_in(int n, const double* v, T* t, const T* dinv, double c0, T* d0, hipStream_t s) {
-  k_cast_in<T><<<grid_for(n, BLK), BLK, 0, s>>>(n, v, t, dinv, (T)c0, d0);
+void VcOps<T>::cast_in(int n, const double* v, T* t, const T* dinv, double c0, T* d0, const double* vs,
+                       hipStream_t s) {
+  k_cast_in<T><<<grid_for(n, BLK), BLK, 0, s>>>(n, v, t, dinv, (T)c0, d0, vs);
   HBGS_HIP(hipGetLastError());
 }
 
