@@ -171,6 +171,23 @@ hbgs_status hbgs_set_tolerance(hbgs_ctx *ctx, double rtol, int32_t max_iters);
  * r, z: device, n doubles, caller's ordering; may not alias. */
 hbgs_status hbgs_apply(hbgs_ctx *ctx, const double *r, double *z, int32_t transpose, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): z = M^-1 r
+ * or M^-T r exactly as hbgs_apply computes it, with every temporary of the
+ * call (the permuted input and output, 16 bytes per row at most) in a fixed
+ * 64 MiB device buffer that the library holds on each device it runs on
+ * until the process ends.  The call allocates nothing and does not
+ * synchronise: it is enqueued on `stream` and z is ready when the stream
+ * reaches that point.  r, z: device, n doubles, caller's ordering; may not
+ * alias.  Returns HBGS_EINVAL (nothing enqueued) when the system has more
+ * than 4,194,304 rows, for a nested-form context (its inner solvers need
+ * their own workspace), or for transpose != 0 while the adjoint's operators
+ * do not exist (build_transpose = 0 and no transpose call since the last
+ * setup or value update).  Calls on one device share the buffer: calls
+ * that overlap in time on one device (several host threads, or streams
+ * that are not ordered with each other) race and must not be issued. */
+hbgs_status hbgs_apply_noalloc(hbgs_ctx *ctx, const double *r, double *z, int32_t transpose, void *stream);
+
 /* Solve A x = b (transpose = 0) or A^T x = b (transpose = 1) with flexible
  * right-preconditioned GMRES(m).  b, x: device, n doubles; x is the initial
  * guess when use_x0 != 0, else zero.  On return (stream synchronised):

@@ -62,6 +62,7 @@ EXPORTS = {
     "hbgs_set_precision": ("i32", ["p", "i32"]),
     "hbgs_set_tolerance": ("i32", ["p", "f64", "i32"]),
     "hbgs_apply": ("i32", ["p", "p", "p", "i32", "p"]),
+    "hbgs_apply_noalloc": ("i32", ["p", "p", "p", "i32", "p"]),
     "hbgs_solve": ("i32", ["p", "p", "p", "i32", "i32", "i32*", "p", "i32", "i32*", "p"]),
     "hbgs_grad_values": ("i32", ["p", "p", "p", "p", "p"]),
     "hbgs_stats": ("i32", ["p", "stats*"]),
@@ -220,6 +221,16 @@ class Solver:
         r = _dev(r, torch.float64, torch)
         z = torch.empty_like(r)
         _check(self.lib.hbgs_apply(self.h, r.data_ptr(), z.data_ptr(), int(transpose), _stream(torch)))
+        return z
+
+    def apply_noalloc(self, r, z, transpose=False):
+        """z = M^-1 r (or M^-T r) into the caller's z through the entry point
+        that allocates nothing; enqueued on the current stream, no sync."""
+        torch = self._torch
+        if not (r.is_cuda and z.is_cuda and r.dtype == z.dtype == torch.float64
+                and r.is_contiguous() and z.is_contiguous() and r.numel() == z.numel() == self.n):
+            raise ValueError("r and z must be contiguous float64 device tensors of n entries")
+        _check(self.lib.hbgs_apply_noalloc(self.h, r.data_ptr(), z.data_ptr(), int(transpose), _stream(torch)))
         return z
 
     def solve(self, b, x0=None, transpose=False, hist_cap=4096):

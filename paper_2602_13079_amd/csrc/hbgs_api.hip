@@ -30,6 +30,34 @@ Allocator current_allocator() {
   return g_alloc;
 }
 
+// Fixed device buffer of hbgs_apply_noalloc: the permuted input (8 bytes
+// per row) and the permuted output column (4 or 8 bytes per row), so at most
+// 16 bytes per row.  Each device that loads the library holds its own copy
+// until the process ends.  Host code never uses the array's name as an
+// address: hbgs_setup looks the address up once per device (with that
+// device current) and keeps it in scratch_dev.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int64_t kNoAllocMaxRows = (int64_t)(kNoAllocScratchBytes / 16);
+static __device__ __align__(256) double scratch[kNoAllocScratchBytes / sizeof(double)];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices] = {};
+
+// the device address of `scratch` on the current device (looked up once)
+static void* scratch_dev() {
+  int dev = 0;
+  HBGS_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) HBGS_FAIL(HBGS_EHIP, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HBGS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) HBGS_FAIL(HBGS_EHIP, "no device address for the fixed scratch buffer");
+    g_scratch_dev[dev] = p;
+  }
+  return g_scratch_dev[dev];
+}
+
 hipStream_t& tmp_stream() {
   static thread_local hipStream_t s = nullptr;
   return s;
@@ -389,6 +417,7 @@ struct hbgs_ctx {
   int64_t nnz = 0;
   hbgs::Pool pool;
   hbgs::Pool hier{true};  // value-dependent hierarchy (rebuilt by set_values; arena)
+  void* noalloc_scratch = nullptr;  // this device's fixed scratch buffer (hbgs_apply_noalloc)
   // setup temporaries: one scratch per field's build thread, the last for
   // the calling thread
   hbgs::Scratch scratch[HBGS_MAX_FIELDS + 1];
@@ -1586,6 +1615,7 @@ hbgs_status hbgs_setup(hbgs_ctx** out, int32_t n, int64_t nnz, const int32_t* ro
     (void)hipGetLastError();
   }
   c = new hbgs_ctx();
+  c->noalloc_scratch = scratch_dev();
   if (opt)
     c->o = *opt;
   else
@@ -1753,6 +1783,39 @@ hbgs_status hbgs_apply(hbgs_ctx* c, const double* r, double* z, int32_t transpos
   }
   solve::permute_out(c->n, c->perm, zp, z, s);
   HBGS_HIP(hipStreamSynchronize(s));
+  return HBGS_OK;
+  HBGS_API_END
+}
+
+hbgs_status hbgs_apply_noalloc(hbgs_ctx* c, const double* r, double* z, int32_t transpose, void* stream) {
+  if (!c || !r || !z) {
+    set_error("NULL argument");
+    return HBGS_EINVAL;
+  }
+  HBGS_API_BEGIN
+  hipStream_t s = (hipStream_t)stream;
+  if ((int64_t)c->n > kNoAllocMaxRows)
+    HBGS_FAIL(HBGS_EINVAL, "hbgs_apply_noalloc: " + std::to_string(c->n) + " rows exceed the fixed buffer's " +
+                               std::to_string(kNoAllocMaxRows) + "; use hbgs_apply");
+  if (c->o.nested) HBGS_FAIL(HBGS_EINVAL, "hbgs_apply_noalloc: the nested form needs the inner solvers' workspace");
+  if (transpose && !(c->apt_fresh && c->hier_t))
+    HBGS_FAIL(HBGS_EINVAL, "hbgs_apply_noalloc: the adjoint's operators are not built (build_transpose = 0 "
+                           "and no transpose call since the last setup or value update)");
+  if (!c->noalloc_scratch) HBGS_FAIL(HBGS_EHIP, "hbgs_apply_noalloc: no fixed scratch buffer");
+  // [0, 8n): the permuted input; then the output column, 256-byte aligned;
+  // both are written in full before they are read
+  char* base = static_cast<char*>(c->noalloc_scratch);
+  double* vp = reinterpret_cast<double*>(base);
+  void* zp = base + ((size_t)c->n * sizeof(double) + 255) / 256 * 256;
+  solve::permute_in(c->n, c->perm, r, vp, s);
+  const int tr = transpose ? 1 : 0;
+  if (c->precision == 1) {
+    sweep<float>(c, c->plan[tr], tr, vp, static_cast<float*>(zp), 0, nullptr, s);
+    solve::permute_out_f32(c->n, c->perm, static_cast<const float*>(zp), z, s);
+  } else {
+    sweep<double>(c, c->plan[tr], tr, vp, static_cast<double*>(zp), 0, nullptr, s);
+    solve::permute_out(c->n, c->perm, static_cast<const double*>(zp), z, s);
+  }
   return HBGS_OK;
   HBGS_API_END
 }

@@ -396,6 +396,7 @@ struct VcOps {
 // GMRES pieces (FP64)
 void permute_in(int n, const int* perm, const double* x, double* xp, hipStream_t s);   // xp[perm[i]] = x[i]
 void permute_out(int n, const int* perm, const double* xp, double* x, hipStream_t s);  // x[i] = xp[perm[i]]
+void permute_out_f32(int n, const int* perm, const float* xp, double* x, hipStream_t s);  // widening
 int dot_blocks(int n);
 // Givens step inputs: column j of the (m+1) x m Hessenberg matrix H, the
 // rotations cs/sn, the rotated right-hand side g, and where to put the

@@ -649,6 +649,15 @@ void permute_out(int n, const int* perm, const double* xp, double* x, hipStream_
   k_permute_out<<<grid_for(n, BLK), BLK, 0, s>>>(n, perm, xp, x);
   HBGS_HIP(hipGetLastError());
 }
+__global__ void k_permute_out_f32(int n, const int* __restrict__ perm, const float* __restrict__ xp,
+                                  double* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK)
+    x[i] = (double)xp[perm[i]];
+}
+void permute_out_f32(int n, const int* perm, const float* xp, double* x, hipStream_t s) {
+  k_permute_out_f32<<<grid_for(n, BLK), BLK, 0, s>>>(n, perm, xp, x);
+  HBGS_HIP(hipGetLastError());
+}
 
 constexpr int DOT_BLOCKS_MAX = 1024;
 int dot_blocks(int n) {
