@@ -36,7 +36,7 @@ def build(force: bool = False) -> str:
     src = os.path.join(_HERE, "hbgs_oracle.cpp")
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fPIC", "-shared",
+        subprocess.check_call(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
                                "-o", tmp, src])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -53,6 +53,8 @@ def _load():
         sig = {
             "or_default_options": (None, [P]),
             "or_last_error": (ctypes.c_char_p, []),
+            "or_set_threads": (None, [i32]),
+            "or_get_threads": (i32, []),
             "or_amg_setup": (vp, [i32, vp, vp, vp, f64, P, u64]),
             "or_amg_destroy": (None, [vp]),
             "or_amg_levels": (i32, [vp]),
@@ -84,6 +86,16 @@ def _load():
             fn.argtypes = args
         _lib = lib
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops (results are bitwise the same
+    for every count)."""
+    _load().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return _load().or_get_threads()
 
 
 def _p(a):

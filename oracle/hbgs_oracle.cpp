@@ -33,7 +33,15 @@
 // sequentially in ascending index order, products rounded before adding.
 // Setup reductions over long vectors use 256-element chunks summed in order,
 // then the chunk sums in order.
+//
+// Threads (OpenMP, for the CPU baseline timing only): loops whose iterations
+// are independent run in parallel -- rows of a sparse product, element-wise
+// vector updates, the rows of a dense elimination step, the fields'
+// hierarchy setups.  Every reduction (dot products, norms, maxima) and every
+// order-dependent step (aggregation, Gustavson products, transposes) stays
+// sequential, so results are bitwise the same for any thread count.
 #include <algorithm>
+#include <omp.h>
 #include <functional>
 #include <cmath>
 #include <cstdint>
@@ -144,6 +152,7 @@ std::vector<char> strength(const CsrD& a, double theta) {
       if (a.ci[k] == i) diag[i] = a.v[k];
   double th2 = theta * theta;
   std::vector<char> s(a.ci.size(), 0);
+#pragma omp parallel for schedule(static) if (a.n > 4096)
   for (int i = 0; i < a.n; ++i)
     for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) {
       int j = a.ci[k];
@@ -313,6 +322,7 @@ double power_estimate(const CsrD& b, const std::vector<double>& d, int iters, ui
   for (int i = 0; i < n; ++i)
     w[i] = 2.0 * ((double)(splitmix64((uint64_t)(uint32_t)i ^ salt) >> 11) * 0x1.0p-53) - 1.0;
   auto apply = [&]() {
+#pragma omp parallel for schedule(static) if (n > 4096)
     for (int i = 0; i < n; ++i) {
       double s = 0.0;
       for (int k = b.rp[i]; k < b.rp[i + 1]; ++k) s += b.v[k] * w[b.ci[k]];
@@ -326,6 +336,7 @@ double power_estimate(const CsrD& b, const std::vector<double>& d, int iters, ui
     if (mx == 0.0) return 0.0;
     int e;
     std::frexp(mx, &e);
+#pragma omp parallel for schedule(static) if (n > 4096)
     for (int i = 0; i < n; ++i) w[i] = std::ldexp(y[i], -e);
   }
   apply();
@@ -425,6 +436,7 @@ bool lu_factor(const CsrD& a, DenseLU& f) {
     if (best == 0.0) return false;
     if (p != k)
       for (int j = 0; j < n; ++j) std::swap(m[(size_t)k * n + j], m[(size_t)p * n + j]);
+#pragma omp parallel for schedule(static) if (n - k > 256)
     for (int i = k + 1; i < n; ++i) {
       double l = m[(size_t)i * n + k] / m[(size_t)k * n + k];
       m[(size_t)i * n + k] = l;
@@ -481,7 +493,7 @@ struct Status {
 };
 Status g_err;
 
-int setup_amg(const CsrD& a0, double theta, const or_options& o, uint64_t salt_base, Amg& h) {
+int setup_amg(const CsrD& a0, double theta, const or_options& o, uint64_t salt_base, Amg& h, Status& err) {
   h.theta = theta;
   h.lv.clear();
   h.lv.emplace_back();
@@ -500,7 +512,7 @@ int setup_amg(const CsrD& a0, double theta, const or_options& o, uint64_t salt_b
         filter(L.A, s, af, dabs);
         L.lam_p = power_estimate(af, dabs, o.eig_iters, splitmix64(salt_base + 0x5000 + l));
         if (!(L.lam_p > 0.0)) {
-          g_err = {-5, "non-positive eigenvalue estimate for prolongator smoothing"};
+          err = {-5, "non-positive eigenvalue estimate for prolongator smoothing"};
           return -5;
         }
         L.omega = o.omega_override >= 0 ? o.omega_override : o.sa_damping / L.lam_p;
@@ -516,11 +528,11 @@ int setup_amg(const CsrD& a0, double theta, const or_options& o, uint64_t salt_b
     Level& M = h.lv[l];
     if (last) {
       if (M.A.n > 8000) {
-        g_err = {-5, "coarsest level too large for a dense factorisation"};
+        err = {-5, "coarsest level too large for a dense factorisation"};
         return -5;
       }
       if (!lu_factor(M.A, h.lu)) {
-        g_err = {-4, "singular coarsest-level matrix"};
+        err = {-4, "singular coarsest-level matrix"};
         return -4;
       }
       break;
@@ -533,7 +545,7 @@ int setup_amg(const CsrD& a0, double theta, const or_options& o, uint64_t salt_b
         if (M.A.ci[k] == i) d[i] = M.A.v[k];
     for (int i = 0; i < M.A.n; ++i) {
       if (d[i] == 0.0) {
-        g_err = {-1, "zero diagonal entry"};
+        err = {-1, "zero diagonal entry"};
         return -1;
       }
       M.dinv[i] = 1.0 / d[i];
@@ -573,6 +585,7 @@ const std::vector<float>& dinv_of<float>(const Level& L) { return L.dinvf; }
 
 template <class T>
 void spmv(const Csr<T>& a, const T* x, T* y) {
+#pragma omp parallel for schedule(static) if (a.n > 4096)
   for (int i = 0; i < a.n; ++i) {
     T s = 0;
     for (int k = a.rp[i]; k < a.rp[i + 1]; ++k) s += a.v[k] * x[a.ci[k]];
@@ -593,12 +606,15 @@ void chebyshev(const Level& L, const or_options& o, int transpose, const T* b, T
   double sigma = theta / delta, rho = 1.0 / sigma;
   std::vector<T> r(n), d(n), ad(n);
   if (zero) {
+#pragma omp parallel for schedule(static) if (n > 4096)
     for (int i = 0; i < n; ++i) r[i] = b[i];
   } else {
     spmv(A, x, ad.data());
+#pragma omp parallel for schedule(static) if (n > 4096)
     for (int i = 0; i < n; ++i) r[i] = b[i] - ad[i];
   }
   T c0 = (T)(1.0 / theta);
+#pragma omp parallel for schedule(static) if (n > 4096)
   for (int i = 0; i < n; ++i) {
     d[i] = dinv[i] * r[i] * c0;
     x[i] = zero ? d[i] : x[i] + d[i];
@@ -607,6 +623,7 @@ void chebyshev(const Level& L, const or_options& o, int transpose, const T* b, T
     spmv(A, d.data(), ad.data());
     double rho_new = 1.0 / (2.0 * sigma - rho);
     T c1 = (T)(rho_new * rho), c2 = (T)(2.0 * rho_new / delta);
+#pragma omp parallel for schedule(static) if (n > 4096)
     for (int i = 0; i < n; ++i) {
       r[i] = r[i] - ad[i];
       d[i] = c1 * d[i] + c2 * (dinv[i] * r[i]);
@@ -635,10 +652,12 @@ void vcycle(const Amg& h, const or_options& o, int l, int transpose, const T* b,
   chebyshev<T>(L, o, transpose, b, x, true);
   std::vector<T> r(n), ax(n), bc(R.n), xc(R.n), e(n);
   spmv(A, x, ax.data());
+#pragma omp parallel for schedule(static) if (n > 4096)
   for (int i = 0; i < n; ++i) r[i] = b[i] - ax[i];
   spmv(R, r.data(), bc.data());
   vcycle<T>(h, o, l + 1, transpose, bc.data(), xc.data());
   spmv(P, xc.data(), e.data());
+#pragma omp parallel for schedule(static) if (n > 4096)
   for (int i = 0; i < n; ++i) x[i] = x[i] + e[i];
   chebyshev<T>(L, o, transpose, b, x, false);
 }
@@ -873,6 +892,7 @@ void bgs_node(const Ctx& c, int id, int transpose, const T* r, T* z) {
       chi = nd.hi;
     }
     std::vector<T> t(c.n, (T)0);
+#pragma omp parallel for schedule(static) if (ch.hi - ch.lo > 4096)
     for (int i = ch.lo; i < ch.hi; ++i) {
       T s = r[i];
       if (!c.o.block_jacobi)
@@ -890,8 +910,10 @@ void bgs_node(const Ctx& c, int id, int transpose, const T* r, T* z) {
 void node_sweep(const Ctx& c, int id, int transpose, const double* r, double* z) {
   if (c.o.precision == 1) {
     std::vector<float> rf(c.n, 0.0f), zf(c.n, 0.0f);
+#pragma omp parallel for schedule(static) if (c.n > 4096)
     for (int i = 0; i < c.n; ++i) rf[i] = (float)r[i];
     bgs_node<float>(c, id, transpose, rf.data(), zf.data());
+#pragma omp parallel for schedule(static) if (c.n > 4096)
     for (int i = 0; i < c.n; ++i) z[i] = (double)zf[i];
   } else {
     std::vector<double> zz(c.n, 0.0);
@@ -929,6 +951,7 @@ int fgmres(const CsrD& A, int m, double rtol, int max_iters, const std::function
   std::vector<double> r(n), ax(n);
   auto true_resid = [&]() {
     spmv(A, x.data(), ax.data());
+#pragma omp parallel for schedule(static) if (n > 4096)
     for (int i = 0; i < n; ++i) r[i] = b[i] - ax[i];
     return std::sqrt(dot(r, r));
   };
@@ -940,6 +963,7 @@ int fgmres(const CsrD& A, int m, double rtol, int max_iters, const std::function
   for (;;) {
     if (beta / bnorm <= rtol) return 0;
     if (*iters >= max_iters) return 1;
+#pragma omp parallel for schedule(static) if (n > 4096)
     for (int i = 0; i < n; ++i) V[0][i] = r[i] / beta;
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
@@ -951,14 +975,18 @@ int fgmres(const CsrD& A, int m, double rtol, int max_iters, const std::function
       for (int pass = 0; pass < 2; ++pass) {
         std::vector<double>& hh = pass == 0 ? h1 : h2;
         for (int k = 0; k <= j; ++k) hh[k] = dot(V[k], w);
-        for (int k = 0; k <= j; ++k)
-          for (int i = 0; i < n; ++i) w[i] -= hh[k] * V[k][i];
+        // w -= V hh, each element in ascending k
+#pragma omp parallel for schedule(static) if (n > 4096)
+        for (int i = 0; i < n; ++i)
+          for (int k = 0; k <= j; ++k) w[i] -= hh[k] * V[k][i];
       }
       for (int k = 0; k <= j; ++k) Hs(k, j) = h1[k] + h2[k];
       double hn = std::sqrt(dot(w, w));
       Hs(j + 1, j) = hn;
-      if (hn > 0.0)
+      if (hn > 0.0) {
+#pragma omp parallel for schedule(static) if (n > 4096)
         for (int i = 0; i < n; ++i) V[j + 1][i] = w[i] / hn;
+      }
       for (int k = 0; k < j; ++k) {
         double t1 = cs[k] * Hs(k, j) + sn[k] * Hs(k + 1, j);
         double t2 = -sn[k] * Hs(k, j) + cs[k] * Hs(k + 1, j);
@@ -985,8 +1013,10 @@ int fgmres(const CsrD& A, int m, double rtol, int max_iters, const std::function
       for (int k = i + 1; k < jend; ++k) s -= Hs(i, k) * y[k];
       y[i] = s / Hs(i, i);
     }
-    for (int k = 0; k < jend; ++k)
-      for (int i = 0; i < n; ++i) x[i] += y[k] * Z[k][i];
+    // x += Z y, each element in ascending k
+#pragma omp parallel for schedule(static) if (n > 4096)
+    for (int i = 0; i < n; ++i)
+      for (int k = 0; k < jend; ++k) x[i] += y[k] * Z[k][i];
     beta = true_resid();
     if (hist && *hlen - 1 < cap) hist[*hlen - 1] = beta / bnorm;
   }
@@ -1084,6 +1114,9 @@ void or_default_options(or_options* o) {
 }
 
 const char* or_last_error(void) { return g_err.msg.c_str(); }
+// threads of the parallel loops (results do not depend on it)
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_get_threads(void) { return omp_get_max_threads(); }
 
 static CsrD make_csr(int n, int m, const int* rp, const int* ci, const double* v) {
   CsrD a;
@@ -1103,7 +1136,7 @@ or_amg* or_amg_setup(int n, const int* rp, const int* ci, const double* v, doubl
                      const or_options* o, uint64_t salt) {
   Amg* h = new Amg();
   CsrD a = make_csr(n, n, rp, ci, v);
-  if (setup_amg(a, theta, *o, salt, *h) != 0) {
+  if (setup_amg(a, theta, *o, salt, *h, g_err) != 0) {
     delete h;
     return nullptr;
   }
@@ -1276,21 +1309,21 @@ or_ctx* or_setup(int n, const int* rp, const int* ci, const double* v, int nf, c
   c->ilu.resize(nf);
   c->dinv.resize(nf);
   c->dinvf.resize(nf);
-  for (int f = 0; f < nf; ++f) {
+  for (int f = 0; f < nf; ++f)
     if (o->field_leaf[f] < 0 || o->field_leaf[f] > 2 || o->ilu_block < 1) {
       g_err = {-1, "invalid leaf solver options"};
       delete c;
       return nullptr;
     }
+  // the fields' leaf setups are independent: one field per thread
+  std::vector<Status> st(nf);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int f = 0; f < nf; ++f) {
     CsrD blk = block(ap, c->f_lo[f], c->f_hi[f]);
     c->dinv[f].assign(blk.n, 0.0);
     c->dinvf[f].assign(blk.n, 0.0f);
     if (o->exact_leaves) {
-      if (!lu_factor(blk, c->exact[f])) {
-        g_err = {-4, "singular diagonal block"};
-        delete c;
-        return nullptr;
-      }
+      if (!lu_factor(blk, c->exact[f])) st[f] = {-4, "singular diagonal block"};
     } else if (o->field_leaf[f] == 1) {
       std::vector<double> d(blk.n, 0.0);
       for (int i = 0; i < blk.n; ++i)
@@ -1298,27 +1331,24 @@ or_ctx* or_setup(int n, const int* rp, const int* ci, const double* v, int nf, c
           if (blk.ci[k] == i) d[i] = blk.v[k];
       for (int i = 0; i < blk.n; ++i) {
         if (d[i] == 0.0) {
-          g_err = {-1, "zero diagonal entry"};
-          delete c;
-          return nullptr;
+          st[f] = {-1, "zero diagonal entry"};
+          break;
         }
         c->dinv[f][i] = 1.0 / d[i];
         c->dinvf[f][i] = (float)c->dinv[f][i];
       }
     } else if (o->field_leaf[f] == 2) {
-      if (!ilu0_setup(blk, o->ilu_block, c->ilu[f])) {
-        g_err = {-4, "zero pivot in the incomplete factorisation"};
-        delete c;
-        return nullptr;
-      }
+      if (!ilu0_setup(blk, o->ilu_block, c->ilu[f])) st[f] = {-4, "zero pivot in the incomplete factorisation"};
     } else {
-      int rc = setup_amg(blk, o->theta[f], c->fo[f], field_salt(o->seed, f), c->amg[f]);
-      if (rc != 0) {
-        delete c;
-        return nullptr;
-      }
+      setup_amg(blk, o->theta[f], c->fo[f], field_salt(o->seed, f), c->amg[f], st[f]);
     }
   }
+  for (int f = 0; f < nf; ++f)
+    if (st[f].code != 0) {
+      g_err = st[f];
+      delete c;
+      return nullptr;
+    }
   return c;
 }
 
@@ -1330,8 +1360,10 @@ const or_amg* or_field_amg(const or_ctx* c, int f) { return &c->amg[f]; }
 // z = M^-1 r (or M^-T r), vectors in the original ordering
 void or_apply(const or_ctx* c, const double* r, double* z, int transpose) {
   std::vector<double> rp(c->n), zp(c->n);
+#pragma omp parallel for schedule(static) if (c->n > 4096)
   for (int i = 0; i < c->n; ++i) rp[c->perm[i]] = r[i];
   precond(*c, transpose, rp.data(), zp.data());
+#pragma omp parallel for schedule(static) if (c->n > 4096)
   for (int i = 0; i < c->n; ++i) z[i] = zp[c->perm[i]];
 }
 
