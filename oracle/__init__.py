@@ -55,6 +55,7 @@ def _load():
             "or_last_error": (ctypes.c_char_p, []),
             "or_set_threads": (None, [i32]),
             "or_get_threads": (i32, []),
+            "or_set_verbose": (None, [i32]),
             "or_amg_setup": (vp, [i32, vp, vp, vp, f64, P, u64]),
             "or_amg_destroy": (None, [vp]),
             "or_amg_levels": (i32, [vp]),
@@ -72,6 +73,7 @@ def _load():
             "or_lu_solve": (i32, [i32, vp, vp, vp, vp, vp, i32]),
             "or_setup": (vp, [i32, vp, vp, vp, i32, vp, i32, vp, P]),
             "or_destroy": (None, [vp]),
+            "or_set_precision": (None, [vp, i32]),
             "or_levels": (i32, [vp, i32]),
             "or_field_amg": (vp, [vp, i32]),
             "or_apply": (None, [vp, vp, vp, i32]),
@@ -96,6 +98,11 @@ def set_threads(n: int) -> None:
 
 def get_threads() -> int:
     return _load().or_get_threads()
+
+
+def set_verbose(on: bool) -> None:
+    """Progress lines on stderr while a system's fields are set up."""
+    _load().or_set_verbose(int(bool(on)))
 
 
 def _p(a):
@@ -286,6 +293,12 @@ class Oracle:
         if getattr(self, "h", None):
             self._lib.or_destroy(self.h)
             self.h = None
+
+    def set_precision(self, precision):
+        """Precision mode of later applies and solves (0 double, 1 single-
+        precision sweep); the hierarchy is the same for both."""
+        self._lib.or_set_precision(self.h, int(precision))
+        self.opts.precision = int(precision)
 
     def amg(self, f) -> Amg:
         return Amg(None, None, None, opts=self.opts, _handle=self._lib.or_field_amg(self.h, f), _owner=self)

@@ -492,6 +492,7 @@ struct Status {
   std::string msg;
 };
 Status g_err;
+int g_verbose = 0;  // progress lines on stderr during the system setup
 
 int setup_amg(const CsrD& a0, double theta, const or_options& o, uint64_t salt_base, Amg& h, Status& err) {
   h.theta = theta;
@@ -1117,6 +1118,7 @@ const char* or_last_error(void) { return g_err.msg.c_str(); }
 // threads of the parallel loops (results do not depend on it)
 void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 int or_get_threads(void) { return omp_get_max_threads(); }
+void or_set_verbose(int on) { g_verbose = on; }
 
 static CsrD make_csr(int n, int m, const int* rp, const int* ci, const double* v) {
   CsrD a;
@@ -1317,8 +1319,10 @@ or_ctx* or_setup(int n, const int* rp, const int* ci, const double* v, int nf, c
     }
   // the fields' leaf setups are independent: one field per thread
   std::vector<Status> st(nf);
+  if (g_verbose) std::fprintf(stderr, "oracle: %d rows permuted; building %d field blocks\n", n, nf);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int f = 0; f < nf; ++f) {
+    const double t0 = omp_get_wtime();
     CsrD blk = block(ap, c->f_lo[f], c->f_hi[f]);
     c->dinv[f].assign(blk.n, 0.0);
     c->dinvf[f].assign(blk.n, 0.0f);
@@ -1342,6 +1346,8 @@ or_ctx* or_setup(int n, const int* rp, const int* ci, const double* v, int nf, c
     } else {
       setup_amg(blk, o->theta[f], c->fo[f], field_salt(o->seed, f), c->amg[f], st[f]);
     }
+    if (g_verbose)
+      std::fprintf(stderr, "oracle: field %d (%d rows) set up in %.1f s\n", f, blk.n, omp_get_wtime() - t0);
   }
   for (int f = 0; f < nf; ++f)
     if (st[f].code != 0) {
@@ -1353,6 +1359,8 @@ or_ctx* or_setup(int n, const int* rp, const int* ci, const double* v, int nf, c
 }
 
 void or_destroy(or_ctx* c) { delete c; }
+// precision mode of later applies and solves (the hierarchy does not depend on it)
+void or_set_precision(or_ctx* c, int precision) { c->o.precision = precision; }
 
 int or_levels(const or_ctx* c, int f) { return (int)c->amg[f].lv.size(); }
 const or_amg* or_field_amg(const or_ctx* c, int f) { return &c->amg[f]; }
