@@ -254,6 +254,17 @@ int32_t hbgs_kernel_times(hbgs_ctx *ctx, char (*names)[48], double *total_ms, in
 hbgs_status hbgs_set_allocator(void *(*alloc)(size_t bytes, void *user), void (*free)(void *ptr, void *user),
                                void *user);
 
+/* Test knob (process-wide; not to be called concurrently with hbgs_setup or
+ * hbgs_set_values): the kernel path that every row of the Galerkin products'
+ * sparse matrix products (eq. galerkin) takes.  0 (default): by the row's
+ * size (narrow LDS tables shared by several rows, one wavefront per row, one
+ * block per row, global-memory tables); 1: one wavefront per row; 2: the
+ * numeric rows one block each; 3: every row through the global-memory
+ * tables.  Every path accumulates each entry's products in ascending order
+ * of the inner index, so the hierarchy is bitwise the same on each route.
+ * Returns HBGS_EINVAL for any other value. */
+hbgs_status hbgs_debug_spgemm_route(int32_t route);
+
 void hbgs_destroy(hbgs_ctx *ctx);
 const char *hbgs_last_error(void);
 

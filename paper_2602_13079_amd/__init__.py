@@ -71,6 +71,7 @@ EXPORTS = {
     "hbgs_profile": ("i32", ["p", "i32"]),
     "hbgs_kernel_times": ("i32", ["p", "p", "p", "p", "p", "i32"]),
     "hbgs_set_allocator": ("i32", ["p", "p", "p"]),
+    "hbgs_debug_spgemm_route": ("i32", ["i32"]),
     "hbgs_destroy": (None, ["p"]),
     "hbgs_last_error": ("str", []),
 }
@@ -123,6 +124,12 @@ def _check(code):
     return code
 
 
+def _values_key(val):
+    """Identity of a value tensor's current contents: storage address and
+    in-place version counter."""
+    return (val.data_ptr(), getattr(val, "_version", 0), val.numel())
+
+
 def _stream(torch):
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -164,6 +171,12 @@ def set_allocator(alloc=None, free=None):
     _alloc_hooks.append(hooks)
 
 
+def debug_spgemm_route(route: int = 0):
+    """Process-wide test knob: the kernel path of every sparse product row in
+    the Galerkin products (0 by size, 1 wavefront, 2 block, 3 global tables)."""
+    _check(load().hbgs_debug_spgemm_route(int(route)))
+
+
 def use_torch_allocator(enable=True):
     """Serve Solver memory from torch's caching allocator (or stop doing so)."""
     if not enable:
@@ -184,6 +197,7 @@ class Solver:
         import torch
         self._torch = torch
         self.lib = load()
+        values_key = _values_key(val)
         rowptr = _dev(rowptr, torch.int32, torch)
         col = _dev(col, torch.int32, torch)
         val = _dev(val, torch.float64, torch)
@@ -198,6 +212,7 @@ class Solver:
                                    val.data_ptr(), n_fields, field_of_row.data_ptr(), len(tree), tr,
                                    ctypes.byref(self.opts), _stream(torch)))
         self.h = h
+        self._values_key = values_key
 
     def __del__(self):
         if getattr(self, "h", None) and self.h.value:
@@ -213,8 +228,10 @@ class Solver:
 
     def set_values(self, val, rebuild=True):
         """New values on the same pattern; rebuild=False keeps the preconditioner."""
+        key = _values_key(val)
         val = _dev(val, self._torch.float64, self._torch)
         _check(self.lib.hbgs_set_values(self.h, val.data_ptr(), int(rebuild), _stream(self._torch)))
+        self._values_key = key
 
     def apply(self, r, transpose=False):
         torch = self._torch
@@ -248,10 +265,10 @@ class Solver:
 
     def grad_values(self, lam, x):
         torch = self._torch
+        lam = _dev(lam, torch.float64, torch)  # kept alive until the kernel is enqueued
+        x = _dev(x, torch.float64, torch)
         g = torch.empty(self.nnz, dtype=torch.float64, device=lam.device)
-        _check(self.lib.hbgs_grad_values(self.h, _dev(lam, torch.float64, torch).data_ptr(),
-                                         _dev(x, torch.float64, torch).data_ptr(), g.data_ptr(),
-                                         _stream(torch)))
+        _check(self.lib.hbgs_grad_values(self.h, lam.data_ptr(), x.data_ptr(), g.data_ptr(), _stream(torch)))
         return g
 
     def stats(self) -> dict:
@@ -340,6 +357,8 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, val, b, solver):
+            if _values_key(val) != solver._values_key:  # new values: rebuild the preconditioner
+                solver.set_values(val)
             x, st, it, _ = solver.solve(b)
             if st != 0:
                 raise HBGSError(st, f"forward solve did not converge ({it} iterations)")
@@ -364,7 +383,9 @@ _HBGSSolve = None
 
 
 def hbgs_solve(val, b, solver: Solver):
-    """Differentiable solve (val must be the values the solver was set up with)."""
+    """Differentiable solve x = A(val)^-1 b.  When val is not the tensor (or
+    its version) the solver last saw, its values are loaded first (with a
+    preconditioner rebuild)."""
     global _HBGSSolve
     if _HBGSSolve is None:
         _HBGSSolve = _autograd_function()

@@ -1954,6 +1954,15 @@ int32_t hbgs_kernel_times(hbgs_ctx* c, char (*names)[48], double* total_ms, int6
   return k;
 }
 
+hbgs_status hbgs_debug_spgemm_route(int32_t route) {
+  if (route < 0 || route > 3) {
+    set_error("spgemm route must be 0, 1, 2 or 3");
+    return HBGS_EINVAL;
+  }
+  setup::set_spgemm_route(route);
+  return HBGS_OK;
+}
+
 hbgs_status hbgs_set_allocator(void* (*alloc)(size_t, void*), void (*free_fn)(void*, void*), void* user) {
   if ((alloc == nullptr) != (free_fn == nullptr)) {
     set_error("hbgs_set_allocator: give both functions or neither");

@@ -284,6 +284,9 @@ void psmooth_fill(const DCsr& af, const int* agg, const double* dabs, double ome
 
 // C = A B with in-order accumulation; allocates C's arrays from pool
 void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s);
+// kernel path of every product row (tests): 0 by row size, 1 one wavefront
+// per row, 2 numeric rows one block each, 3 global-memory tables
+void set_spgemm_route(int route);
 
 // dense coarsest factor: returns 0 ok, -4 singular; inv (row-major n*n) = A^-1
 int dense_inverse(const DCsr& a, double* inv, hipStream_t s);

@@ -8,6 +8,7 @@
 // that read its entries with coalesced loads and combine them with
 // cross-lane shuffles, adding order-dependent sums in entry order.  Only
 // integer decisions and order-independent max reductions use atomics.
+#include <atomic>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -1061,8 +1062,6 @@ constexpr int SPG_NUM_SLOTS = 512;    // numeric: keys and values per wave (6 KB
 constexpr int SPG_BLK_SLOTS = 4096;  // numeric, one block per row: keys and values (48 KB)
 // distinct columns of a product row are at most min(ub, columns of B)
 __device__ __forceinline__ int64_t sym_need(int64_t ub, int m) { return ub < m ? ub : (int64_t)m; }
-__device__ __forceinline__ bool num_fits(int64_t cnt) { return 2 * cnt <= SPG_NUM_SLOTS; }
-__device__ __forceinline__ bool num_fits_block(int64_t cnt) { return 2 * cnt <= SPG_BLK_SLOTS; }
 
 // slot holding key c (claimed if absent); -1 if the table is full, which
 // the table sizes rule out (the caller reports it instead of looping);
@@ -1384,18 +1383,23 @@ __global__ void k_spgemm_numeric(int r0, int r1, const int* arp, const int* aci,
     }
   }
 }
+// every row with products goes to the global-table pass (route 3)
+__global__ void k_spgemm_mark_all(int n, const int64_t* ub, int* cnt) {
+  GRID_STRIDE(i, n) cnt[i] = ub[i] > 0 ? -1 : 0;
+}
 // global table sizes of the rows the group kernels marked (cnt < 0)
 __global__ void k_spgemm_tsize_sym(int n, int bm, const int64_t* ub, const int* cnt, int64_t* ts) {
   GRID_STRIDE(i, n) ts[i] = cnt[i] < 0 ? table_size(sym_need(ub[i], bm)) : 0;
 }
-// rows for the one-block-per-row kernel are listed; rows beyond it get a
-// global table
-__global__ void k_spgemm_tsize_num(int n, const int* crp, int64_t* ts, int* nmid, int* mid) {
+// rows beyond the wave kernels (more than wave_max entries) are listed for
+// the one-block-per-row kernel; rows beyond it (block_max) get a global table
+__global__ void k_spgemm_tsize_num(int n, const int* crp, int64_t wave_max, int64_t block_max, int64_t* ts,
+                                   int* nmid, int* mid) {
   GRID_STRIDE(i, n) {
     const int64_t cnt = crp[i + 1] - crp[i];
     ts[i] = 0;
-    if (num_fits(cnt)) continue;
-    if (num_fits_block(cnt))
+    if (cnt <= wave_max) continue;
+    if (cnt <= block_max)
       mid[atomicAdd(nmid, 1)] = (int)i;
     else
       ts[i] = table_size(cnt);
@@ -1464,8 +1468,15 @@ static int64_t batch_rows(const std::vector<int64_t>& off, int n, std::vector<in
   return maxbatch;
 }
 
+static std::atomic<int> g_spgemm_route{0};
+void set_spgemm_route(int route) { g_spgemm_route.store(route); }
+
 void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
   const int n = a.n;
+  // route: 0 by row size; 1 every row to the one-row-per-wavefront kernels;
+  // 2 numeric rows to the one-block-per-row kernel; 3 every row to the
+  // global-memory tables (the paths give bitwise the same product)
+  const int route = g_spgemm_route.load();
   c.n = n;
   c.m = b.m;
   Tmp<int64_t> ub(n), ts(n), toff(n + 1);
@@ -1477,7 +1488,10 @@ void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
   // group tables go to the one-row-per-wavefront kernels
   const double bavg = b.n ? (double)b.nnz / b.n : 0.0;
   const int lpr = bavg <= 8.0 ? 8 : bavg <= 16.0 ? 16 : bavg <= 32.0 ? 32 : 64;
-  const int64_t sym_g = SPG_SYM_SLOTS / (64 / lpr) / 2, num_g = SPG_NUM_SLOTS / (64 / lpr) / 2;
+  const int64_t sym_g = route ? 0 : SPG_SYM_SLOTS / (64 / lpr) / 2;
+  const int64_t num_g = route ? 0 : SPG_NUM_SLOTS / (64 / lpr) / 2;
+  const int64_t num_w = route >= 2 ? 0 : SPG_NUM_SLOTS / 2;              // wave kernel's rows
+  const int64_t num_b = route == 3 ? 0 : SPG_BLK_SLOTS / 2;              // block kernel's rows
   auto groups = [&](int l) { return (unsigned)(((int64_t)n + (int64_t)SPG_WAVES * (64 / l) - 1) / (SPG_WAVES * (64 / l))); };
   // the wide kernels stride over the listed rows (every row when lpr = 64)
   Tmp<int> wide(lpr < 64 ? n : 1), nwide(1);
@@ -1489,16 +1503,21 @@ void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
 #define HBGS_SYM(L)                                                                                            \
   k_spgemm_sym_grp<L><<<groups(L), 64 * SPG_WAVES, 0, s>>>(n, b.m, a.rp, a.ci, b.rp, b.ci, ub.p, sym_g, cnt.p, \
                                                            overflow.p)
-  switch (lpr) {
-    case 8: HBGS_SYM(8); break;
-    case 16: HBGS_SYM(16); break;
-    case 32: HBGS_SYM(32); break;
-    default: break;
+  if (route == 3) {
+    k_spgemm_mark_all<<<grid_for(n, BLK), BLK, 0, s>>>(n, ub.p, cnt.p);
+  } else {
+    switch (lpr) {
+      case 8: HBGS_SYM(8); break;
+      case 16: HBGS_SYM(16); break;
+      case 32: HBGS_SYM(32); break;
+      default: break;
+    }
+    if (lpr < 64)
+      k_spgemm_list<<<grid_for(n, BLK, 8192), BLK, 0, s>>>(n, ub.p, b.m, nullptr, sym_g, INT64_MAX, wide.p,
+                                                           nwide.p);
+    k_spgemm_sym_wave<<<wgrid, 64 * SPG_WAVES, 0, s>>>(n, b.m, a.rp, a.ci, b.rp, b.ci, ub.p, wl, wn, cnt.p);
   }
 #undef HBGS_SYM
-  if (lpr < 64)
-    k_spgemm_list<<<grid_for(n, BLK, 8192), BLK, 0, s>>>(n, ub.p, b.m, nullptr, sym_g, INT64_MAX, wide.p, nwide.p);
-  k_spgemm_sym_wave<<<wgrid, 64 * SPG_WAVES, 0, s>>>(n, b.m, a.rp, a.ci, b.rp, b.ci, ub.p, wl, wn, cnt.p);
   HBGS_HIP(hipGetLastError());
   k_spgemm_tsize_sym<<<grid_for(n, BLK), BLK, 0, s>>>(n, b.m, ub.p, cnt.p, ts.p);
   HBGS_HIP(hipGetLastError());
@@ -1534,14 +1553,13 @@ void spgemm(const DCsr& a, const DCsr& b, DCsr& c, Pool& pool, hipStream_t s) {
   }
 #undef HBGS_NUM
   if (lpr < 64)
-    k_spgemm_list<<<grid_for(n, BLK, 8192), BLK, 0, s>>>(n, nullptr, 0, c.rp, num_g, SPG_NUM_SLOTS / 2, wide.p,
-                                                         nwide.p);
-  k_spgemm_num_grp<64><<<wgrid, 64 * SPG_WAVES, 0, s>>>(n, a.rp, a.ci, a.v, b.rp, b.ci, b.v, c.rp, SPG_NUM_SLOTS / 2,
-                                                         wl, wn, c.ci, c.v, overflow.p);
+    k_spgemm_list<<<grid_for(n, BLK, 8192), BLK, 0, s>>>(n, nullptr, 0, c.rp, num_g, num_w, wide.p, nwide.p);
+  k_spgemm_num_grp<64><<<wgrid, 64 * SPG_WAVES, 0, s>>>(n, a.rp, a.ci, a.v, b.rp, b.ci, b.v, c.rp, num_w, wl, wn,
+                                                         c.ci, c.v, overflow.p);
   HBGS_HIP(hipGetLastError());
   Tmp<int> nmid(1), mid(n);
   HBGS_HIP(hipMemsetAsync(nmid.p, 0, sizeof(int), s));
-  k_spgemm_tsize_num<<<grid_for(n, BLK), BLK, 0, s>>>(n, c.rp, ts.p, nmid.p, mid.p);
+  k_spgemm_tsize_num<<<grid_for(n, BLK), BLK, 0, s>>>(n, c.rp, num_w, num_b, ts.p, nmid.p, mid.p);
   HBGS_HIP(hipGetLastError());
   int h_nmid = 0;
   HBGS_HIP(hipMemcpyAsync(&h_nmid, nmid.p, sizeof(int), hipMemcpyDeviceToHost, s));

@@ -106,6 +106,32 @@ def test_hierarchy_bit_exact(torch_dev, case):
                 assert sc == oa.scalars(l), (f, l)
 
 
+@pytest.mark.parametrize("route", [1, 2, 3])
+@pytest.mark.parametrize("case", ["cfg0_cm64", "ragged7x5x9_6f_cm40", "cfg1"])
+def test_spgemm_routes_bit_exact(torch_dev, case, route):
+    """Every row of the Galerkin products forced through one kernel path (1:
+    one wavefront per row, 2: numeric rows one block each, 3: global-memory
+    tables, symbolic and numeric): the coarse operators still equal the
+    oracle's bitwise, level by level."""
+    torch, dev = torch_dev
+    import paper_2602_13079_amd as H
+    s, _, o = _pair(torch_dev, case)
+    H.debug_spgemm_route(route)
+    try:
+        g = _solver(torch, dev, s, coarse_max=CASES[case]["coarse_max"])
+    finally:
+        H.debug_spgemm_route(0)
+    for f in range(s.nf):
+        oa = o.amg(f)
+        assert oa.levels == g.stats()["levels"][f]
+        for l in range(1, oa.levels):
+            for w in ("A", "AT"):
+                gr, gc, gv, _ = g.get_level(f, l, w)
+                orp, oc, ov, _ = oa.get(l, w)
+                assert np.array_equal(gr, orp) and np.array_equal(gc, oc), (f, l, w)
+                assert np.array_equal(gv.view(np.int64), ov.view(np.int64)), (f, l, w)
+
+
 @pytest.mark.parametrize("case", ["grid8x8_cm16", "cfg0_cm64", "ragged7x5x9_6f_cm40", "cfg1"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_apply_parity(torch_dev, case, precision):
@@ -259,6 +285,28 @@ def test_gradient_values_and_autograd(torch_dev):
         cf = (xg[nf * c] - xg[nf * c + 1]) * (-(lam[nf * c] - lam[nf * c + 1])
                                               + 0.5 * sum(lam[nf * c + 3 + q] for q in range(3)))
         assert gj[c] == pytest.approx(cf, rel=1e-12, abs=1e-14 * np.abs(gj).max())
+
+
+def test_autograd_solve_follows_new_values(torch_dev):
+    """hbgs_solve given values other than the solver's loads them first: the
+    forward solve and the gradients belong to the new matrix."""
+    torch, dev = torch_dev
+    import paper_2602_13079_amd as H
+    s = synth.make_system(6, 5, 8, 1, seed=4)
+    s2 = synth.make_system(6, 5, 8, 1, seed=4, j0=s.j0 * 1.5)
+    g = _solver(torch, dev, s, coarse_max=20, rtol=1e-11)
+    val2 = torch.from_numpy(s2.val).to(dev).requires_grad_(True)
+    b = torch.from_numpy(s2.b).to(dev)
+    x = H.hbgs_solve(val2, b, g)
+    A2 = sp.csr_matrix((s2.val, s2.col, s2.rowptr), shape=(s2.n, s2.n))
+    assert np.linalg.norm(s2.b - A2 @ x.detach().cpu().numpy()) <= 1e-10 * np.linalg.norm(s2.b)
+    x.sum().backward()
+    lam_d = np.linalg.solve(A2.T.toarray(), np.ones(s2.n))
+    row = np.repeat(np.arange(s2.n), np.diff(s2.rowptr))
+    xd = np.linalg.solve(A2.toarray(), s2.b)
+    gv_ref = -lam_d[row] * xd[s2.col]
+    k = np.linalg.cond(A2.toarray())
+    assert np.linalg.norm(val2.grad.cpu().numpy() - gv_ref) <= 2 * k * 1e-11 * np.linalg.norm(gv_ref)
 
 
 def test_edge_cases(torch_dev):
