@@ -322,6 +322,7 @@ struct Field {
   double setup_seconds = 0.0;  // wall time of this field's part of the last setup
   double stage_seconds[8] = {};  // per setup stage (see hbgs_stats_t)
   int leaf = 0;                  // 0 SA-AMG V-cycle, 1 Jacobi sweep, 2 DD(0)-ILU(0)
+  double bytes[2] = {};          // algorithmic bytes of its sweep step: [0] FP64, [1] mixed
   IluLeaf ilu;
   int n() const { return hi - lo; }
 };
@@ -776,28 +777,29 @@ static void compute_stats(hbgs_ctx* c) {
     int T = p == 0 ? 8 : 4;
     double b = 0;
     for (int f : c->leaf_order) {
-      const Field& F = c->F[f];
-      if (F.lower.nnz) b += spmv_bytes(F.lower, T, T, T, 0) + 8.0 * F.n();
+      Field& F = c->F[f];
+      double fb = 0;
+      if (F.lower.nnz) fb += spmv_bytes(F.lower, T, T, T, 0) + 8.0 * F.n();
       if (F.leaf == 1) {
-        b += 3.0 * T * F.n();
-        continue;
+        fb += 3.0 * T * F.n();
+      } else if (F.leaf == 2) {
+        fb += 2.0 * spmv_bytes(F.ilu.F, T, T, T, 1);
+      } else {
+        for (size_t l = 0; l + 1 < F.lv.size(); ++l) {
+          const Level& L = F.lv[l];
+          const DCsr& A = L.A;
+          fb += spmv_bytes(A, T, T, T, 1);          // pre (b, dinv gathered; x written)
+          fb += spmv_bytes(A, T, T, T, 1);          // residual
+          fb += spmv_bytes(L.R, T, T, T, 0);        // restriction
+          fb += spmv_bytes(L.P, T, T, T, 1);        // prolongation (x read+write)
+          fb += spmv_bytes(A, T, T, 2 * T, 2);      // post start
+          fb += spmv_bytes(A, T, T, T, 3);          // post step
+        }
+        int nc = F.lv.back().A.n;
+        fb += 8.0 * nc * nc + 2.0 * nc * T;
       }
-      if (F.leaf == 2) {
-        b += 2.0 * spmv_bytes(F.ilu.F, T, T, T, 1);
-        continue;
-      }
-      for (size_t l = 0; l + 1 < F.lv.size(); ++l) {
-        const Level& L = F.lv[l];
-        const DCsr& A = L.A;
-        b += spmv_bytes(A, T, T, T, 1);          // pre (b, dinv gathered; x written)
-        b += spmv_bytes(A, T, T, T, 1);          // residual
-        b += spmv_bytes(L.R, T, T, T, 0);        // restriction
-        b += spmv_bytes(L.P, T, T, T, 1);        // prolongation (x read+write)
-        b += spmv_bytes(A, T, T, 2 * T, 2);      // post start
-        b += spmv_bytes(A, T, T, T, 3);          // post step
-      }
-      int nc = F.lv.back().A.n;
-      b += 8.0 * nc * nc + 2.0 * nc * T;
+      F.bytes[p] = fb;
+      b += fb;
     }
     st.vcycle_bytes[p] = b;
     st.spmv_bytes[p] = spmv_bytes(c->Ap, 8, T, 8, 0);
@@ -1176,6 +1178,9 @@ static void sweep(hbgs_ctx* c, const SweepPlan& plan, int tr, const double* v, T
                   hipStream_t s0) {
   const int nl = (int)plan.order.size();
   const int TS = (int)sizeof(T);
+  double plan_bytes = 0;
+  for (int f : plan.order) plan_bytes += c->F[f].bytes[TS == 4 ? 1 : 0];
+  Prof whole(c->prof, s0, solve::K_SWEEP, plan_bytes);
   HBGS_HIP(hipEventRecord(c->fork, s0));
   for (int k = 0; k < plan.nstreams; ++k) HBGS_HIP(hipStreamWaitEvent(c->fstream[k], c->fork, 0));
   std::vector<int> slot_of(c->nf, -1);

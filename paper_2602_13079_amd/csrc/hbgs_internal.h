@@ -339,6 +339,9 @@ enum Kind {
   K_RESID_C,
   K_RESTRICT_C,
   K_PROLONG_C,
+  // one whole preconditioner application (every field's V-cycle and
+  // coupling), timed from its first launch to its last on the caller's stream
+  K_SWEEP,
   K_COUNT
 };
 extern const char* kind_names[K_COUNT];

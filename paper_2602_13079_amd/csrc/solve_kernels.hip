@@ -23,7 +23,7 @@ const char* kind_names[K_COUNT] = {
     "spmv_outer", "spmv_resid", "cheb_pre",  "cheb_post_a", "cheb_post_b", "cheb_other", "resid", "restrict",
     "prolong",    "coarse",     "couple",    "dot1",        "upd_dot2",    "reduce",
     "givens",     "scale",      "xupdate",   "permute",     "cheb_pre_c", "cheb_post_a_c", "cheb_post_b_c",
-    "cheb_other_c", "resid_c",  "restrict_c", "prolong_c"};
+    "cheb_other_c", "resid_c",  "restrict_c", "prolong_c", "sweep"};
 
 // ---------------------------------------------------------- CSR row engine
 template <class T>
@@ -202,26 +202,41 @@ static void launch_csr_cols(const DCsr& a, Col col, const TV* v, LoadX lx, Epi e
                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   constexpr int cap = ROWS_LDS_BYTES / (int)sizeof(TACC);
   const int vec = g_vec_entries && reinterpret_cast<uintptr_t>(v) % 16 == 0 && col.aligned();
+  // Rows per block: the largest RB whose rows fit the LDS staging
+  // (maxlen * RB <= cap) and that still gives MIN_BLOCKS blocks, so a
+  // coarse level (10^3 - 10^5 rows) spreads over every CU instead of a few
+  // hundred blocks; where no RB gives that many, the smallest that fits.
+  // With grouped loads 256-row blocks beat 512-row ones (finest FP32
+  // levels: 13.7 vs 14.3 us at 1M rows); with single loads the larger wins.
+  constexpr int64_t MIN_BLOCKS = 1024;  // 4 per CU
+  static const int kRB[] = {512, 256, 128, 64, 32, 16, 8, 4};
+  int rb = 0;
+  for (int q = vec ? 1 : 0; q < 8; ++q) {
+    const int r = kRB[q];
+    if (a.maxlen <= 0 || a.maxlen > cap / r) continue;
+    rb = r;
+    if (((int64_t)a.n + r - 1) / r >= MIN_BLOCKS) break;
+  }
 #define HBGS_ROWS(RB)                                                                                      \
-  if (a.maxlen > 0 && a.maxlen <= cap / RB) {                                                              \
+  case RB:                                                                                                 \
     if (e0)                                                                                                \
       hipExtLaunchKernelGGL(k_csr_rows<RB, TV, TACC, Col, LoadX, Epi>, dim3((a.n + RB - 1) / RB), dim3(SBLK), \
                             0, s, e0, e1, 0, a.n, a.rp, col, v, lx, epi, vec);                             \
     else                                                                                                   \
       k_csr_rows<RB, TV, TACC, Col, LoadX, Epi><<<(a.n + RB - 1) / RB, SBLK, 0, s>>>(a.n, a.rp, col, v, lx, epi, vec); \
     HBGS_HIP(hipGetLastError());                                                                           \
-    return;                                                                                                \
-  }
-  // with grouped loads 256-row blocks beat 512-row ones (finest FP32 levels:
-  // 13.7 vs 14.3 us at 1M rows); with single loads the larger block wins
-  if (vec) {
+    return;
+  switch (rb) {
+    HBGS_ROWS(512)
     HBGS_ROWS(256)
+    HBGS_ROWS(128)
+    HBGS_ROWS(64)
+    HBGS_ROWS(32)
+    HBGS_ROWS(16)
+    HBGS_ROWS(8)
+    HBGS_ROWS(4)
+    default: break;
   }
-  HBGS_ROWS(512)
-  HBGS_ROWS(256)
-  HBGS_ROWS(128)
-  HBGS_ROWS(64)
-  HBGS_ROWS(32)
 #undef HBGS_ROWS
   float avg = a.avg_row();
   int lpr = avg <= 1.5f ? 1 : avg <= 3.f ? 2 : avg <= 6.f ? 4 : avg <= 16.f ? 8 : avg <= 64.f ? 16 : avg <= 128.f ? 32 : 64;
