@@ -59,6 +59,7 @@ def _load():
             "or_amg_setup": (vp, [i32, vp, vp, vp, f64, P, u64]),
             "or_amg_destroy": (None, [vp]),
             "or_amg_levels": (i32, [vp]),
+            "or_amg_smoothed_coarsest": (i32, [vp]),
             "or_amg_get": (i64, [vp, i32, i32, vp, vp, vp, vp, vp]),
             "or_amg_agg": (None, [vp, i32, vp]),
             "or_amg_scalars": (None, [vp, i32, vp]),
@@ -227,6 +228,12 @@ class Amg:
     @property
     def levels(self):
         return self._lib.or_amg_levels(self.h)
+
+    @property
+    def smoothed_coarsest(self):
+        """True when coarsening stopped above the dense-solve limit and the
+        coarsest level is smoothed instead of solved."""
+        return bool(self._lib.or_amg_smoothed_coarsest(self.h))
 
     def get(self, l, which="A"):
         w = {"A": 0, "P": 1, "R": 2, "AT": 3}[which]

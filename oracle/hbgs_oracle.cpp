@@ -316,6 +316,8 @@ double chunked_dot(const std::vector<double>& x, const std::vector<double>& y) {
 // Rayleigh quotient; the paper does not state its estimate): hashed start
 // vector in [-1,1], `iters` steps each rescaled by the exact power of two
 // that brings max|w| into [0.5,1), then lambda = (w . D^-1 B w) / (w . w).
+// A row with d_i = 0 contributes 0 (with the absolute-row-sum weight of the
+// filtered matrix, d_i = 0 only where that row of B is zero).
 double power_estimate(const CsrD& b, const std::vector<double>& d, int iters, uint64_t salt) {
   const int n = b.n;
   std::vector<double> w(n), y(n);
@@ -326,7 +328,7 @@ double power_estimate(const CsrD& b, const std::vector<double>& d, int iters, ui
     for (int i = 0; i < n; ++i) {
       double s = 0.0;
       for (int k = b.rp[i]; k < b.rp[i + 1]; ++k) s += b.v[k] * w[b.ci[k]];
-      y[i] = s / d[i];
+      y[i] = d[i] != 0.0 ? s / d[i] : 0.0;
     }
   };
   for (int it = 0; it < iters; ++it) {
@@ -346,7 +348,10 @@ double power_estimate(const CsrD& b, const std::vector<double>& d, int iters, ui
 // Smoothed prolongator P = P_tent - omega D_abs^-1 A_F P_tent with a unit
 // tentative prolongator (reading: the piecewise-constant aggregate
 // indicator, so the coarse near-nullspace is the constant vector).  The
-// pattern is structural: every aggregate met in the row is kept.
+// pattern is structural: every aggregate met in the row is kept.  A row
+// whose absolute row sum is 0 (every off-diagonal entry dropped and the
+// lumped diagonal 0, i.e. a zero row of A_F) gets no smoothing term: its
+// row of D_abs^-1 A_F is read as 0.
 CsrD smooth_prolongator(const CsrD& af, const std::vector<double>& dabs, const std::vector<int>& agg,
                         int nagg, double omega) {
   CsrD p;
@@ -360,7 +365,7 @@ CsrD smooth_prolongator(const CsrD& af, const std::vector<double>& dabs, const s
         if (agg[af.ci[k]] >= 0) cols.push_back(agg[af.ci[k]]);
       std::sort(cols.begin(), cols.end());
       cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
-      double q = omega / dabs[i];
+      double q = dabs[i] != 0.0 ? omega / dabs[i] : 0.0;
       for (int c : cols) {
         double s = 0.0;
         for (int k = af.rp[i]; k < af.rp[i + 1]; ++k)
@@ -481,9 +486,18 @@ struct Level {
   double lam_cheb = 0, lam_p = 0, omega = 0;
 };
 
+// Coarsest levels up to this many rows are solved by a dense LU.  A
+// coarsening that stops above it (it stalls, or hits the level cap) ends in
+// a smoothed coarsest level instead: one application of that level's
+// Chebyshev polynomial from zero (the paper's coarse solver is a sparse
+// direct one, which has no size limit; this reading keeps large strength
+// thresholds usable).
+constexpr int kDenseCoarseMax = 8000;
+
 struct Amg {
-  std::vector<Level> lv;  // lv.back() is the coarsest (direct solve)
+  std::vector<Level> lv;  // lv.back() is the coarsest (direct solve, or smoothed)
   DenseLU lu;
+  bool smoothed_coarsest = false;
   double theta = 0;
 };
 
@@ -527,17 +541,14 @@ int setup_amg(const CsrD& a0, double theta, const or_options& o, uint64_t salt_b
       }
     }
     Level& M = h.lv[l];
-    if (last) {
-      if (M.A.n > 8000) {
-        err = {-5, "coarsest level too large for a dense factorisation"};
-        return -5;
-      }
+    if (last && M.A.n <= kDenseCoarseMax) {
       if (!lu_factor(M.A, h.lu)) {
         err = {-4, "singular coarsest-level matrix"};
         return -4;
       }
       break;
     }
+    h.smoothed_coarsest = last;
     // Chebyshev data for level l: D = diag(A_l)
     M.dinv.assign(M.A.n, 0.0);
     std::vector<double> d(M.A.n, 0.0);
@@ -552,6 +563,7 @@ int setup_amg(const CsrD& a0, double theta, const or_options& o, uint64_t salt_b
       M.dinv[i] = 1.0 / d[i];
     }
     M.lam_cheb = power_estimate(M.A, d, o.eig_iters, splitmix64(salt_base + 0x9000 + l));
+    if (last) break;  // smoothed coarsest level
   }
   for (auto& L : h.lv) {
     L.AT = transpose(L.A);
@@ -641,6 +653,10 @@ template <class T>
 void vcycle(const Amg& h, const or_options& o, int l, int transpose, const T* b, T* x) {
   const Level& L = h.lv[l];
   const int n = L.A.n;
+  if (l + 1 == (int)h.lv.size() && h.smoothed_coarsest) {
+    chebyshev<T>(L, o, transpose, b, x, true);
+    return;
+  }
   if (l + 1 == (int)h.lv.size()) {
     std::vector<double> bd(b, b + n), xd(n);
     lu_solve(h.lu, bd.data(), xd.data(), transpose);
@@ -1146,6 +1162,7 @@ or_amg* or_amg_setup(int n, const int* rp, const int* ci, const double* v, doubl
 }
 void or_amg_destroy(or_amg* h) { delete h; }
 int or_amg_levels(const or_amg* h) { return (int)h->lv.size(); }
+int or_amg_smoothed_coarsest(const or_amg* h) { return h->smoothed_coarsest ? 1 : 0; }
 // which: 0 A, 1 P, 2 R, 3 A^T.  Returns nnz; fills when pointers non-null.
 int64_t or_amg_get(const or_amg* h, int l, int which, int* nrows, int* ncols, int* rp, int* ci, double* v) {
   const Level& L = h->lv[l];

@@ -819,3 +819,97 @@ def test_adjoint_and_gradient_dense():
         fd = (loss(jp) - loss(jm)) / (2 * hstep)
         assert fd == pytest.approx(gjd[c], rel=1e-5, abs=1e-10)
         assert gj[c] == pytest.approx(gjd[c], rel=1e-6, abs=1e-12)
+
+
+# --------------------------------- large strength thresholds (zero weights, stalls)
+def _chain_with_weak_nodes(n_seg=6, seg=10, w_weak=0.01):
+    """1D Neumann chain: segments of `seg` nodes joined by unit links, each
+    segment followed by one node tied to its neighbours by weak links only.
+    At theta = 0.45 the weak nodes lose every connection; their rows of A
+    sum to zero, so the lumped diagonal and D_abs are 0 there."""
+    edges, n = [], 0
+    weak_nodes = []
+    for k in range(n_seg):
+        for q in range(seg - 1):
+            edges.append((n + q, n + q + 1, 1.0))
+        n += seg
+        if k + 1 < n_seg:
+            edges.append((n - 1, n, w_weak))
+            edges.append((n, n + 1, w_weak))
+            weak_nodes.append(n)
+            n += 1
+    L = np.zeros((n, n))
+    for i, j, w in edges:
+        L[i, j] -= w
+        L[j, i] -= w
+        L[i, i] += w
+        L[j, j] += w
+    L[0, 0] += 1.0  # one Dirichlet face keeps the chain nonsingular
+    A = sp.csr_matrix(L)
+    A.sort_indices()
+    return A, np.array(weak_nodes)
+
+
+def test_zero_absolute_row_sum_rows_keep_the_tentative_row():
+    """A row of the filtered matrix that is entirely zero (D_abs = 0) has no
+    smoothing term: its prolongator row is the tentative one (a single 1 at
+    its own singleton aggregate), and the eigenvalue estimate stays finite."""
+    A, weak = _chain_with_weak_nodes()
+    rp, ci, v = csr_args(A)
+    st = oracle.strength(rp, ci, v, 0.45)
+    frp, fci, fv, dabs = oracle.filtered(rp, ci, v, st)
+    assert np.all(dabs[weak] == 0.0)
+    assert np.all(dabs[np.setdiff1d(np.arange(A.shape[0]), weak)] > 0)
+    lam = oracle.power_estimate(frp, fci, fv, dabs, 10, 5)
+    assert np.isfinite(lam) and lam > 0
+    h = oracle.Amg(rp, ci, v, theta=0.45, salt=3, opts=oracle.options(coarse_max=8, max_levels=2))
+    assert h.levels == 2 and not h.smoothed_coarsest
+    prp, pci, pv, nc = h.get(0, "P")
+    agg = h.agg(0)
+    for i in weak:
+        assert list(pci[prp[i]:prp[i + 1]]) == [agg[i]] and list(pv[prp[i]:prp[i + 1]]) == [1.0]
+        assert np.sum(agg == agg[i]) == 1  # a singleton aggregate
+
+
+def test_coarsest_beyond_dense_limit_is_smoothed():
+    """1D Poisson, 9000 rows, theta = 0.64: every connection is weak, the
+    aggregation makes only singletons and the coarsening stalls at the finest
+    level, above the 8000-row dense limit.  The hierarchy is then one
+    smoothed level and the cycle is exactly one Chebyshev application from
+    zero (pinned separately by its closed form); the transposed cycle is its
+    transpose."""
+    A = poisson1d(9000)
+    rp, ci, v = csr_args(A)
+    h = oracle.Amg(rp, ci, v, theta=0.64, salt=7, opts=oracle.options())
+    assert h.levels == 1 and h.smoothed_coarsest
+    rng = np.random.default_rng(2)
+    b, u = rng.standard_normal(9000), rng.standard_normal(9000)
+    x = h.vcycle(b)
+    assert np.array_equal(x, h.chebyshev(0, b))
+    xt = h.vcycle(u, transpose=True)
+    assert abs(u @ x - xt @ b) <= 1e-13 * np.linalg.norm(u) * np.linalg.norm(x)
+
+
+def test_level_cap_above_dense_limit_two_grid_with_smoothed_coarse():
+    """1D Poisson, 30000 rows, two levels at most: the second level (~10000
+    rows) exceeds the dense limit and is smoothed.  The cycle equals the
+    two-grid cycle written out: pre-smoothing from zero, restriction of the
+    residual, the coarse level's Chebyshev from zero, prolongation, post-
+    smoothing; it is symmetric (A is), checked by u^T B v = v^T B u."""
+    A = poisson1d(30000)
+    rp, ci, v = csr_args(A)
+    h = oracle.Amg(rp, ci, v, theta=0.0, salt=9, opts=oracle.options(max_levels=2))
+    assert h.levels == 2 and h.smoothed_coarsest
+    nc = h.get(1, "A")[0].shape[0] - 1
+    assert nc > 8000
+    prp, pci, pv, _ = h.get(0, "P")
+    P = sp.csr_matrix((pv, pci, prp), shape=(30000, nc))
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(30000)
+    x = h.chebyshev(0, b)
+    r = b - A @ x
+    xc = h.chebyshev(1, P.T @ r)
+    x = h.chebyshev(0, b, x0=x + P @ xc)
+    assert np.allclose(h.vcycle(b), x, rtol=1e-13, atol=1e-13 * np.abs(x).max())
+    u = rng.standard_normal(30000)
+    assert abs(u @ h.vcycle(b) - b @ h.vcycle(u)) <= 1e-12 * np.linalg.norm(u) * np.linalg.norm(b)
