@@ -47,7 +47,8 @@ typedef enum {
   HBGS_ENOMEM = -2,       /* device allocation failed */
   HBGS_EHIP = -3,         /* HIP runtime error */
   HBGS_ESINGULAR = -4,    /* zero pivot in the coarsest-level factorisation */
-  HBGS_ESETUP = -5        /* hierarchy could not be built (e.g. coarsening stalled) */
+  HBGS_ESETUP = -5        /* hierarchy could not be built (e.g. a non-positive eigenvalue
+                             estimate, an overflowing product table) */
 } hbgs_status;
 
 #define HBGS_MAX_FIELDS 16
@@ -64,7 +65,11 @@ typedef struct {
   double cheb_boost;     /* lambda_max = boost * power estimate (default 1.1) */
   int32_t eig_iters;     /* power iterations per eigenvalue estimate (default 10) */
   double sa_damping;     /* omega = sa_damping / lambda(D_abs^-1 A_F) (default 4/3) */
-  int32_t coarse_max;    /* coarsen until a level has at most this many rows (2000) */
+  int32_t coarse_max;    /* coarsen until a level has at most this many rows (2000); the
+                            coarsest level is solved with a dense inverse when it has at
+                            most 8000 rows, and smoothed (one Chebyshev application from
+                            zero) when coarsening stops above that (it stalls beyond 0.95
+                            of the rows, or reaches max_levels) */
   int32_t max_levels;    /* levels per field, including the finest (default 10) */
   uint64_t seed;         /* salt of the aggregation priorities and start vectors */
   double theta[HBGS_MAX_FIELDS]; /* strength threshold per field (default 0.04 for

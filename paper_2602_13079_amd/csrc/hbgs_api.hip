@@ -611,6 +611,15 @@ struct StageClock {
   ~StageClock() { to(-1); }
 };
 
+// Coarsest levels up to this many rows are solved with a dense inverse; a
+// coarsening that stops above it (stalled, or at the level cap) ends in a
+// smoothed coarsest level: one application of its Chebyshev polynomial from
+// zero.  (The paper's coarse solver is sparse direct and has no such limit.)
+constexpr int kDenseCoarseMax = 8000;
+
+// a level whose cycle smooths (every level but a dense-solved coarsest one)
+static bool smoothed_level(const Field& F, size_t l) { return l + 1 < F.lv.size() || !F.inv; }
+
 // SA-AMG hierarchy of one field's diagonal block (level 0 already set)
 static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
   const hbgs_options& o = c->o;
@@ -716,9 +725,8 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
       }
     }
     Level& L = F.lv[l];
-    if (last) {
+    if (last && n <= kDenseCoarseMax) {
       clk.to(5);
-      if (n > 8000) HBGS_FAIL(HBGS_ESETUP, "coarsest level too large for the dense factorisation");
       F.inv = pool.make<double>((size_t)n * n);
       if (setup::dense_inverse(L.A, F.inv, s) != 0) HBGS_FAIL(HBGS_ESINGULAR, "singular coarsest-level matrix");
       break;
@@ -731,6 +739,7 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
     hbgs_options of = o;
     if (o.field_cheb_degree[F.id] > 0) of.cheb_degree = o.field_cheb_degree[F.id];
     L.cc = cheb_coef(of, L.lam_cheb);
+    if (last) break;  // beyond the dense limit: a smoothed coarsest level (F.inv stays null)
   }
   // solve-phase data: transposes, FP32 copies, work vectors
   clk.to(7);
@@ -795,8 +804,12 @@ static void compute_stats(hbgs_ctx* c) {
           fb += spmv_bytes(A, T, T, 2 * T, 2);      // post start
           fb += spmv_bytes(A, T, T, T, 3);          // post step
         }
-        int nc = F.lv.back().A.n;
-        fb += 8.0 * nc * nc + 2.0 * nc * T;
+        const Level& C = F.lv.back();
+        const int nc = C.A.n;
+        if (F.inv)
+          fb += 8.0 * nc * nc + 2.0 * nc * T;
+        else  // smoothed coarsest: the pre-smoothing polynomial only
+          fb += (C.cc.degree - 1) * spmv_bytes(C.A, T, T, T, 3) + 4.0 * T * nc;
       }
       F.bytes[p] = fb;
       b += fb;
@@ -879,9 +892,11 @@ static void build_field_T(hbgs_ctx* c, Field& F, hipStream_t s) {
       setup::transpose_symmetric(L.A, L.AT.v, s);
       add_f32(pool, L.AT, s);
     }
-    const int nc = F.lv.back().A.n;
-    F.invT = pool.make<double>((size_t)nc * nc);
-    setup::dense_transpose(nc, F.inv, F.invT, s);
+    if (F.inv) {
+      const int nc = F.lv.back().A.n;
+      F.invT = pool.make<double>((size_t)nc * nc);
+      setup::dense_transpose(nc, F.inv, F.invT, s);
+    }
   }
   HBGS_HIP(hipStreamSynchronize(s));
 }
@@ -894,6 +909,7 @@ static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
   clk.to(0);
   F.lv.clear();
   F.lv.emplace_back();
+  F.inv = F.invT = nullptr;  // set again if the new hierarchy ends in a dense-solved level
   F.lv[0].A = extract(c->hier, c->Ap, F.lo, F.hi, F.lo, F.hi, F.lo, F.n(), s);
   // couplings read by this field's sweep step: every earlier (later, for the
   // adjoint) field; in the nested form only those of its own group, with
@@ -1111,7 +1127,8 @@ static void vcycle(hbgs_ctx* c, Field& F, int l, int tr, const T* b, T* x, hipSt
   const int TS = (int)sizeof(T);
   Level& L = F.lv[l];
   const int n = L.A.n;
-  if (l + 1 == (int)F.lv.size()) {
+  const bool coarsest = l + 1 == (int)F.lv.size();
+  if (coarsest && F.inv) {
     Prof p(c->prof, s, solve::K_COARSE, 8.0 * n * n + 2.0 * n * TS);
     VcOps<T>::coarse(n, tr ? F.invT : F.inv, 0, b, x, s);
     return;
@@ -1136,13 +1153,14 @@ static void vcycle(hbgs_ctx* c, Field& F, int l, int tr, const T* b, T* x, hipSt
       std::swap(d, dn);
     }
   }
+  if (coarsest) return;  // a smoothed coarsest level: the polynomial from zero only
   {
     Prof p(c->prof, s, lk(solve::K_RESID, l), spmv_bytes(A, TS, TS, TS, 1));
     VcOps<T>::resid(A, b, x, r, s);
   }
   Level& C = F.lv[l + 1];
   {
-    const bool d0c = l + 2 < (int)F.lv.size() && C.cc.degree == 2;
+    const bool d0c = smoothed_level(F, l + 1) && C.cc.degree == 2;
     Prof p(c->prof, s, lk(solve::K_RESTRICT, l), spmv_bytes(L.R, TS, TS, TS, d0c ? 2 : 0));
     VcOps<T>::restrict_(L.R, r, B::b(C), d0c ? B::dinv(C) : nullptr, C.cc.c0, d0c ? B::d(C) : nullptr, s);
   }
@@ -1197,7 +1215,7 @@ static void sweep(hbgs_ctx* c, const SweepPlan& plan, int tr, const double* v, T
     const int off = F.lo - base;
     Level& L0 = F.lv[0];
     // the finest level's first Chebyshev direction is formed with its rhs
-    const bool d0 = F.lv.size() > 1 && L0.cc.degree == 2;
+    const bool d0 = F.leaf == 0 && smoothed_level(F, 0) && L0.cc.degree == 2;
     const T* dinv0 = d0 ? Buf<T>::dinv(L0) : nullptr;
     T* d00 = d0 ? Buf<T>::d(L0) : nullptr;
     if (F.leaf == 1) {  // z = D^-1 t straight from the coupling / cast epilogue

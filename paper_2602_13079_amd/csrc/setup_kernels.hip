@@ -845,7 +845,7 @@ __global__ __launch_bounds__(PW_RB) void k_pw_apply(int n, const int* __restrict
       __syncthreads();
     }
     if (own) {
-      const double yi = s / d[i];
+      const double yi = d[i] != 0.0 ? s / d[i] : 0.0;  // a zero weight only where the row is zero
       y[i] = yi;
       const unsigned long long bits = (unsigned long long)__double_as_longlong(fabs(yi));
       m = bits > m ? bits : m;
@@ -986,7 +986,7 @@ __global__ void k_psmooth_fill(int n, const int* rp, const int* ci, const double
   ROW_GROUPS(L, i, gl, n) {
     const int ai = agg[i];
     if (ai < 0) continue;
-    const double q = omega / dabs[i];
+    const double q = dabs[i] != 0.0 ? omega / dabs[i] : 0.0;  // a zero row of A_F: no smoothing term
     const int s = rp[i], e = rp[i + 1];
     int o = rpp[i];
     int cur = INT32_MAX;
