@@ -38,6 +38,9 @@ def main():
     ap.add_argument("--config", type=int, default=2, help="layered-battery configuration (default: 4.2M DOF)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the preconditioner variants and sweeps")
+    ap.add_argument("--protocol-reps", type=int, default=None,
+                    help="repetitions of each solve in the timing protocol after the timed steps (the first is "
+                         "discarded; default 100, 5 on the 50.3M-DOF system)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -129,20 +132,25 @@ def main():
     # other classes are not timed
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rs = [step(prof_kinds=[dominant]) for _ in range(args.steps)]
+    rs = [step(prof_kinds=[dominant, "sweep"]) for _ in range(args.steps)]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     dk = dict(ms=0.0, launches=0, bytes=0.0)
+    sw = dict(ms=0.0, launches=0, bytes=0.0)
     for r in rs:
-        kr = r.pop("kernel_times")[dominant]
+        kts = r.pop("kernel_times")
         for key in dk:
-            dk[key] += kr[key]
+            dk[key] += kts[dominant][key]
+            sw[key] += kts["sweep"][key]
     for i, r in enumerate(rs):
         log(f"step {i}: " + ", ".join(f"{k}={v:.4g}" if isinstance(v, float) else f"{k}={v}" for k, v in r.items()))
     log(f"timed steps: {dominant}: {dk['launches']} launches, {dk['ms']:.3f} ms")
 
     def mean(k):
         return float(np.mean([r[k] for r in rs]))
+
+    def std(k):
+        return float(np.std([r[k] for r in rs], ddof=1)) if len(rs) > 1 else 0.0
 
     # V-cycle bandwidth: preconditioner applies in mixed precision
     solver.set_precision(1)
@@ -181,7 +189,9 @@ def main():
             "n_dof": s.n, "nnz": s.nnz, "fields": s.nf, "seed": s.seed,
         },
         "mixed_solve_s": round(mean("mixed_s"), 6),
+        "mixed_solve_s_std": round(std("mixed_s"), 6),
         "fp64_solve_s": round(mean("fp64_s"), 6),
+        "fp64_solve_s_std": round(std("fp64_s"), 6),
         "mixed_speedup_vs_fp64": round(mean("fp64_s") / mean("mixed_s"), 3),
         "iters_mixed": int(rs[-1]["it_mixed"]),
         "iters_fp64": int(rs[-1]["it_fp64"]),
@@ -191,17 +201,23 @@ def main():
         "true_res_fp64": float(rs[-1]["res_fp64"]),
         "err_mixed_vs_fp64": float(rs[-1]["err_mixed_vs_fp64"]),
         "setup_s": round(mean("setup_s"), 4),
+        "setup_s_std": round(std("setup_s"), 4),
         "setup_stage_s": dict(zip(("extract", "aggregation", "prolongator", "transpose_P", "galerkin", "coarse_lu",
                                    "smoother_data", "solve_data"), (round(x, 4) for x in st["setup_stage_seconds"]))),
         "setup_field_s": [round(x, 4) for x in st["setup_field_seconds"]],
         "adjoint_mixed_s": round(mean("adjoint_s"), 6),
+        "adjoint_mixed_s_std": round(std("adjoint_s"), 6),
         "adjoint_fp64_s": round(mean("adjoint64_s"), 6),
+        "adjoint_fp64_s_std": round(std("adjoint64_s"), 6),
         "iters_adjoint": int(rs[-1]["it_adjoint"]),
         "iters_adjoint_fp64": int(rs[-1]["it_adjoint64"]),
         "err_adjoint_mixed_vs_fp64": float(rs[-1]["err_adjoint_mixed_vs_fp64"]),
         "copy_gbs": round(copy_gbs, 1),
         "grad_s": round(mean("grad_s"), 6),
         "vcycle_gbs_kernels": round(vc_bytes / (vc_ms * 1e-3) / 1e9, 1) if vc_ms > 0 else None,
+        "vcycle_gbs_sweep": round(sw["bytes"] / (sw["ms"] * 1e-3) / 1e9, 1) if sw["ms"] > 0 else None,
+        "vcycle_frac_sweep": round(sw["bytes"] / (sw["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if sw["ms"] > 0 else None,
+        "vcycle_us_sweep": round(sw["ms"] / max(sw["launches"], 1) * 1e3, 2),
         "vcycle_gbs_apply": round(vbytes / apply_s / 1e9, 1),
         "vcycle_frac_apply": round(vbytes / apply_s / 1e9 / HBM_PEAK_GBS, 4),
         "apply_ms_mixed": round(apply_s * 1e3, 4),
@@ -220,11 +236,43 @@ def main():
             "traffic_source": traffic_src,
         },
     }
+    reps = args.protocol_reps if args.protocol_reps is not None else (5 if s.n > 10_000_000 else 100)
+    if reps > 1:
+        out["protocol"] = protocol(solver, b, xt, reps)
     if not args.no_variants:
         out["variants"] = variants(H, torch, s, rp, ci, val, fl, b)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(s)
     print(json.dumps(out), flush=True)
+
+
+def protocol(solver, b, xt, reps):
+    """The paper's timing protocol (Sec. 4: repeated runs, the first
+    discarded, mean and standard deviation) on each solve of the step, with
+    the preconditioner kept: `reps` solves each, the first dropped."""
+    import numpy as np
+    import torch
+    out = {"repetitions": reps, "discarded": 1}
+    for name, prec, tr in (("mixed", 1, False), ("fp64", 0, False), ("adjoint_mixed", 1, True),
+                           ("adjoint_fp64", 0, True)):
+        solver.set_precision(prec)
+        rhs = xt if tr else b
+        ts, its = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, st, it, _ = solver.solve(rhs, transpose=tr)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+            its.append(it)
+        ts = np.array(ts[1:])
+        out[name] = {"mean_s": round(float(ts.mean()), 6),
+                     "std_s": round(float(ts.std(ddof=1)) if len(ts) > 1 else 0.0, 6),
+                     "min_s": round(float(ts.min()), 6), "iters": its[-1],
+                     "ms_per_iter": round(float(ts.mean()) / its[-1] * 1e3, 4)}
+        log(f"protocol {name}: {out[name]}")
+    solver.set_precision(1)
+    return out
 
 
 def variants(H, torch, s, rp, ci, val, fl, b, reps=3):
@@ -321,21 +369,41 @@ def measured_traffic(kind, alg_bytes):
     return None, "no PMC summary for this kernel class on this workload"
 
 
-def cpu_baseline(s):
-    """The CPU oracle (single-threaded, plain loops) on the same system: one
-    mixed-precision solve to 1e-8; its setup is timed separately."""
+def cpu_baseline(s, reps=3):
+    """The CPU oracle (plain loops; OpenMP over rows and element-wise work
+    with sequential reductions, so every thread count gives the same bits)
+    on the same system: `reps` mixed-precision solves to 1e-8 with every
+    thread of the process's CPU share (OMP_NUM_THREADS, else os.cpu_count()),
+    then `reps` with one thread; the setup (all threads) is timed apart."""
+    import numpy as np
     import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    oracle.set_threads(threads)
     t = time.perf_counter()
     o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, precision=1)
     setup_s = time.perf_counter() - t
-    t = time.perf_counter()
-    r = o.solve(s.b)
-    solve_s = time.perf_counter() - t
-    log(f"cpu oracle: setup {setup_s:.2f}s, mixed solve {solve_s:.2f}s, {r['iters']} iterations")
-    return {"value": round(solve_s, 3), "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": f"the full {s.n}-DOF system: one mixed-precision solve to 1e-8 "
-                      f"({r['iters']} iterations); oracle setup {setup_s:.2f}s not included",
-            "setup_s": round(setup_s, 3), "iters": r["iters"], "os_cpu_count": os.cpu_count()}
+    runs = {}
+    for nth in (threads, 1):
+        oracle.set_threads(nth)
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            r = o.solve(s.b)
+            ts.append(time.perf_counter() - t)
+        runs[nth] = (np.array(ts), r["iters"])
+        log(f"cpu oracle, {nth} thread(s): mixed solve {np.mean(ts):.2f} +- {np.std(ts):.2f} s, {r['iters']} iterations")
+    oracle.set_threads(threads)
+    ts, iters = runs[threads]
+    ts1, _ = runs[1]
+    return {"value": round(float(ts.mean()), 3), "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": f"the full {s.n}-DOF system: mixed-precision solves to 1e-8 ({iters} iterations), "
+                      f"{reps} with {threads} threads and {reps} with one; the oracle setup "
+                      f"({setup_s:.2f} s with {threads} threads) not included",
+            "std": round(float(ts.std(ddof=1)), 3) if reps > 1 else 0.0,
+            "single_thread_s": round(float(ts1.mean()), 3),
+            "single_thread_std": round(float(ts1.std(ddof=1)), 3) if reps > 1 else 0.0,
+            "repetitions": reps, "setup_s": round(setup_s, 3), "iters": iters,
+            "os_cpu_count": os.cpu_count(), "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 if __name__ == "__main__":

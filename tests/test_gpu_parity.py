@@ -411,6 +411,54 @@ def test_setup_concurrent_matches_sequential(torch_dev):
     assert torch.equal(x1, x0)
 
 
+def test_enomem_through_allocator_hook(torch_dev):
+    """An allocator hook that fails (returns NULL) from its k-th call on, for
+    the first, a middle and the last call a successful setup makes: setup
+    returns HBGS_ENOMEM, every block the hook did hand out is freed again, and
+    a solver made afterwards with the default allocator solves as before."""
+    torch, dev = torch_dev
+    import paper_2602_13079_amd as H
+    s = _system("ragged7x5x9_6f_cm40")
+    b = torch.from_numpy(s.b).to(dev)
+    ref = _solver(torch, dev, s, coarse_max=40)
+    xr, _, itr, _ = ref.solve(b)
+    calls = {"n": 0, "fail_at": None}
+    live = {}
+
+    def alloc(n):
+        calls["n"] += 1
+        if calls["fail_at"] is not None and calls["n"] >= calls["fail_at"]:
+            return 0
+        p = torch.cuda.caching_allocator_alloc(n)
+        live[p] = n
+        return p
+
+    def free(p):
+        del live[p]
+        torch.cuda.caching_allocator_delete(p)
+
+    H.set_allocator(alloc, free)
+    try:
+        g = _solver(torch, dev, s, coarse_max=40)
+        total = calls["n"]
+        del g
+        torch.cuda.synchronize()
+        assert total >= 3 and not live
+        for k in sorted({1, total // 2, total}):
+            calls.update(n=0, fail_at=k)
+            print(f"allocation {k} of {total} fails", flush=True)
+            with pytest.raises(H.HBGSError) as e:
+                _solver(torch, dev, s, coarse_max=40)
+            assert e.value.code == -2, e.value
+            torch.cuda.synchronize()
+            assert not live, (k, len(live))
+    finally:
+        H.set_allocator()
+    g = _solver(torch, dev, s, coarse_max=40)
+    x, st, it, _ = g.solve(b)
+    assert st == 0 and it == itr and torch.equal(x, xr)
+
+
 def test_allocator_hook(torch_dev):
     """Solver memory served by torch's caching allocator through
     hbgs_set_allocator: same results, and every block handed back."""
