@@ -294,6 +294,8 @@ int dense_inverse(const DCsr& a, double* inv, hipStream_t s);
 void cast_f32(int64_t n, const double* in, float* out, hipStream_t s);
 // A^T of a structurally symmetric A: same pattern, values gathered (no sort)
 void transpose_symmetric(const DCsr& a, double* vt, hipStream_t s);
+// q: 2 a.n rows, row 2i = row i of a, row 2i+1 = row i of b (a.m == b.m)
+void interleave_rows(Pool& pool, const DCsr& a, const DCsr& b, DCsr& q, hipStream_t s);
 // longest row of a (a.maxlen)
 void row_stats(DCsr& a, hipStream_t s);
 // DD(0)-ILU(0) of the n x n block a with subdomains of `sub` rows (factors,
@@ -387,6 +389,13 @@ struct VcOps {
   static void restrict_(const DCsr& rmat, const T* r, T* bc, const T* dinv_c, double c0_c, T* d0_c,
                         hipStream_t s);
   static void prolong(const DCsr& p, const T* xc, T* x, hipStream_t s);
+  // prolongation fused with the post-smoother's start: with Q the rows of
+  // A P (even) and P (odd) interleaved and r the residual b - A x from
+  // before the coarse correction, one pass forms r = r - (A P) xc,
+  // d = D^-1 r / theta and x = x + P xc, i.e. the residual and first
+  // direction of the corrected x without re-reading A
+  static void post_q(const DCsr& q, const T* dinv, const ChebCoef& c, const T* xc, T* r, T* x, T* d,
+                     hipStream_t s);
   static void coarse(int n, const double* inv, int transpose, const T* b, T* x, hipStream_t s);
   static void ilu(const IluLeaf& f, int transpose, const T* t, T* z, hipStream_t s);
   // t = (T)(v / vs) - sum over coupling columns of a * z, rows of one field;

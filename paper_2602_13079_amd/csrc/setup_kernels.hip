@@ -2102,6 +2102,43 @@ __global__ void k_transpose_sym(int n, const int* __restrict__ rp, const int* __
     }
   }
 }
+// Q with rows 2i = row i of a and 2i+1 = row i of b (same column count):
+// one row-block pass over Q then forms both products with one operand
+template <int L>
+__global__ void k_interleave(int n, const int* arp, const int* aci, const double* av, const int* brp,
+                             const int* bci, const double* bv, const int* qrp, int* qci, double* qv) {
+  ROW_GROUPS(L, i, gl, n) {
+    const int qa = qrp[2 * i], qb = qrp[2 * i + 1];
+    for (int k = arp[i] + gl; k < arp[i + 1]; k += L) {
+      qci[qa + k - arp[i]] = aci[k];
+      qv[qa + k - arp[i]] = av[k];
+    }
+    for (int k = brp[i] + gl; k < brp[i + 1]; k += L) {
+      qci[qb + k - brp[i]] = bci[k];
+      qv[qb + k - brp[i]] = bv[k];
+    }
+  }
+}
+__global__ void k_interleave_rp(int n, const int* arp, const int* brp, int* qrp) {
+  GRID_STRIDE(i, n + 1) {
+    qrp[2 * i] = arp[i] + brp[i];
+    if (i < n) qrp[2 * i + 1] = arp[i + 1] + brp[i];
+  }
+}
+void interleave_rows(Pool& pool, const DCsr& a, const DCsr& b, DCsr& q, hipStream_t s) {
+  q = DCsr{};
+  q.n = 2 * a.n;
+  q.m = a.m;
+  q.nnz = a.nnz + b.nnz;
+  q.rp = pool.make<int>(q.n + 1);
+  q.ci = pool.make<int>(q.nnz);
+  q.v = pool.make<double>(q.nnz);
+  k_interleave_rp<<<grid_for(a.n + 1, BLK), BLK, 0, s>>>(a.n, a.rp, b.rp, q.rp);
+  HBGS_HIP(hipGetLastError());
+  const int L = row_lanes(a.n, a.nnz + b.nnz);
+  LAUNCH_ROW_GROUPS(k_interleave, L, a.n, s, a.n, a.rp, a.ci, a.v, b.rp, b.ci, b.v, q.rp, q.ci, q.v);
+}
+
 void transpose_symmetric(const DCsr& a, double* vt, hipStream_t s) {
   const int L = row_lanes(a.n, a.nnz);
   LAUNCH_ROW_GROUPS(k_transpose_sym, L, a.n, s, a.n, a.rp, a.ci, a.v, vt);

@@ -413,6 +413,36 @@ struct EpiCouple {
   }
 };
 
+// rows of the interleaved [A P; P] operator: even row 2i gives
+// r_i = r_i - (A P xc)_i and d_i = D^-1 r_i / theta, odd row 2i+1 gives
+// x_i = x_i + (P xc)_i
+template <class T>
+struct EpiPostQ {
+  const T* __restrict__ dinv;
+  T* __restrict__ r;
+  T* __restrict__ x;
+  T* __restrict__ d;
+  T c0;
+  struct Pre {
+    T a, b;
+  };
+  __device__ Pre load(int k) const {
+    const int i = k >> 1;
+    if (k & 1) return {x[i], T(0)};
+    return {r[i], dinv[i]};
+  }
+  __device__ void store(int k, T acc, Pre p) const {
+    const int i = k >> 1;
+    if (k & 1) {
+      x[i] = p.a + acc;
+    } else {
+      const T ri = p.a - acc;
+      r[i] = ri;
+      d[i] = p.b * ri * c0;
+    }
+  }
+};
+
 // group right-hand side of the nested form: t = v / vs - sum a z (FP64 out)
 struct EpiSubFrom {
   const double* __restrict__ v;
@@ -530,6 +560,11 @@ void VcOps<T>::restrict_(const DCsr& rmat, const T* r, T* bc, const T* dinv_c, d
 template <class T>
 void VcOps<T>::prolong(const DCsr& p, const T* xc, T* x, hipStream_t s) {
   launch_csr<T, T>(p, vals_of<T>(p), LoadArr<T>{xc}, EpiAdd<T, T>{x}, s);
+}
+template <class T>
+void VcOps<T>::post_q(const DCsr& q, const T* dinv, const ChebCoef& c, const T* xc, T* r, T* x, T* d,
+                      hipStream_t s) {
+  launch_csr<T, T>(q, vals_of<T>(q), LoadArr<T>{xc}, EpiPostQ<T>{dinv, r, x, d, (T)c.c0}, s);
 }
 template <class T>
 void VcOps<T>::couple(const DCsr& c, const double* v, const T* z, T* t, const T* dinv, double c0, T* d0,
