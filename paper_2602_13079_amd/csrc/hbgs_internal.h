@@ -189,6 +189,9 @@ struct Tmp {
 
 // ------------------------------------------------------------- device CSR
 constexpr int COL_CHUNK = 256;  // entries sharing one base of packed column indices
+// row-block sizes of the streaming SpMV, largest first: row_block(q) = 512 >> q
+constexpr int kRowBlocks = 8;
+__host__ __device__ constexpr int row_block(int q) { return 512 >> q; }
 struct DCsr {
   int n = 0, m = 0;  // rows, columns
   int64_t nnz = 0;
@@ -196,7 +199,11 @@ struct DCsr {
   int* ci = nullptr;
   double* v = nullptr;
   float* vf = nullptr;  // FP32 copy of v (solve phase, mixed precision)
-  int maxlen = 0;  // longest row (selects the solve-phase kernel shape)
+  int maxlen = 0;  // longest row
+  // entries of the fullest block of row_block(q) consecutive rows (block b:
+  // rows [b RB, min(n, (b + 1) RB))); with maxlen, selects the solve-phase
+  // kernel shape
+  int blkmax[kRowBlocks] = {};
   // packed column indices for the solve phase (null when a chunk of
   // COL_CHUNK consecutive entries spans 65536 columns or more):
   // col(k) = cb[k / COL_CHUNK] + cd[k]
@@ -296,7 +303,7 @@ void cast_f32(int64_t n, const double* in, float* out, hipStream_t s);
 void transpose_symmetric(const DCsr& a, double* vt, hipStream_t s);
 // q: 2 a.n rows, row 2i = row i of a, row 2i+1 = row i of b (a.m == b.m)
 void interleave_rows(Pool& pool, const DCsr& a, const DCsr& b, DCsr& q, hipStream_t s);
-// longest row of a (a.maxlen)
+// longest row of a and its fullest row blocks (a.maxlen, a.blkmax)
 void row_stats(DCsr& a, hipStream_t s);
 // DD(0)-ILU(0) of the n x n block a with subdomains of `sub` rows (factors,
 // transposed factors, schedules, FP32 copies); returns -4 on a zero pivot

@@ -2144,18 +2144,47 @@ void transpose_symmetric(const DCsr& a, double* vt, hipStream_t s) {
   LAUNCH_ROW_GROUPS(k_transpose_sym, L, a.n, s, a.n, a.rp, a.ci, a.v, vt);
 }
 
-__global__ void k_max_row(int n, const int* __restrict__ rp, int* __restrict__ maxlen) {
-  int m = 0;
-  GRID_STRIDE(i, n) m = max(m, rp[i + 1] - rp[i]);
-  if (m) atomicMax(maxlen, m);
+// out[0] = longest row, out[1 + q] = entries of the fullest block of
+// row_block(q) consecutive rows.  Unit u covers rows [4u, 4u + 4); the unit
+// that starts a block of each size also reads that block's end.  Wave
+// maxima, one atomic per wave and statistic.
+__global__ __launch_bounds__(BLK) void k_row_stats(int n, const int* __restrict__ rp, int* __restrict__ out) {
+  int m[1 + kRowBlocks] = {};
+  const int64_t nu = ((int64_t)n + 3) / 4;
+  GRID_STRIDE(u, nu) {
+    const int r0 = (int)(4 * u), r1 = min(n, r0 + 4);
+    const int base = rp[r0];
+    int prev = base;
+    for (int r = r0 + 1; r <= r1; ++r) {
+      const int x = rp[r];
+      m[0] = max(m[0], x - prev);
+      prev = x;
+    }
+#pragma unroll
+    for (int q = 0; q < kRowBlocks; ++q) {
+      const int rb = row_block(q);
+      if (r0 % rb == 0) m[1 + q] = max(m[1 + q], rp[min(n, r0 + rb)] - base);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q <= kRowBlocks; ++q) {
+    int x = m[q];
+    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
+    if ((threadIdx.x & 63) == 0 && x) atomicMax(out + q, x);
+  }
 }
 void row_stats(DCsr& a, hipStream_t s) {
-  Tmp<int> ml(1);
-  HBGS_HIP(hipMemsetAsync(ml.p, 0, sizeof(int), s));
-  k_max_row<<<grid_for(a.n, BLK, 4096), BLK, 0, s>>>(a.n, a.rp, ml.p);
-  HBGS_HIP(hipGetLastError());
-  HBGS_HIP(hipMemcpyAsync(&a.maxlen, ml.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  Tmp<int> st(1 + kRowBlocks);
+  int h[1 + kRowBlocks];
+  HBGS_HIP(hipMemsetAsync(st.p, 0, sizeof(h), s));
+  if (a.n > 0) {
+    k_row_stats<<<grid_for((a.n + 3) / 4, BLK, 4096), BLK, 0, s>>>(a.n, a.rp, st.p);
+    HBGS_HIP(hipGetLastError());
+  }
+  HBGS_HIP(hipMemcpyAsync(h, st.p, sizeof(h), hipMemcpyDeviceToHost, s));
   HBGS_HIP(hipStreamSynchronize(s));
+  a.maxlen = h[0];
+  for (int q = 0; q < kRowBlocks; ++q) a.blkmax[q] = h[1 + q];
 }
 
 // ------------------------------------------------------- DD(0)-ILU(0) leaf

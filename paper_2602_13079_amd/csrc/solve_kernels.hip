@@ -97,8 +97,9 @@ template <class TACC, class Epi>
 __global__ void k_empty(int n, Epi epi) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) epi.store((int)i, TACC(0), epi.load((int)i));
 }
-// Row-block streaming form for short and medium rows (longest row <=
-// ROWS_LDS / RB).  Block b owns rows [RB b, RB (b+1)) and their entries: the
+// Row-block streaming form for short and medium rows (at most
+// ROWS_LDS_BYTES / sizeof(TACC) entries in any block of RB rows).  Block b
+// owns rows [RB b, RB (b+1)) and their entries: the
 // row epilogues' vector loads and the rows' bounds are issued first, so they
 // overlap the entry stream; the threads then stream the entries' values and column indices
 // with unit-stride (coalesced) loads, gather the operand and stage the
@@ -202,18 +203,17 @@ static void launch_csr_cols(const DCsr& a, Col col, const TV* v, LoadX lx, Epi e
                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   constexpr int cap = ROWS_LDS_BYTES / (int)sizeof(TACC);
   const int vec = g_vec_entries && reinterpret_cast<uintptr_t>(v) % 16 == 0 && col.aligned();
-  // Rows per block: the largest RB whose rows fit the LDS staging
-  // (maxlen * RB <= cap) and that still gives MIN_BLOCKS blocks, so a
+  // Rows per block: the largest RB whose every block's entries fit the LDS
+  // staging (blkmax <= cap) and that still gives MIN_BLOCKS blocks, so a
   // coarse level (10^3 - 10^5 rows) spreads over every CU instead of a few
   // hundred blocks; where no RB gives that many, the smallest that fits.
   // With grouped loads 256-row blocks beat 512-row ones (finest FP32
   // levels: 13.7 vs 14.3 us at 1M rows); with single loads the larger wins.
   constexpr int64_t MIN_BLOCKS = 1024;  // 4 per CU
-  static const int kRB[] = {512, 256, 128, 64, 32, 16, 8, 4};
   int rb = 0;
-  for (int q = vec ? 1 : 0; q < 8; ++q) {
-    const int r = kRB[q];
-    if (a.maxlen <= 0 || a.maxlen > cap / r) continue;
+  for (int q = vec ? 1 : 0; q < kRowBlocks; ++q) {
+    const int r = row_block(q);
+    if (a.blkmax[q] <= 0 || a.blkmax[q] > cap) continue;
     rb = r;
     if (((int64_t)a.n + r - 1) / r >= MIN_BLOCKS) break;
   }
