@@ -2144,11 +2144,15 @@ void transpose_symmetric(const DCsr& a, double* vt, hipStream_t s) {
   LAUNCH_ROW_GROUPS(k_transpose_sym, L, a.n, s, a.n, a.rp, a.ci, a.v, vt);
 }
 
-// out[0] = longest row, out[1 + q] = entries of the fullest block of
-// row_block(q) consecutive rows.  Unit u covers rows [4u, 4u + 4); the unit
-// that starts a block of each size also reads that block's end.  Wave
-// maxima, one atomic per wave and statistic.
-__global__ __launch_bounds__(BLK) void k_row_stats(int n, const int* __restrict__ rp, int* __restrict__ out) {
+// Per-block row statistics: part[9 b] = longest row, part[9 b + 1 + q] =
+// entries of the fullest block of row_block(q) consecutive rows, over the
+// units block b visits.  Unit u covers rows [4u, 4u + 4); the unit that
+// starts a row block of each size also reads that block's end.  Wave maxima
+// through shuffles, block maxima through LDS; the host takes the maximum
+// over the blocks (no atomics: same-address atomics from every wave cost
+// more than the kernel's loads).
+__global__ __launch_bounds__(BLK) void k_row_stats(int n, const int* __restrict__ rp, int* __restrict__ part) {
+  __shared__ int red[BLK / 64][1 + kRowBlocks];
   int m[1 + kRowBlocks] = {};
   const int64_t nu = ((int64_t)n + 3) / 4;
   GRID_STRIDE(u, nu) {
@@ -2166,25 +2170,36 @@ __global__ __launch_bounds__(BLK) void k_row_stats(int n, const int* __restrict_
       if (r0 % rb == 0) m[1 + q] = max(m[1 + q], rp[min(n, r0 + rb)] - base);
     }
   }
+  const int w = (int)threadIdx.x >> 6;
 #pragma unroll
   for (int q = 0; q <= kRowBlocks; ++q) {
     int x = m[q];
     for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o));
-    if ((threadIdx.x & 63) == 0 && x) atomicMax(out + q, x);
+    if ((threadIdx.x & 63) == 0) red[w][q] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x <= kRowBlocks) {
+    int x = 0;
+    for (int k = 0; k < BLK / 64; ++k) x = max(x, red[k][threadIdx.x]);
+    part[(size_t)blockIdx.x * (1 + kRowBlocks) + threadIdx.x] = x;
   }
 }
 void row_stats(DCsr& a, hipStream_t s) {
-  Tmp<int> st(1 + kRowBlocks);
-  int h[1 + kRowBlocks];
-  HBGS_HIP(hipMemsetAsync(st.p, 0, sizeof(h), s));
-  if (a.n > 0) {
-    k_row_stats<<<grid_for((a.n + 3) / 4, BLK, 4096), BLK, 0, s>>>(a.n, a.rp, st.p);
-    HBGS_HIP(hipGetLastError());
-  }
-  HBGS_HIP(hipMemcpyAsync(h, st.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  a.maxlen = 0;
+  for (int q = 0; q < kRowBlocks; ++q) a.blkmax[q] = 0;
+  if (a.n <= 0) return;
+  constexpr int S = 1 + kRowBlocks;
+  const unsigned nb = grid_for(((int64_t)a.n + 3) / 4, BLK, 1024);
+  Tmp<int> part((size_t)nb * S);
+  std::vector<int> h((size_t)nb * S);
+  k_row_stats<<<nb, BLK, 0, s>>>(a.n, a.rp, part.p);
+  HBGS_HIP(hipGetLastError());
+  HBGS_HIP(hipMemcpyAsync(h.data(), part.p, sizeof(int) * h.size(), hipMemcpyDeviceToHost, s));
   HBGS_HIP(hipStreamSynchronize(s));
-  a.maxlen = h[0];
-  for (int q = 0; q < kRowBlocks; ++q) a.blkmax[q] = h[1 + q];
+  for (unsigned b = 0; b < nb; ++b) {
+    a.maxlen = std::max(a.maxlen, h[(size_t)b * S]);
+    for (int q = 0; q < kRowBlocks; ++q) a.blkmax[q] = std::max(a.blkmax[q], h[(size_t)b * S + 1 + q]);
+  }
 }
 
 // ------------------------------------------------------- DD(0)-ILU(0) leaf
