@@ -173,7 +173,9 @@ hbgs_status hbgs_set_tolerance(hbgs_ctx *ctx, double rtol, int32_t max_iters);
 /* z = M^-1 r (transpose = 0) or z = M^-T r (transpose = 1): one block
  * Gauss-Seidel sweep (forward: lower, leaves in order; transposed: upper,
  * leaves in reverse order, with A^T couplings and adjoint V-cycles).
- * r, z: device, n doubles, caller's ordering; may not alias. */
+ * r, z: device, n doubles, caller's ordering; may not alias.  The call is
+ * enqueued on `stream` and returns once z is complete (stream synchronised);
+ * in the mixed mode the FP32 result is widened to FP64 exactly. */
 hbgs_status hbgs_apply(hbgs_ctx *ctx, const double *r, double *z, int32_t transpose, void *stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph

@@ -353,7 +353,7 @@ struct Krylov {
   size_t ld = 0;
   double *V = nullptr, *Zd = nullptr;
   float* Zf = nullptr;
-  double *bp = nullptr, *xp = nullptr, *r = nullptr, *tmp = nullptr, *part = nullptr, *h1 = nullptr, *h2 = nullptr,
+  double *bp = nullptr, *xp = nullptr, *r = nullptr, *part = nullptr, *h1 = nullptr, *h2 = nullptr,
          *hn2 = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr, *scal = nullptr;
   double* host = nullptr;      // pinned
   double* host_dev = nullptr;  // its device-side address
@@ -380,7 +380,6 @@ struct Krylov {
     bp = pool.make<double>(n);
     xp = pool.make<double>(n);
     r = pool.make<double>(n);
-    tmp = pool.make<double>(n);
     part = pool.make<double>((size_t)(m + 2) * solve::dot_blocks(n));
     h1 = pool.make<double>(m + 2);
     h2 = pool.make<double>(m + 2);
@@ -1822,15 +1821,10 @@ hbgs_status hbgs_apply(hbgs_ctx* c, const double* r, double* z, int32_t transpos
   Krylov& K = c->K;
   solve::permute_in(c->n, c->perm, r, K.bp, s);
   apply_perm(c, transpose ? 1 : 0, K.bp, 0, nullptr, s);
-  const double* zp = K.Zd;
-  if (c->precision == 1) {  // widen the FP32 result: tmp = 0 + 1 * Z_0
-    K.host[4] = 1.0;
-    HBGS_HIP(hipMemcpyAsync(K.y, K.host + 4, sizeof(double), hipMemcpyHostToDevice, s));
-    HBGS_HIP(hipMemsetAsync(K.tmp, 0, sizeof(double) * c->n, s));
-    solve::xupdate<float>(c->n, 1, K.Zf, K.ld, K.y, K.tmp, s);
-    zp = K.tmp;
-  }
-  solve::permute_out(c->n, c->perm, zp, z, s);
+  if (c->precision == 1)  // the FP32 result, widened as it is permuted back
+    solve::permute_out_f32(c->n, c->perm, K.Zf, z, s);
+  else
+    solve::permute_out(c->n, c->perm, K.Zd, z, s);
   HBGS_HIP(hipStreamSynchronize(s));
   return HBGS_OK;
   HBGS_API_END
