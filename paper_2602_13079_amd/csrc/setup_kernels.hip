@@ -1126,12 +1126,52 @@ __global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_sym_grp(int n, int bm
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const uint32_t mask = (uint32_t)(T - 1);
-    for (int k = arp[i]; k < arp[i + 1]; ++k) {
-      const int kk = aci[k];
-      for (int q = brp[kk] + gl; q < brp[kk + 1]; q += LPR) {
-        bool fresh;
-        if (lds_claim(keys, mask, bci[q], &fresh) < 0) atomicOr(overflow, 1);
-        u += fresh;
+    const int a0 = arp[i], a1 = arp[i + 1], gbase = grp * LPR;
+    // A's row LPR entries at a time: the lanes load the entries' B row
+    // bounds together, then take the B rows one after another (the distinct
+    // count does not depend on the order)
+    for (int c0 = a0; c0 < a1; c0 += LPR) {
+      const int kl = c0 + gl;
+      int bl0 = 0, bl1 = 0;
+      if (kl < a1) {
+        const int kk = aci[kl];
+        bl0 = brp[kk];
+        bl1 = brp[kk + 1];
+      }
+      const int nt = min(LPR, a1 - c0);
+      if constexpr (LPR <= 16) {
+        int pk[LPR];
+#pragma unroll
+        for (int t = 0; t < LPR; ++t) {
+          const int q = __shfl(bl0, gbase + t) + gl;
+          pk[t] = t < nt && q < __shfl(bl1, gbase + t) ? bci[q] : -1;
+        }
+#pragma unroll
+        for (int t = 0; t < LPR; ++t) {
+          if (pk[t] >= 0) {
+            bool fresh;
+            if (lds_claim(keys, mask, pk[t], &fresh) < 0) atomicOr(overflow, 1);
+            u += fresh;
+          }
+        }
+        // rows of B longer than LPR
+        for (int t = 0; t < nt; ++t) {
+          const int b1 = __shfl(bl1, gbase + t);
+          for (int q = __shfl(bl0, gbase + t) + gl + LPR; q < b1; q += LPR) {
+            bool fresh;
+            if (lds_claim(keys, mask, bci[q], &fresh) < 0) atomicOr(overflow, 1);
+            u += fresh;
+          }
+        }
+      } else {
+        for (int t = 0; t < nt; ++t) {
+          const int b1 = __shfl(bl1, gbase + t);
+          for (int q = __shfl(bl0, gbase + t) + gl; q < b1; q += LPR) {
+            bool fresh;
+            if (lds_claim(keys, mask, bci[q], &fresh) < 0) atomicOr(overflow, 1);
+            u += fresh;
+          }
+        }
       }
     }
   }
@@ -1259,20 +1299,76 @@ __global__ __launch_bounds__(64 * SPG_WAVES) void k_spgemm_num_grp(int n, const 
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const uint32_t mask = (uint32_t)(T - 1);
-  for (int k = arp[i]; k < arp[i + 1]; ++k) {
-    const int kk = aci[k];
-    const double a = av[k];
-    for (int q = brp[kk] + gl; q < brp[kk + 1]; q += LPR) {
-      bool fresh;
-      const int h = lds_claim(keys, mask, bci[q], &fresh);
-      if (h >= 0)
-        vals[h] += a * bv[q];
-      else
-        atomicOr(overflow, 1);
+  const int a0 = arp[i], a1 = arp[i + 1], gbase = grp * LPR;
+  // A's row LPR entries at a time: the group's lanes load the entries and
+  // the bounds of their rows of B together, then the steps take the entries
+  // in order (ascending k), each broadcast from its lane
+  for (int c0 = a0; c0 < a1; c0 += LPR) {
+    const int kl = c0 + gl;
+    double al = 0.0;
+    int bl0 = 0, bl1 = 0;
+    if (kl < a1) {
+      const int kk = aci[kl];
+      al = av[kl];
+      bl0 = brp[kk];
+      bl1 = brp[kk + 1];
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int nt = min(LPR, a1 - c0);
+    if constexpr (LPR <= 16) {
+      // every step's first LPR entries of B, requested before the first step
+      int pk[LPR];
+      double pv[LPR];
+#pragma unroll
+      for (int t = 0; t < LPR; ++t) {
+        const int q = __shfl(bl0, gbase + t) + gl;
+        const bool ok = t < nt && q < __shfl(bl1, gbase + t);
+        pk[t] = ok ? bci[q] : -1;
+        pv[t] = ok ? bv[q] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < LPR; ++t) {
+        if (t < nt) {
+          const double a = __shfl(al, gbase + t);
+          const int b1 = __shfl(bl1, gbase + t);
+          int q = __shfl(bl0, gbase + t) + gl;
+          if (q < b1) {
+            bool fresh;
+            const int h = lds_claim(keys, mask, pk[t], &fresh);
+            if (h >= 0)
+              vals[h] += a * pv[t];
+            else
+              atomicOr(overflow, 1);
+          }
+          for (q += LPR; q < b1; q += LPR) {
+            bool fresh;
+            const int h = lds_claim(keys, mask, bci[q], &fresh);
+            if (h >= 0)
+              vals[h] += a * bv[q];
+            else
+              atomicOr(overflow, 1);
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+      }
+    } else {
+      for (int t = 0; t < nt; ++t) {
+        const double a = __shfl(al, gbase + t);
+        const int b0 = __shfl(bl0, gbase + t), b1 = __shfl(bl1, gbase + t);
+        for (int q = b0 + gl; q < b1; q += LPR) {
+          bool fresh;
+          const int h = lds_claim(keys, mask, bci[q], &fresh);
+          if (h >= 0)
+            vals[h] += a * bv[q];
+          else
+            atomicOr(overflow, 1);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+    }
   }
   // Compact the occupied slots to the front of the table, LPR slots at a
   // time (a round's slots are read before its writes, which land at or
