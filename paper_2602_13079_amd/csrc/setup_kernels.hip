@@ -802,18 +802,23 @@ __global__ void k_pw_init(int n, uint64_t salt, double* w) {
 // w is win, or (amax_in set) win scaled by 2^-e with max|win| = f * 2^e,
 // f in [0.5, 1), as the power method normalises its iterate (zero if
 // max|win| = 0); the scaling is exact, so folding it into the gather gives
-// bitwise the products of the scaled vector.  A block takes PW_RB rows: its
-// threads stage the products of PW_CH consecutive entries at a time in LDS
-// with coalesced loads, then each row's thread adds its products in order.
-constexpr int PW_RB = 256;
+// bitwise the products of the scaled vector.  A block of PW_BLK threads
+// takes RB rows: its threads stage the products of PW_CH consecutive
+// entries at a time in LDS with coalesced loads, then each row's thread
+// (the first RB threads) adds its products in order.  Coarse levels (few
+// rows of hundreds of entries) take small RB, so they spread over many
+// blocks instead of walking many chunks in a few.
+constexpr int PW_BLK = 256;
 constexpr int PW_CH = 2048;
-__global__ __launch_bounds__(PW_RB) void k_pw_apply(int n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                    const double* __restrict__ v, const double* __restrict__ d,
-                                                    const double* __restrict__ win,
-                                                    const unsigned long long* amax_in, double* __restrict__ y,
-                                                    unsigned long long* amax) {
+template <int RB>
+__global__ __launch_bounds__(PW_BLK) void k_pw_apply(int n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                     const double* __restrict__ v, const double* __restrict__ d,
+                                                     const double* __restrict__ win,
+                                                     const unsigned long long* amax_in, double* __restrict__ y,
+                                                     unsigned long long* amax) {
+  static_assert(RB <= PW_BLK, "one thread per row in the sums");
   __shared__ double prod[PW_CH];
-  __shared__ unsigned long long sh[PW_RB / 64];
+  __shared__ unsigned long long sh[PW_BLK / 64];
   bool scaled = amax_in != nullptr, zero = false;
   int e = 0;
   if (scaled) {
@@ -824,17 +829,17 @@ __global__ __launch_bounds__(PW_RB) void k_pw_apply(int n, const int* __restrict
       zero = true;
   }
   unsigned long long m = 0;
-  const int64_t nblk = ((int64_t)n + PW_RB - 1) / PW_RB;
+  const int64_t nblk = ((int64_t)n + RB - 1) / RB;
   for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
-    const int r0 = (int)(b * PW_RB), r1 = min(r0 + PW_RB, n);
+    const int r0 = (int)(b * RB), r1 = min(r0 + RB, n);
     const int i = r0 + (int)threadIdx.x;
-    const bool own = i < r1;
+    const bool own = (int)threadIdx.x < RB && i < r1;
     const int e0 = rp[r0], e1 = rp[r1];
     const int my0 = own ? rp[i] : 0, my1 = own ? rp[i + 1] : 0;
     double s = 0.0;
     for (int c0 = e0; c0 < e1; c0 += PW_CH) {
       const int c1 = min(c0 + PW_CH, e1);
-      for (int k = c0 + (int)threadIdx.x; k < c1; k += PW_RB) {
+      for (int k = c0 + (int)threadIdx.x; k < c1; k += PW_BLK) {
         double w = win[ci[k]];
         if (scaled) w = zero ? 0.0 : ldexp(w, -e);
         prod[k - c0] = v[k] * w;
@@ -859,9 +864,38 @@ __global__ __launch_bounds__(PW_RB) void k_pw_apply(int n, const int* __restrict
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int q = 1; q < PW_RB / 64; ++q) m = sh[q] > m ? sh[q] : m;
+    for (int q = 1; q < PW_BLK / 64; ++q) m = sh[q] > m ? sh[q] : m;
     atomicMax(amax, m);
   }
+}
+// rows per block: the largest of 256 ... 4 that still gives 1024 blocks
+// (4 per CU), else 4; the grid is capped at 2048 blocks (8 per CU, one
+// atomicMax each on a single address) that stride over the row blocks
+static void pw_apply(const DCsr& b, const double* d, const double* win, const unsigned long long* amax_in,
+                     double* y, unsigned long long* amax, hipStream_t s) {
+  const int n = b.n;
+  int rb = 4;
+  for (int r = 256; r >= 4; r >>= 1)
+    if (((int64_t)n + r - 1) / r >= 1024) {
+      rb = r;
+      break;
+    }
+  const unsigned g = (unsigned)std::max<int64_t>(1, std::min<int64_t>(((int64_t)n + rb - 1) / rb, 2048));
+#define HBGS_PW(R)                                                                                   \
+  case R:                                                                                            \
+    k_pw_apply<R><<<g, PW_BLK, 0, s>>>(n, b.rp, b.ci, b.v, d, win, amax_in, y, amax);                \
+    break;
+  switch (rb) {
+    HBGS_PW(256)
+    HBGS_PW(128)
+    HBGS_PW(64)
+    HBGS_PW(32)
+    HBGS_PW(16)
+    HBGS_PW(8)
+    HBGS_PW(4)
+  }
+#undef HBGS_PW
+  HBGS_HIP(hipGetLastError());
 }
 // w = y * 2^-e with max|y| = f * 2^e, f in [0.5, 1)
 __global__ void k_pw_scale(int n, const double* y, const unsigned long long* amax, double* w) {
@@ -871,12 +905,28 @@ __global__ void k_pw_scale(int n, const double* y, const unsigned long long* ama
   GRID_STRIDE(i, n) w[i] = mx > 0.0 ? ldexp(y[i], -e) : 0.0;
 }
 // fixed-association sum: consecutive runs of 256 terms summed in order ...
-__global__ void k_chunk_dot(int64_t n, const double* x, const double* y, double* part) {
-  GRID_STRIDE(c, (n + 255) / 256) {
-    double s = 0.0;
-    int64_t e = (c + 1) * 256 < n ? (c + 1) * 256 : n;
-    for (int64_t i = c * 256; i < e; ++i) s += x[i] * y[i];
-    part[c] = s;
+// A block of 256 threads takes 16 runs: it stages their 4096 products in
+// LDS with coalesced loads (every load in flight at once), then 16 threads
+// add one run each, in index order.  Terms beyond n are staged as +0.0,
+// which leaves a sum that starts at +0.0 unchanged.
+constexpr int DOT_RUNS = 16;
+__global__ __launch_bounds__(256) void k_chunk_dot(int64_t n, const double* x, const double* y, double* part) {
+  __shared__ double tile[DOT_RUNS][257];
+  const int64_t m = (n + 255) / 256;
+  const int t = (int)threadIdx.x;
+  for (int64_t c0 = (int64_t)blockIdx.x * DOT_RUNS; c0 < m; c0 += (int64_t)gridDim.x * DOT_RUNS) {
+#pragma unroll
+    for (int r = 0; r < DOT_RUNS; ++r) {
+      const int64_t i = (c0 + r) * 256 + t;
+      tile[r][t] = i < n ? x[i] * y[i] : 0.0;
+    }
+    __syncthreads();
+    if (t < DOT_RUNS && c0 + t < m) {
+      double s = 0.0;
+      for (int j = 0; j < 256; ++j) s += tile[t][j];
+      part[c0 + t] = s;
+    }
+    __syncthreads();
   }
 }
 // ... then the m run sums added in order: the block stages 1024 of them in
@@ -900,7 +950,7 @@ static double chunked_dot(int64_t n, const double* x, const double* y, double* p
                           hipStream_t s) {
   if (n == 0) return 0.0;
   const int64_t m = (n + 255) / 256;
-  k_chunk_dot<<<grid_for(m, 64), 64, 0, s>>>(n, x, y, part);
+  k_chunk_dot<<<grid_for(m, DOT_RUNS, 2048), 256, 0, s>>>(n, x, y, part);
   HBGS_HIP(hipGetLastError());
   k_chunk_total<<<1, 256, 0, s>>>(m, part, out);
   HBGS_HIP(hipGetLastError());
@@ -915,18 +965,13 @@ double power_estimate(const DCsr& b, const double* d, int iters, uint64_t salt, 
   Tmp<double> w(n), y(n), pa((n + 255) / 256 + 1), pb(1);
   Tmp<unsigned long long> amax(iters > 0 ? iters : 1);
   const unsigned g = grid_for(n, BLK);
-  // one block per CU slot (8 per CU): each block ends in one atomicMax on a
-  // single address, so the grid stays small and strides over the row blocks
-  const unsigned ga = grid_for(n, PW_RB, 2048);
   k_pw_init<<<g, BLK, 0, s>>>(n, salt, w.p);
   HBGS_HIP(hipGetLastError());
   if (iters > 0) HBGS_HIP(hipMemsetAsync(amax.p, 0, sizeof(unsigned long long) * iters, s));
   // iterate it reads the previous one scaled on the fly: w -> y -> w -> ...
   double* buf[2] = {y.p, w.p};
   for (int it = 0; it < iters; ++it) {
-    k_pw_apply<<<ga, PW_RB, 0, s>>>(n, b.rp, b.ci, b.v, d, buf[(it + 1) & 1], it ? amax.p + it - 1 : nullptr,
-                                    buf[it & 1], amax.p + it);
-    HBGS_HIP(hipGetLastError());
+    pw_apply(b, d, buf[(it + 1) & 1], it ? amax.p + it - 1 : nullptr, buf[it & 1], amax.p + it, s);
   }
   const double* wl = w.p;  // the normalised last iterate
   if (iters > 0) {
@@ -941,14 +986,12 @@ double power_estimate(const DCsr& b, const double* d, int iters, uint64_t salt, 
     k_pw_scale<<<g, BLK, 0, s>>>(n, last, amax.p + iters - 1, other);
     HBGS_HIP(hipGetLastError());
     wl = other;
-    k_pw_apply<<<ga, PW_RB, 0, s>>>(n, b.rp, b.ci, b.v, d, other, nullptr, last, nullptr);
-    HBGS_HIP(hipGetLastError());
+    pw_apply(b, d, other, nullptr, last, nullptr, s);
     double wy = chunked_dot(n, wl, last, pa.p, pb.p, s);
     double ww = chunked_dot(n, wl, wl, pa.p, pb.p, s);
     return wy / ww;
   }
-  k_pw_apply<<<ga, PW_RB, 0, s>>>(n, b.rp, b.ci, b.v, d, w.p, nullptr, y.p, nullptr);
-  HBGS_HIP(hipGetLastError());
+  pw_apply(b, d, w.p, nullptr, y.p, nullptr, s);
   double wy = chunked_dot(n, w.p, y.p, pa.p, pb.p, s);
   double ww = chunked_dot(n, w.p, w.p, pa.p, pb.p, s);
   return wy / ww;
