@@ -128,22 +128,26 @@ def main():
             log(f"  {k:14s} {v['ms']:9.3f} ms {v['launches']:7d} launches "
                 f"{v['bytes'] / max(v['ms'], 1e-9) / 1e6:8.1f} GB/s")
 
-    # timed region.  Every launch of the dominant class in the mixed solves
-    # is timed with HIP events on the stream it runs on (stamped by the
-    # dispatch for the outer SpMV, event records around it otherwise); the
-    # other classes are not timed
+    # timed region.  Every launch of the dominant class and of the outer SpMV
+    # in the mixed solves is timed with HIP events on the stream it runs on
+    # (stamped by the dispatch for the outer SpMV, event records around it
+    # otherwise), and every sweep with events before its fork and after its
+    # join; the other classes are not timed
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rs = [step(prof_kinds=[dominant, "sweep"]) for _ in range(args.steps)]
+    timed_kinds = list(dict.fromkeys([dominant, "spmv_outer", "sweep"]))
+    rs = [step(prof_kinds=timed_kinds) for _ in range(args.steps)]
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     dk = dict(ms=0.0, launches=0, bytes=0.0)
     sw = dict(ms=0.0, launches=0, bytes=0.0)
+    so = dict(ms=0.0, launches=0, bytes=0.0)
     for r in rs:
         kts = r.pop("kernel_times")
         for key in dk:
             dk[key] += kts[dominant][key]
             sw[key] += kts["sweep"][key]
+            so[key] += kts["spmv_outer"][key]
     for i, r in enumerate(rs):
         log(f"step {i}: " + ", ".join(f"{k}={v:.4g}" if isinstance(v, float) else f"{k}={v}" for k, v in r.items()))
     log(f"timed steps: {dominant}: {dk['launches']} launches, {dk['ms']:.3f} ms")
@@ -220,6 +224,9 @@ def main():
         "vcycle_gbs_sweep": round(sw["bytes"] / (sw["ms"] * 1e-3) / 1e9, 1) if sw["ms"] > 0 else None,
         "vcycle_frac_sweep": round(sw["bytes"] / (sw["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if sw["ms"] > 0 else None,
         "vcycle_us_sweep": round(sw["ms"] / max(sw["launches"], 1) * 1e3, 2),
+        "spmv_outer_gbs": round(so["bytes"] / (so["ms"] * 1e-3) / 1e9, 1) if so["ms"] > 0 else None,
+        "spmv_outer_frac": round(so["bytes"] / (so["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if so["ms"] > 0 else None,
+        "spmv_outer_us": round(so["ms"] / max(so["launches"], 1) * 1e3, 2),
         "vcycle_gbs_apply": round(vbytes / apply_s / 1e9, 1),
         "vcycle_frac_apply": round(vbytes / apply_s / 1e9 / HBM_PEAK_GBS, 4),
         "apply_ms_mixed": round(apply_s * 1e3, 4),
