@@ -272,6 +272,15 @@ hbgs_status hbgs_set_allocator(void *(*alloc)(size_t bytes, void *user), void (*
  * Returns HBGS_EINVAL for any other value. */
 hbgs_status hbgs_debug_spgemm_route(int32_t route);
 
+/* Test knob (process-wide; not to be called while a solve or apply runs):
+ * 1 (default): sparse matrix-vector products whose matrix has operand
+ * tiles (built at setup where every block of rows reads its operand in at
+ * most 48 spans of 64 consecutive entries) stage those spans in LDS instead
+ * of gathering operand entries from memory; 0: always gather.  Both forms
+ * compute the same products and row sums, so results are bitwise the same.
+ * Returns HBGS_EINVAL for any other value. */
+hbgs_status hbgs_debug_spmv_tiles(int32_t on);
+
 void hbgs_destroy(hbgs_ctx *ctx);
 const char *hbgs_last_error(void);
 

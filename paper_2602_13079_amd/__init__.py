@@ -72,6 +72,7 @@ EXPORTS = {
     "hbgs_kernel_times": ("i32", ["p", "p", "p", "p", "p", "i32"]),
     "hbgs_set_allocator": ("i32", ["p", "p", "p"]),
     "hbgs_debug_spgemm_route": ("i32", ["i32"]),
+    "hbgs_debug_spmv_tiles": ("i32", ["i32"]),
     "hbgs_destroy": (None, ["p"]),
     "hbgs_last_error": ("str", []),
 }
@@ -175,6 +176,12 @@ def debug_spgemm_route(route: int = 0):
     """Process-wide test knob: the kernel path of every sparse product row in
     the Galerkin products (0 by size, 1 wavefront, 2 block, 3 global tables)."""
     _check(load().hbgs_debug_spgemm_route(int(route)))
+
+
+def debug_spmv_tiles(on: bool = True):
+    """Process-wide test knob: SpMVs stage their operand tiles in LDS where
+    the matrix has them (default), or always gather (bitwise the same)."""
+    _check(load().hbgs_debug_spmv_tiles(1 if on else 0))
 
 
 def use_torch_allocator(enable=True):

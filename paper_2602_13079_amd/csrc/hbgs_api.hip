@@ -754,6 +754,7 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
     add_f32(pool, L.A, s);
     setup::row_stats(L.A, s);
     setup::pack_columns(pool, L.A, s);
+    setup::build_tiles(pool, L.A, solve::rows_per_block(L.A, solve::ROWS_CAP_F32, true), s);
     if (l + 1 < F.lv.size()) {
       add_f32(pool, L.P, s);
       add_f32(pool, L.R, s);
@@ -761,10 +762,12 @@ static void build_hierarchy(hbgs_ctx* c, Field& F, hipStream_t s) {
       setup::row_stats(L.R, s);
       setup::pack_columns(pool, L.P, s);
       setup::pack_columns(pool, L.R, s);
+      setup::build_tiles(pool, L.P, solve::rows_per_block(L.P, solve::ROWS_CAP_F32, true), s);
       if (L.Q.n) {
         add_f32(pool, L.Q, s);
         setup::row_stats(L.Q, s);
         setup::pack_columns(pool, L.Q, s);
+        setup::build_tiles(pool, L.Q, solve::rows_per_block(L.Q, solve::ROWS_CAP_F32, true), s);
       }
     }
     const int n = L.A.n;
@@ -893,6 +896,7 @@ static void build_field_T(hbgs_ctx* c, Field& F, hipStream_t s) {
   add_f32(pool, F.upperT, s);
   setup::row_stats(F.upperT, s);
   setup::pack_columns(pool, F.upperT, s);
+  setup::build_tiles(pool, F.upperT, solve::rows_per_block(F.upperT, solve::ROWS_CAP_F32, true), s);
   if (F.leaf == 2) setup::ilu_transpose(pool, F.ilu, s);
   if (F.leaf == 0) {
     for (size_t l = 0; l < F.lv.size(); ++l) {
@@ -944,6 +948,7 @@ static void build_field(hbgs_ctx* c, Field& F, hipStream_t s) {
   add_f32(c->hier, F.lower, s);
   setup::row_stats(F.lower, s);
   setup::pack_columns(c->hier, F.lower, s);
+  setup::build_tiles(c->hier, F.lower, solve::rows_per_block(F.lower, solve::ROWS_CAP_F32, true), s);
   F.td = c->hier.make<double>(F.n());
   F.tf = c->hier.make<float>(F.n());
   HBGS_HIP(hipStreamSynchronize(s));
@@ -1748,6 +1753,7 @@ hbgs_status hbgs_setup(hbgs_ctx** out, int32_t n, int64_t nnz, const int32_t* ro
   setup::row_stats(c->ApT, s);
   setup::pack_columns(c->pool, c->Ap, s);
   setup::pack_columns(c->pool, c->ApT, s);
+  for (DCsr* a : {&c->Ap, &c->ApT}) setup::build_tiles(c->pool, *a, solve::rows_per_block(*a, solve::ROWS_CAP_F64, true), s);
   build_values(c, s);
   c->stats.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   *out = c;
@@ -2003,6 +2009,15 @@ hbgs_status hbgs_debug_spgemm_route(int32_t route) {
     return HBGS_EINVAL;
   }
   setup::set_spgemm_route(route);
+  return HBGS_OK;
+}
+
+hbgs_status hbgs_debug_spmv_tiles(int32_t on) {
+  if (on != 0 && on != 1) {
+    set_error("spmv tiles switch must be 0 or 1");
+    return HBGS_EINVAL;
+  }
+  solve::set_tiles(on != 0);
   return HBGS_OK;
 }
 

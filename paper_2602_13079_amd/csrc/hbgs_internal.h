@@ -209,8 +209,18 @@ struct DCsr {
   // col(k) = cb[k / COL_CHUNK] + cd[k]
   uint16_t* cd = nullptr;
   int* cb = nullptr;
+  // operand tiles for the row-block SpMV that stages its operand in LDS
+  // (tile_rb = 0: not built): block b of tile_rb rows reads the operand
+  // only in the tiles of TILE_W consecutive entries listed at
+  // tiles[b * TILE_MAX + j] (ascending, then -1), at most tile_cnt of them;
+  // entry k reads slot lc[k] / TILE_W of that list, element lc[k] % TILE_W
+  int tile_rb = 0, tile_cnt = 0;
+  int* tiles = nullptr;
+  uint16_t* lc = nullptr;
   float avg_row() const { return n ? (float)nnz / (float)n : 0.f; }
 };
+constexpr int TILE_W = 64;    // operand entries per tile
+constexpr int TILE_MAX = 48;  // tiles per row block at most
 
 
 // DD(0)-ILU(0) leaf of one field: factors on the subdomain-block pattern of
@@ -305,6 +315,10 @@ void transpose_symmetric(const DCsr& a, double* vt, hipStream_t s);
 void interleave_rows(Pool& pool, const DCsr& a, const DCsr& b, DCsr& q, hipStream_t s);
 // longest row of a and its fullest row blocks (a.maxlen, a.blkmax)
 void row_stats(DCsr& a, hipStream_t s);
+// the operand tiles of a's blocks of rb rows (a.tiles, a.lc, a.tile_cnt;
+// a.tile_rb = rb), or none (a.tile_rb = 0) where a block has more than
+// TILE_MAX tiles or more entries than one block's LDS staging holds
+void build_tiles(Pool& pool, DCsr& a, int rb, hipStream_t s);
 // DD(0)-ILU(0) of the n x n block a with subdomains of `sub` rows (factors,
 // transposed factors, schedules, FP32 copies); returns -4 on a zero pivot
 int ilu_setup(Pool& pool, const DCsr& a, int sub, IluLeaf& out, hipStream_t s);
@@ -320,6 +334,12 @@ void sort_rows(const DCsr& a, hipStream_t s);
 
 // ======================================================== solve kernels
 namespace solve {
+// rows per block of the streaming SpMV for matrix a with LDS staging of
+// cap products per block (0: no row-block shape fits)
+int rows_per_block(const DCsr& a, int cap, bool vec);
+constexpr int ROWS_CAP_F32 = 4096, ROWS_CAP_F64 = 2048;
+// use the operand tiles where a matrix has them (default) or never (tests)
+void set_tiles(bool on);
 // kernel classes tracked by the optional profiler
 enum Kind {
   K_SPMV_OUTER = 0,

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -2339,6 +2340,105 @@ void row_stats(DCsr& a, hipStream_t s) {
     a.maxlen = std::max(a.maxlen, h[(size_t)b * S]);
     for (int q = 0; q < kRowBlocks; ++q) a.blkmax[q] = std::max(a.blkmax[q], h[(size_t)b * S + 1 + q]);
   }
+}
+
+// Operand tiles of one row block per workgroup: the tile ids (col /
+// TILE_W) of the block's entries go into an LDS hash set; each distinct id's
+// slot is its rank among them (ascending), and each entry's slot is found by
+// binary search in the ranked list.  A block with more than TILE_MAX tiles
+// sets *too_many and writes nothing.
+constexpr int TILE_ENTRIES = 4096;  // entries of one row block at most (the FP32 staging limit)
+constexpr int TILE_HASH = 128;   // hash slots (> 2 TILE_MAX)
+__global__ __launch_bounds__(256) void k_tiles(int n, int rb, const int* __restrict__ rp, const int* __restrict__ ci,
+                                               int* __restrict__ tiles, uint16_t* __restrict__ lc,
+                                               int* __restrict__ too_many, int* __restrict__ cnt_max) {
+  __shared__ int tab[TILE_HASH];
+  __shared__ int uniq[TILE_MAX];
+  __shared__ int cnt, full;
+  const int b = (int)blockIdx.x, t = (int)threadIdx.x;
+  const int r0 = b * rb, r1 = min(n, r0 + rb);
+  const int s0 = rp[r0], s1 = rp[r1];
+  if (t < TILE_HASH) tab[t] = -1;
+  if (t == 0) {
+    cnt = 0;
+    full = 0;
+  }
+  __syncthreads();
+  for (int k = s0 + t; k < s1; k += 256) {
+    const int id = ci[k] / TILE_W;
+    uint32_t h = ((uint32_t)id * 2654435761u) & (TILE_HASH - 1);
+    for (int probe = 0;; ++probe) {
+      if (probe == TILE_HASH) {
+        full = 1;
+        break;
+      }
+      const int prev = atomicCAS(&tab[h], -1, id);
+      if (prev == -1) {
+        atomicAdd(&cnt, 1);
+        break;
+      }
+      if (prev == id) break;
+      h = (h + 1) & (TILE_HASH - 1);
+    }
+  }
+  __syncthreads();
+  const int nt = cnt;
+  if (full || nt > TILE_MAX) {
+    if (t == 0) atomicOr(too_many, 1);
+    return;
+  }
+  if (t == 0 && nt) atomicMax(cnt_max, nt);
+  if (t < TILE_HASH) {
+    const int id = tab[t];
+    if (id >= 0) {
+      int rank = 0;
+      for (int q = 0; q < TILE_HASH; ++q) rank += tab[q] >= 0 && tab[q] < id;
+      uniq[rank] = id;
+    }
+  }
+  __syncthreads();
+  if (t < TILE_MAX) tiles[(size_t)b * TILE_MAX + t] = t < nt ? uniq[t] : -1;
+  for (int k = s0 + t; k < s1; k += 256) {
+    const int col = ci[k], id = col / TILE_W;
+    int lo = 0, hi = nt - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (uniq[mid] < id)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    lc[k] = (uint16_t)(lo * TILE_W + col % TILE_W);
+  }
+}
+void build_tiles(Pool& pool, DCsr& a, int rb, hipStream_t s) {
+  a.tile_rb = 0;
+  a.tile_cnt = 0;
+  a.tiles = nullptr;
+  a.lc = nullptr;
+  if (a.n <= 0 || a.nnz <= 0 || rb <= 0) return;
+  int q = 0;
+  while (q < kRowBlocks && row_block(q) != rb) ++q;
+  if (q == kRowBlocks || a.blkmax[q] > TILE_ENTRIES) return;
+  const int64_t nblk = ((int64_t)a.n + rb - 1) / rb;
+  int* tiles = pool.make<int>((size_t)nblk * TILE_MAX);
+  uint16_t* lc = pool.make<uint16_t>(a.nnz);
+  Tmp<int> flags(2);
+  HBGS_HIP(hipMemsetAsync(flags.p, 0, 2 * sizeof(int), s));
+  k_tiles<<<(unsigned)nblk, 256, 0, s>>>(a.n, rb, a.rp, a.ci, tiles, lc, flags.p, flags.p + 1);
+  HBGS_HIP(hipGetLastError());
+  int h[2] = {0, 0};
+  HBGS_HIP(hipMemcpyAsync(h, flags.p, sizeof(h), hipMemcpyDeviceToHost, s));
+  HBGS_HIP(hipStreamSynchronize(s));
+  if (h[0] || h[1] <= 0) {
+    pool.release(lc);
+    pool.release(tiles);
+    return;
+  }
+  a.tile_rb = rb;
+  a.tile_cnt = h[1];
+  a.tiles = tiles;
+  a.lc = lc;
 }
 
 // ------------------------------------------------------- DD(0)-ILU(0) leaf

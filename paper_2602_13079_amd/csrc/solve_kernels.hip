@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "hbgs_internal.h"
 
@@ -195,6 +196,135 @@ __global__ __launch_bounds__(SBLK) void k_csr_rows(int n, const int* __restrict_
   }
 }
 
+// Row-block form with the operand staged in LDS (matrices with operand
+// tiles): the block's tiles of TILE_W consecutive operand entries are
+// loaded with coalesced loads at the same time as its entries, whose local
+// columns (2 bytes each) then index the staged tiles, so no load waits on a
+// column index.  The block's entries (at most 4 * SBLK * NG) are held in
+// registers across the barrier that publishes the tiles.  Same products,
+// LDS positions and row sums as k_csr_rows: bitwise the same result.
+template <int RB, class TV, class TACC, class TX, class Epi>
+__global__ __launch_bounds__(SBLK) void k_csr_rows_tiled(int n, int m, const int* __restrict__ rp,
+                                                         const uint16_t* __restrict__ lc,
+                                                         const int* __restrict__ tiles, int tcnt,
+                                                         const TV* __restrict__ v, const TX* __restrict__ x,
+                                                         Epi epi, int prod_bytes) {
+  constexpr int LPR = RB >= SBLK ? 1 : SBLK / RB;
+  constexpr int RPT = RB >= SBLK ? RB / SBLK : 1;
+  constexpr int NG = (ROWS_LDS_BYTES / (int)sizeof(TACC)) / (4 * SBLK);  // groups of four per thread
+  constexpr int TPP = SBLK / TILE_W;                                      // tiles per pass
+  extern __shared__ __align__(16) unsigned char smem[];
+  TACC* prod = reinterpret_cast<TACC*>(smem);
+  TX* xs = reinterpret_cast<TX*>(smem + prod_bytes);
+  const int t = (int)threadIdx.x;
+  const int b = (int)blockIdx.x;
+  const int r0 = b * RB, r1 = min(n, r0 + RB);
+  const int lane = t & (LPR - 1);
+  const int rbase = r0 + t / LPR;
+  typename Epi::Pre pre[RPT];
+  int rkb[RPT], rke[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = rbase + q * SBLK;
+    if (r < r1 && lane == 0) pre[q] = epi.load(r);
+    rkb[q] = r < r1 ? rp[r] : 0;
+    rke[q] = r < r1 ? rp[r + 1] : 0;
+  }
+  // the tiles' ids, then their entries (thread t stages element t % TILE_W
+  // of tiles t / TILE_W + TPP j)
+  const int e = t % TILE_W, j0 = t / TILE_W;
+  int id[TILE_MAX / TPP];
+#pragma unroll
+  for (int j = 0; j < TILE_MAX / TPP; ++j) {
+    const int slot = j0 + TPP * j;
+    id[j] = slot < tcnt ? tiles[(size_t)b * TILE_MAX + slot] : -1;
+  }
+  const int s0 = rp[r0], s1 = rp[r1];
+  TX xv[TILE_MAX / TPP];
+#pragma unroll
+  for (int j = 0; j < TILE_MAX / TPP; ++j) {
+    const int c = id[j] * TILE_W + e;
+    xv[j] = id[j] >= 0 && c < m ? x[c] : TX(0);
+  }
+  // the entries: the 4-aligned middle [m0, m1) in groups of four, the at
+  // most 3 + 3 entries at the ends singly
+  const int m0 = min((s0 + 3) & ~3, s1), m1 = max(s1 & ~3, m0);
+  const bool hh = s0 + t < m0, ht = m1 + t < s1;
+  const int kh = s0 + t, kt = m1 + t;
+  const TV vh = hh ? v[kh] : TV(0), vt = ht ? v[kt] : TV(0);
+  const int lh = hh ? (int)lc[kh] : 0, lt = ht ? (int)lc[kt] : 0;
+  TV w[NG][4];
+  int c[NG][4];
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int k4 = m0 + 4 * t + 4 * SBLK * g;
+    if (k4 < m1) {
+      load4(v + k4, w[g]);
+      const ushort4 u = *reinterpret_cast<const ushort4*>(lc + k4);
+      c[g][0] = u.x;
+      c[g][1] = u.y;
+      c[g][2] = u.z;
+      c[g][3] = u.w;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < TILE_MAX / TPP; ++j)
+    if (id[j] >= 0) xs[(j0 + TPP * j) * TILE_W + e] = xv[j];
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+    const int k4 = m0 + 4 * t + 4 * SBLK * g;
+    if (k4 < m1)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) prod[k4 + q - s0] = (TACC)w[g][q] * (TACC)xs[c[g][q]];
+  }
+  if (hh) prod[kh - s0] = (TACC)vh * (TACC)xs[lh];
+  if (ht) prod[kt - s0] = (TACC)vt * (TACC)xs[lt];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = rbase + q * SBLK;
+    TACC acc = 0;
+    if (r < r1) {
+      const int k0 = rkb[q] - s0, k1 = rke[q] - s0;
+      for (int k = k0 + lane; k < k1; k += LPR) acc += prod[k];
+    }
+    if (LPR > 1) acc = lanes_sum<TACC>(acc, LPR);
+    if (r < r1 && lane == 0) epi.store(r, acc, pre[q]);
+  }
+}
+
+template <class T>
+struct LoadArr;
+template <class L>
+struct load_arr_elem {
+  using type = void;
+};
+template <class T>
+struct load_arr_elem<LoadArr<T>> {
+  using type = T;
+};
+static bool g_tiles_on = true;  // the LDS-staged operand where a matrix has tiles
+void set_tiles(bool on) { g_tiles_on = on; }
+
+int rows_per_block(const DCsr& a, int cap, bool vec) {
+  // the largest RB whose every block's entries fit the LDS staging
+  // (blkmax <= cap) and that still gives MIN_BLOCKS blocks, so a coarse
+  // level (10^3 - 10^5 rows) spreads over every CU instead of a few hundred
+  // blocks; where no RB gives that many, the smallest that fits.  With
+  // grouped loads 256-row blocks beat 512-row ones (finest FP32 levels:
+  // 13.7 vs 14.3 us at 1M rows); with single loads the larger wins.
+  constexpr int64_t MIN_BLOCKS = 1024;  // 4 per CU
+  int rb = 0;
+  for (int q = vec ? 1 : 0; q < kRowBlocks; ++q) {
+    const int r = row_block(q);
+    if (a.blkmax[q] <= 0 || a.blkmax[q] > cap) continue;
+    rb = r;
+    if (((int64_t)a.n + r - 1) / r >= MIN_BLOCKS) break;
+  }
+  return rb;
+}
+
 // e0/e1 (optional): events that the dispatch itself stamps with the
 // kernel's start and end (no extra packets in the stream), for timing one
 // class of launches inside a timed run
@@ -203,19 +333,35 @@ static void launch_csr_cols(const DCsr& a, Col col, const TV* v, LoadX lx, Epi e
                             hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   constexpr int cap = ROWS_LDS_BYTES / (int)sizeof(TACC);
   const int vec = g_vec_entries && reinterpret_cast<uintptr_t>(v) % 16 == 0 && col.aligned();
-  // Rows per block: the largest RB whose every block's entries fit the LDS
-  // staging (blkmax <= cap) and that still gives MIN_BLOCKS blocks, so a
-  // coarse level (10^3 - 10^5 rows) spreads over every CU instead of a few
-  // hundred blocks; where no RB gives that many, the smallest that fits.
-  // With grouped loads 256-row blocks beat 512-row ones (finest FP32
-  // levels: 13.7 vs 14.3 us at 1M rows); with single loads the larger wins.
-  constexpr int64_t MIN_BLOCKS = 1024;  // 4 per CU
-  int rb = 0;
-  for (int q = vec ? 1 : 0; q < kRowBlocks; ++q) {
-    const int r = row_block(q);
-    if (a.blkmax[q] <= 0 || a.blkmax[q] > cap) continue;
-    rb = r;
-    if (((int64_t)a.n + r - 1) / r >= MIN_BLOCKS) break;
+  const int rb = rows_per_block(a, cap, vec != 0);
+  // the LDS-staged operand where the matrix has tiles for this block size
+  // and the staging (products and tiles) leaves room for 8 blocks per CU
+  using TX = typename load_arr_elem<LoadX>::type;
+  if constexpr (!std::is_void<TX>::value) {
+    if (g_tiles_on && vec && a.tile_rb == rb && a.lc && (rb == 256 || rb == 128 || rb == 64)) {
+      int q = 0;
+      while (row_block(q) != rb) ++q;
+      const int pb = (a.blkmax[q] * (int)sizeof(TACC) + 15) / 16 * 16;
+      const int lds = pb + a.tile_cnt * TILE_W * (int)sizeof(TX);
+      if (lds <= 20480) {
+        const unsigned grid = (unsigned)(((int64_t)a.n + rb - 1) / rb);
+#define HBGS_TILED(RB)                                                                                     \
+  if (rb == RB) {                                                                                          \
+    if (e0)                                                                                                \
+      hipExtLaunchKernelGGL(k_csr_rows_tiled<RB, TV, TACC, TX, Epi>, dim3(grid), dim3(SBLK), lds, s, e0, e1, 0, \
+                            a.n, a.m, a.rp, a.lc, a.tiles, a.tile_cnt, v, lx.x, epi, pb);                  \
+    else                                                                                                   \
+      k_csr_rows_tiled<RB, TV, TACC, TX, Epi><<<grid, SBLK, lds, s>>>(a.n, a.m, a.rp, a.lc, a.tiles,       \
+                                                                      a.tile_cnt, v, lx.x, epi, pb);       \
+    HBGS_HIP(hipGetLastError());                                                                           \
+    return;                                                                                                \
+  }
+        HBGS_TILED(256)
+        HBGS_TILED(128)
+        HBGS_TILED(64)
+#undef HBGS_TILED
+      }
+    }
   }
 #define HBGS_ROWS(RB)                                                                                      \
   case RB:                                                                                                 \

@@ -177,6 +177,38 @@ def test_full_size_solve_cfg2(torch_dev, precision):
     _check_solve(torch_dev, s, g, precision)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_operand_tiles_bitwise_cfg2(torch_dev, precision):
+    """The benchmark's configuration: its finest and first coarse levels and
+    its outer operator take the SpMV with the operand staged in LDS; the
+    gathering form must give the same bits (the apply in both directions,
+    an 8-step locked solve)."""
+    torch, dev = torch_dev
+    import paper_2602_13079_amd as H
+    s, g, o = _workload(torch_dev, 2)
+    r = torch.from_numpy(np.random.default_rng(12).standard_normal(s.n)).to(dev)
+    b = torch.from_numpy(s.b).to(dev)
+    g.set_precision(precision)
+    g.set_tolerance(0.0, 8)
+    out = {}
+    try:
+        for on in (True, False):
+            H.debug_spmv_tiles(on)
+            z = [g.apply(r, transpose=tr).cpu().numpy() for tr in (False, True)]
+            x, st, it, hist = g.solve(b)
+            out[on] = (z, x.cpu().numpy(), np.asarray(hist), it)
+    finally:
+        H.debug_spmv_tiles(True)
+        g.set_tolerance(1e-8, 2000)
+        g.set_precision(0)
+    (za, xa, ha, ia), (zb, xb, hb, ib) = out[True], out[False]
+    for tr in (0, 1):
+        assert np.array_equal(za[tr].view(np.int64), zb[tr].view(np.int64)), tr
+    assert ia == ib == 8
+    assert np.array_equal(xa.view(np.int64), xb.view(np.int64))
+    assert np.array_equal(ha.view(np.int64), hb.view(np.int64))
+
+
 # ------------------------------------------------------------ 5.3M DOF (cfg 3)
 @pytest.mark.parametrize("field", [0, 1, 2, 3, 4, 5])
 def test_full_size_hierarchy_cfg3(torch_dev, field):

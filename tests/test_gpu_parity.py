@@ -147,6 +147,37 @@ def test_apply_parity(torch_dev, case, precision):
         assert np.array_equal(z, z2)  # deterministic
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_operand_tiles_bitwise(torch_dev, precision):
+    """The 1M-DOF case's finest operators (1024 blocks of 256 rows) and its
+    outer operator (8192 blocks of 128 rows) have operand tiles, so their
+    SpMVs stage the operand in LDS; gathering it instead must give the same
+    bits: the apply in both directions and a 6-step locked solve (x and
+    the residual history)."""
+    torch, dev = torch_dev
+    import paper_2602_13079_amd as H
+    s, g, _ = _pair(torch_dev, "cfg1", precision)
+    r = torch.from_numpy(np.random.default_rng(5).standard_normal(s.n)).to(dev)
+    b = torch.from_numpy(s.b).to(dev)
+    g.set_tolerance(0.0, 6)
+    out = {}
+    try:
+        for on in (True, False):
+            H.debug_spmv_tiles(on)
+            z = [g.apply(r, transpose=tr).cpu().numpy() for tr in (False, True)]
+            x, st, it, hist = g.solve(b)
+            out[on] = (z, x.cpu().numpy(), np.asarray(hist), it)
+    finally:
+        H.debug_spmv_tiles(True)
+        g.set_tolerance(1e-8, 2000)
+    (za, xa, ha, ia), (zb, xb, hb, ib) = out[True], out[False]
+    for tr in (0, 1):
+        assert np.array_equal(za[tr].view(np.int64), zb[tr].view(np.int64)), tr
+    assert ia == ib == 6
+    assert np.array_equal(xa.view(np.int64), xb.view(np.int64))
+    assert np.array_equal(ha.view(np.int64), hb.view(np.int64))
+
+
 @pytest.mark.parametrize("case", ["grid8x8_cm16", "cfg0_cm64", "ragged7x5x9_6f_cm40", "cfg0", "cfg1"])
 def test_solve_parity_fp64(torch_dev, case):
     torch, dev = torch_dev
