@@ -335,7 +335,9 @@ static void launch_csr_cols(const DCsr& a, Col col, const TV* v, LoadX lx, Epi e
   const int vec = g_vec_entries && reinterpret_cast<uintptr_t>(v) % 16 == 0 && col.aligned();
   const int rb = rows_per_block(a, cap, vec != 0);
   // the LDS-staged operand where the matrix has tiles for this block size
-  // and the staging (products and tiles) leaves room for 8 blocks per CU
+  // and the staging (products and tiles) takes at most 32 KiB, 5 blocks per
+  // CU (at 4.2M DOF the outer SpMV's 21-27 KiB still run faster staged: 95
+  // -> 83 us mixed, 102 -> 93 us FP64)
   using TX = typename load_arr_elem<LoadX>::type;
   if constexpr (!std::is_void<TX>::value) {
     if (g_tiles_on && vec && a.tile_rb == rb && a.lc && (rb == 256 || rb == 128 || rb == 64)) {
@@ -343,7 +345,7 @@ static void launch_csr_cols(const DCsr& a, Col col, const TV* v, LoadX lx, Epi e
       while (row_block(q) != rb) ++q;
       const int pb = (a.blkmax[q] * (int)sizeof(TACC) + 15) / 16 * 16;
       const int lds = pb + a.tile_cnt * TILE_W * (int)sizeof(TX);
-      if (lds <= 20480) {
+      if (lds <= 32768) {
         const unsigned grid = (unsigned)(((int64_t)a.n + rb - 1) / rb);
 #define HBGS_TILED(RB)                                                                                     \
   if (rb == RB) {                                                                                          \
