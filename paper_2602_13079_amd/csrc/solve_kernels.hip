@@ -955,30 +955,46 @@ __global__ __launch_bounds__(BLK) void k_cgs(int n, int nv, double* __restrict__
     for (int k = 0; k < MAXV; ++k) hq[k] = k < nrd ? hp[k < nrd ? k : 0] : 0.0;
   }
   double ww = 0.0, accf = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
-    double vk[MAXV];
+  // U rows per step (i, i + stride, ...), all their loads issued before any
+  // use; the rows are accumulated in the order of a one-row loop
+  constexpr int U = MAXV <= 16 ? 2 : 1;
+  const int64_t stride = (int64_t)gridDim.x * BLK;
+  for (int64_t i0 = (int64_t)blockIdx.x * BLK + threadIdx.x; i0 < n; i0 += U * stride) {
+    double vk[U][MAXV], uu[U], wv[U];
 #pragma unroll
-    for (int k = 0; k < MAXV; ++k) vk[k] = k < nrd ? V[(size_t)(k < nrd ? k : 0) * ldv + i] : 0.0;
-    double vf = 0.0;
-    if (FIN) {
-      double u = V[(size_t)nrd * ldv + i];
+    for (int r = 0; r < U; ++r) {
+      const int64_t i = i0 + r * stride;
+      const bool in = i < n;
 #pragma unroll
-      for (int k = 0; k < MAXV; ++k) u -= hq[k] * vk[k];
-      vf = u / hn;
-      V[(size_t)nrd * ldv + i] = vf;
+      for (int k = 0; k < MAXV; ++k) vk[r][k] = in && k < nrd ? V[(size_t)(k < nrd ? k : 0) * ldv + i] : 0.0;
+      uu[r] = FIN && in ? V[(size_t)nrd * ldv + i] : 0.0;
+      wv[r] = in ? w[i] : 0.0;
     }
-    double wi = w[i];
-    if (UPD) {
 #pragma unroll
-      for (int k = 0; k < MAXV; ++k) wi -= hh[k] * vk[k];
-      w[i] = wi;
-    }
-    if (DOTS) {
+    for (int r = 0; r < U; ++r) {
+      const int64_t i = i0 + r * stride;
+      if (i >= n) break;
+      double vf = 0.0;
+      if (FIN) {
+        double u = uu[r];
 #pragma unroll
-      for (int k = 0; k < MAXV; ++k) acc[k] += vk[k] * wi;
-      if (FIN) accf += vf * wi;  // the finished column's dot: acc[nrd] only saw zeros
+        for (int k = 0; k < MAXV; ++k) u -= hq[k] * vk[r][k];
+        vf = u / hn;
+        V[(size_t)nrd * ldv + i] = vf;
+      }
+      double wi = wv[r];
+      if (UPD) {
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k) wi -= hh[k] * vk[r][k];
+        w[i] = wi;
+      }
+      if (DOTS) {
+#pragma unroll
+        for (int k = 0; k < MAXV; ++k) acc[k] += vk[r][k] * wi;
+        if (FIN) accf += vf * wi;  // the finished column's dot: acc[nrd] only saw zeros
+      }
+      ww += wi * wi;
     }
-    ww += wi * wi;
   }
   const int nb = gridDim.x;
   if (DOTS) {
