@@ -397,6 +397,85 @@ def test_edge_cases(torch_dev):
     assert st == 0 and np.allclose(x.cpu().numpy(), 1.0, rtol=1e-6)
 
 
+def _degenerate_system():
+    """Three fields: a 30-row chain, a single row, a 20-row chain (1D
+    Poisson blocks plus a mass term), the single row coupled one way to rows
+    of both chains and the chains' last rows coupled to it."""
+    n0, n2 = 30, 20
+    n = n0 + 1 + n2
+    A = sp.lil_matrix((n, n))
+    for lo, m in ((0, n0), (n0 + 1, n2)):
+        for i in range(m):
+            A[lo + i, lo + i] = 2.1
+            if i > 0:
+                A[lo + i, lo + i - 1] = -1.0
+            if i + 1 < m:
+                A[lo + i, lo + i + 1] = -1.0
+    A[n0, n0] = 3.0
+    A[n0, 4] = -0.5
+    A[n0, n0 + 7] = -0.25
+    A[n0 - 1, n0] = -0.3
+    A[n - 1, n0] = 0.2
+    A = A.tocsr()
+    A.sort_indices()
+    fl = np.array([0] * n0 + [1] + [2] * n2, dtype=np.int32)
+    b = A @ np.linspace(-1.0, 1.0, n)
+    return synth.System(n=n, nf=3, rowptr=A.indptr.astype(np.int32), col=A.indices.astype(np.int32),
+                        val=A.data.astype(np.float64), field_of_row=fl, tree=[-1, 0, 1, 2, -2], b=b)
+
+
+def test_degenerate_sizes(torch_dev):
+    """A field of one row between two chains (its one-level hierarchy is the
+    1x1 dense inverse), and a one-row system: hierarchies bitwise, applies
+    per field in both precisions and directions, FP64 solves against the
+    oracle; the one-row system solves exactly in one step."""
+    torch, dev = torch_dev
+    s = _degenerate_system()
+    g = _solver(torch, dev, s, coarse_max=8)
+    o = oracle.Oracle(s.rowptr, s.col, s.val, s.nf, s.field_of_row, s.tree, coarse_max=8)
+    st = g.stats()
+    for f in range(s.nf):
+        oa = o.amg(f)
+        assert oa.levels == st["levels"][f]
+        for l in range(oa.levels):
+            for w in ("A", "AT") if l + 1 == oa.levels else ("A", "AT", "P", "R"):
+                gr, gc, gv, _ = g.get_level(f, l, w)
+                orp, oc, ov, _ = oa.get(l, w)
+                assert np.array_equal(gr, orp) and np.array_equal(gc, oc), (f, l, w)
+                assert np.array_equal(gv.view(np.int64), ov.view(np.int64)), (f, l, w)
+    assert st["levels"][1] == 1 and st["levels"][0] >= 2
+    r = np.random.default_rng(17).standard_normal(s.n)
+    for precision, tol in ((0, 1e-13), (1, 1e-5)):
+        g.set_precision(precision)
+        o.set_precision(precision)
+        for tr in (False, True):
+            z = g.apply(torch.from_numpy(r).to(dev), transpose=tr).cpu().numpy()
+            assert_fields_close(z, o.apply(r, transpose=tr), s.field_of_row, tol, (precision, tr))
+    g.set_precision(0)
+    o.set_precision(0)
+    A = sp.csr_matrix((s.val, s.col, s.rowptr), shape=(s.n, s.n))
+    for tr in (False, True):
+        x, stt, it, _ = g.solve(torch.from_numpy(s.b).to(dev), transpose=tr)
+        x = x.cpu().numpy()
+        ro = o.solve(s.b, transpose=tr)
+        assert stt == 0 and ro["status"] == 0
+        M = A.T if tr else A
+        assert np.linalg.norm(s.b - M @ x) <= 1e-8 * np.linalg.norm(s.b)
+        assert abs(it - ro["iters"]) <= 2
+        if it == ro["iters"]:
+            assert np.linalg.norm(x - ro["x"]) <= 1e-9 * np.linalg.norm(ro["x"])
+    # one row
+    one = synth.System(n=1, nf=1, rowptr=np.array([0, 1], np.int32), col=np.array([0], np.int32),
+                       val=np.array([4.0]), field_of_row=np.zeros(1, np.int32), tree=[-1, 0, -2])
+    g1 = _solver(torch, dev, one)
+    for precision in (0, 1):
+        g1.set_precision(precision)
+        z = g1.apply(torch.tensor([3.0], dtype=torch.float64, device=dev)).cpu().numpy()
+        assert z[0] == 0.75
+        x, stt, it, _ = g1.solve(torch.tensor([3.0], dtype=torch.float64, device=dev))
+        assert stt == 0 and it == 1 and x.cpu().numpy()[0] == 0.75
+
+
 def test_set_values_rebuilds(torch_dev):
     torch, dev = torch_dev
     s = synth.make_system(6, 5, 8, 1, seed=4)
