@@ -1411,8 +1411,11 @@ static void run_iteration(hbgs_ctx* c, Krylov& K, const DCsr& A, Prec& prec, int
 // The Givens kernel stores ||w||, h_{j+1,j} and then, after a system-scope
 // fence, the residual estimate into coherent pinned memory.  The host waits
 // for the estimate slot to leave its sentinel instead of synchronising the
-// stream, so it decides and enqueues the next step while the basis update
-// of this one still runs.  Should the store not arrive, the stream's
+// stream, so it decides on the next step as soon as the store lands, while
+// the Givens kernel's last wave and the stream's completion are still
+// pending (enqueuing several steps ahead instead runs slower: the runtime
+// handles a queue many steps deep worse than one a step deep).  Should the
+// store not arrive, the stream's
 // completion ends the wait (and an idle stream with the sentinel still in
 // place is an error).
 constexpr double kEstPending = -1.0;  // estimates are norms (>= 0, or NaN)
