@@ -1,7 +1,9 @@
 """hbgs_apply_noalloc (the entry point that allocates nothing) against
 hbgs_apply, through the C ABI: two calls in a row on one device, the second
-on a smaller system, in both precisions and both directions; then the
-rejections (too many rows, the nested form, adjoint operators not built)."""
+on a smaller system, in both precisions and both directions (on small
+systems, and on a 1M-DOF one whose passes stage their operand in LDS); then
+the rejections (too many rows, the nested form, adjoint operators not
+built)."""
 import ctypes
 
 import numpy as np
@@ -41,6 +43,26 @@ def test_noalloc_apply_matches_apply(torch_dev, precision):
         for tag, g, s in (("4096 rows", gb, big), ("1890 rows", gs, small)):
             print(f"noalloc apply: precision {precision} transpose {tr} {tag}", flush=True)
             r = torch.from_numpy(np.random.default_rng(21 + s.n).standard_normal(s.n)).to(dev)
+            z = torch.full_like(r, float("nan"))
+            g.apply_noalloc(r, z, transpose=tr)
+            torch.cuda.synchronize()
+            ref = g.apply(r, transpose=tr)
+            assert torch.equal(z, ref), (tag, tr)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_noalloc_apply_matches_apply_staged(torch_dev, precision):
+    """A 1M-DOF system (its finest passes stage their operand in LDS, 256-row
+    blocks; its fields run on concurrent streams), then a smaller one."""
+    torch, dev = torch_dev
+    big = synth.make_system(cfg=1)                       # 1,048,576 rows
+    small = synth.make_system(cfg=0)                     # 4,096 rows
+    gb = _solver(torch, dev, big, precision=precision)
+    gs = _solver(torch, dev, small, coarse_max=64, precision=precision)
+    for tr in (False, True):
+        for tag, g, s in (("1M rows", gb, big), ("4096 rows", gs, small)):
+            print(f"noalloc apply: precision {precision} transpose {tr} {tag}", flush=True)
+            r = torch.from_numpy(np.random.default_rng(31 + s.n).standard_normal(s.n)).to(dev)
             z = torch.full_like(r, float("nan"))
             g.apply_noalloc(r, z, transpose=tr)
             torch.cuda.synchronize()
