@@ -1,6 +1,7 @@
 """bench.py's HBM-traffic lookup: a PMC record counts only for its own kernel
 class, on its own workload (same algorithmic bytes per launch), and only
-while the solve kernels' source matches the hash it was taken from."""
+while the solve kernels' source matches the hash it was taken from; and its
+refusal of more than one GPU."""
 import hashlib
 import importlib.util
 import json
@@ -40,3 +41,14 @@ def test_stale_record_is_ignored(tmp_path):
     _record(tmp_path, solve_kernels_sha256="0" * 64)
     traffic, why = b.measured_traffic("spmv_outer", 1000)
     assert traffic is None and "stale" in why
+
+
+def test_more_than_one_gpu_is_refused():
+    """bench.py --gpus N (N > 1), or a launch with WORLD_SIZE > 1, exits with
+    status 2 and a message before touching any device."""
+    import subprocess
+    import sys
+    for args, env in ((["--gpus", "2"], {}), (["--gpus", "1"], {"WORLD_SIZE": "4"})):
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                           env={**os.environ, **env}, timeout=60)
+        assert r.returncode == 2 and "one GPU" in r.stderr and r.stdout == "", (args, env, r.stderr)
