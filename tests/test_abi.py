@@ -59,3 +59,15 @@ def test_struct_layouts_match_header(tmp_path):
 
 def test_last_error_is_a_string():
     assert isinstance(H.load().hbgs_last_error(), bytes)
+
+
+def test_debug_knobs_reject_other_values():
+    """The process-wide test knobs set host state only (no device call):
+    values outside their documented range return HBGS_EINVAL with a message
+    and change nothing; the defaults are accepted and restored."""
+    lib = H.load()
+    for fn, bad, default in ((lib.hbgs_debug_spmv_tiles, (2, -1), 1), (lib.hbgs_debug_spgemm_route, (4, -1), 0)):
+        for v in bad:
+            assert fn(v) == -1
+            assert lib.hbgs_last_error()
+        assert fn(default) == 0
